@@ -1,0 +1,331 @@
+"""Seeded synthetic inputs: temporal graphs and motif query streams.
+
+This module only draws inputs. It holds none of the mining arithmetic, so the
+GPU path and the CPU oracle can both be fed from it without sharing any code
+that decides a result.
+
+Every generator uses ``numpy.random.Generator(PCG64(seed))``. Edge ids are the
+positions after a stable sort by ``(t, src, dst)``: the temporal edge list is
+chronologically ordered, as the problem definition assumes (Sec. 2.1), except
+that equal timestamps are allowed here.
+
+Workloads (the paper's datasets are not available, so these stand in for
+them; the sizes follow the evaluation's graph table, Sec. 6, Table 1):
+
+* ``tiny``     n=1,000, m=20,000, Chung-Lu power law (exponent 2.1), times
+               uniform in [0, 1e6), float32 log-normal weights.
+* ``wiki``     n=1.1M, m=7.8M, Chung-Lu exponent 2.0 with the expected top
+               degree near 1e5, bursty per-source Poisson times over 2e8 s
+               (shaped like wiki-talk: 1.14M nodes, 7.83M edges, 6.24 years).
+* ``skew``     n=10M, m=50M, Zipf degrees (hubs of degree 1e6+), per-source
+               1..20 s spacing within a 1e8 s span.
+
+Motif queries (``random_motif``) are motif-order connected: every edge after
+the first touches an already used motif node and adds at most one new one.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+GEN_VERSION = 1
+
+# Predicate operators, shared numbering with the C ABI (documented in the
+# public header): weight OP theta.
+PRED_GE, PRED_GT, PRED_LE, PRED_LT = 0, 1, 2, 3
+NO_GAP = np.iinfo(np.int64).max
+
+
+@dataclasses.dataclass
+class TemporalGraph:
+    """A time-sorted temporal edge list (structure of arrays)."""
+
+    n: int
+    src: np.ndarray  # int32[m]
+    dst: np.ndarray  # int32[m]
+    t: np.ndarray    # int64[m], non-decreasing
+    w: Optional[np.ndarray] = None  # float32[m]
+    name: str = ""
+
+    @property
+    def m(self) -> int:
+        return int(self.src.shape[0])
+
+
+@dataclasses.dataclass
+class Motif:
+    """A motif query: ordered edges over nodes 0..k-1 plus its limits.
+
+    ``gap`` has l-1 entries (``NO_GAP`` = unconstrained); the predicate, when
+    ``pred_edge >= 0``, requires ``w[e_pred_edge] OP theta`` in float32.
+    """
+
+    edges: List[Tuple[int, int]]
+    delta: int
+    gap: Optional[List[int]] = None
+    pred_edge: int = -1
+    pred_op: int = PRED_GE
+    pred_theta: float = 0.0
+
+    @property
+    def l(self) -> int:
+        return len(self.edges)
+
+    @property
+    def k(self) -> int:
+        return 1 + max(max(a, b) for a, b in self.edges)
+
+    def gaps(self) -> List[int]:
+        if self.gap is None:
+            return [int(NO_GAP)] * max(self.l - 1, 0)
+        return [int(g) for g in self.gap]
+
+
+@dataclasses.dataclass
+class Query:
+    motif: Motif
+    t_lo: int
+    t_hi: int
+    enumerate: bool = False
+    arrival: float = 0.0  # unit-rate arrival time; scale by 1/qps
+
+
+def _finish(n, src, dst, t, w, name) -> TemporalGraph:
+    order = np.lexsort((dst, src, t))
+    g = TemporalGraph(
+        n=int(n),
+        src=np.ascontiguousarray(src[order], dtype=np.int32),
+        dst=np.ascontiguousarray(dst[order], dtype=np.int32),
+        t=np.ascontiguousarray(t[order], dtype=np.int64),
+        w=None if w is None else np.ascontiguousarray(w[order], dtype=np.float32),
+        name=name,
+    )
+    return g
+
+
+def _draw_nodes(rng, cdf, count):
+    u = rng.random(count)
+    return np.minimum(np.searchsorted(cdf, u, side="right"), cdf.shape[0] - 1).astype(np.int64)
+
+
+def _chung_lu_pairs(rng, weights, m):
+    """Sources and destinations drawn independently in proportion to
+    ``weights``; self-loops are redrawn (destination side)."""
+    cdf = np.cumsum(weights / weights.sum())
+    src = _draw_nodes(rng, cdf, m)
+    dst = _draw_nodes(rng, cdf, m)
+    bad = np.nonzero(src == dst)[0]
+    while bad.size:
+        dst[bad] = _draw_nodes(rng, cdf, bad.size)
+        bad = bad[src[bad] == dst[bad]]
+    return src, dst
+
+
+def tiny_graph(seed: int = 0, n: int = 1000, m: int = 20000) -> TemporalGraph:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    wts = (np.arange(n, dtype=np.float64) + 1.0) ** (-1.0 / (2.1 - 1.0))
+    src, dst = _chung_lu_pairs(rng, wts, m)
+    t = np.sort(rng.integers(0, 1_000_000, m, dtype=np.int64))
+    w = rng.lognormal(0.0, 1.0, m).astype(np.float32)
+    return _finish(n, src, dst, t, w, f"tiny(n={n},m={m},seed={seed})")
+
+
+def _wiki_offset(n, m, top):
+    """i0 such that m * w_0 / sum(w) == top for w_i = 1/(i+i0)."""
+    idx = np.arange(n, dtype=np.float64)
+
+    def top_deg(i0):
+        return m * (1.0 / i0) / np.sum(1.0 / (idx + i0))
+
+    lo, hi = 1e-3, 1e7
+    for _ in range(200):
+        mid = math.sqrt(lo * hi)
+        if top_deg(mid) > top:
+            lo = mid
+        else:
+            hi = mid
+    return math.sqrt(lo * hi)
+
+
+def _segment_starts(keys_sorted):
+    """Start offsets and lengths of equal-key runs in a sorted key array."""
+    if keys_sorted.size == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    brk = np.nonzero(np.diff(keys_sorted))[0] + 1
+    starts = np.concatenate(([0], brk)).astype(np.int64)
+    lens = np.diff(np.concatenate((starts, [keys_sorted.size]))).astype(np.int64)
+    return starts, lens
+
+
+def _segmented_cumsum(vals, starts, lens):
+    cs = np.cumsum(vals)
+    base = np.concatenate(([0.0], cs))[starts]
+    return cs - np.repeat(base, lens)
+
+
+def wiki_graph(seed: int = 1, n: int = 1_100_000, m: int = 7_800_000,
+               top_degree: float = 1e5, span: float = 2e8) -> TemporalGraph:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    i0 = _wiki_offset(n, m, top_degree)
+    wts = 1.0 / (np.arange(n, dtype=np.float64) + i0)
+    src, dst = _chung_lu_pairs(rng, wts, m)
+    # bursty per-source Poisson process, log-normal rate, start uniform in span
+    order = np.argsort(src, kind="stable")
+    s_sorted = src[order]
+    starts, lens = _segment_starts(s_sorted)
+    nodes = s_sorted[starts]
+    z = rng.standard_normal(n)
+    start_t = rng.random(n) * span
+    rate = (lens.astype(np.float64) / span) * np.exp(2.0 * z[nodes])
+    gaps = rng.standard_exponential(m) / np.repeat(rate, lens)
+    times = np.repeat(start_t[nodes], lens) + _segmented_cumsum(gaps, starts, lens)
+    t_sorted = np.floor(np.mod(times, span)).astype(np.int64)
+    t = np.empty(m, np.int64)
+    t[order] = t_sorted
+    w = rng.lognormal(0.0, 1.0, m).astype(np.float32)
+    return _finish(n, src, dst, t, w, f"wiki(n={n},m={m},seed={seed})")
+
+
+def skew_graph(seed: int = 2, n: int = 10_000_000, m: int = 50_000_000,
+               span: int = 100_000_000) -> TemporalGraph:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    wts = 1.0 / (np.arange(n, dtype=np.float64) + 1.0)
+    src, dst = _chung_lu_pairs(rng, wts, m)
+    order = np.argsort(src, kind="stable")
+    s_sorted = src[order]
+    starts, lens = _segment_starts(s_sorted)
+    nodes = s_sorted[starts]
+    lim = np.maximum(0, span - 20 * lens)
+    start_t = rng.integers(0, lim + 1)
+    gaps = rng.integers(1, 21, m).astype(np.int64)
+    cs = np.cumsum(gaps)
+    base = np.concatenate(([0], cs))[starts]
+    t_sorted = np.repeat(start_t, lens) + cs - np.repeat(base, lens)
+    t = np.empty(m, np.int64)
+    t[order] = t_sorted
+    del nodes
+    return _finish(n, src, dst, t, None, f"skew(n={n},m={m},seed={seed})")
+
+
+def random_graph(rng: np.random.Generator, n: int, m: int, t_max: int,
+                 self_loops: bool = True, weights: bool = True) -> TemporalGraph:
+    """Small uniform random graph for exhaustive tests (ties and, optionally,
+    self-loops allowed)."""
+    src = rng.integers(0, n, m)
+    dst = rng.integers(0, n, m)
+    if not self_loops:
+        bad = src == dst
+        dst[bad] = (dst[bad] + 1 + rng.integers(0, n - 1, int(bad.sum()))) % n
+    t = rng.integers(0, t_max + 1, m).astype(np.int64)
+    w = rng.lognormal(0.0, 1.0, m).astype(np.float32) if weights else None
+    return _finish(n, src, dst, t, w, f"random(n={n},m={m})")
+
+
+# ---------------------------------------------------------------- motifs
+
+def random_motif(rng: np.random.Generator, l: int, k: int) -> List[Tuple[int, int]]:
+    """A motif-order connected motif with exactly ``l`` edges and ``k`` nodes.
+
+    Edge 0 is (0, 1); each later edge touches a used node and adds at most one
+    new node, numbered in order of first appearance; no edge has a == b.
+    """
+    if not (2 <= k <= l + 1):
+        raise ValueError("need 2 <= k <= l+1")
+    news = set(rng.choice(np.arange(1, l), size=k - 2, replace=False).tolist()) if k > 2 else set()
+    edges = [(0, 1)]
+    used = 2
+    for i in range(1, l):
+        if i in news:
+            x = int(rng.integers(0, used))
+            y = used
+            used += 1
+            edges.append((x, y) if rng.random() < 0.5 else (y, x))
+        else:
+            x, y = rng.choice(used, size=2, replace=False).tolist()
+            edges.append((int(x), int(y)))
+    return edges
+
+
+def _log_uniform_int(rng, lo, hi):
+    return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+
+
+def batch_queries(seed: int = 3, q: int = 64) -> List[Motif]:
+    """64 mixed motifs over the tiny graph: l in 3..6, k in 3..min(5, l+1),
+    delta log-uniform in [600, 86400]; odd queries carry a weight predicate."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(q):
+        l = int(rng.integers(3, 7))
+        k = int(rng.integers(3, min(5, l + 1) + 1))
+        edges = random_motif(rng, l, k)
+        delta = _log_uniform_int(rng, 600, 86400)
+        mot = Motif(edges=edges, delta=delta)
+        if i % 2 == 1:
+            mot.pred_edge = int(rng.integers(0, l))
+            mot.pred_op = PRED_GE if rng.random() < 0.5 else PRED_LT
+            mot.pred_theta = float(np.float32(math.exp(rng.standard_normal())))
+        out.append(mot)
+    return out
+
+
+def serve_queries(t_min: int, t_max: int, seed: int = 4, q: int = 10_000,
+                  enum_frac: float = 0.1) -> List[Query]:
+    """A query stream: motifs as in ``batch_queries``, a root time range
+    covering 1-100% of the span, 10% enumerate requests, unit-rate Poisson
+    arrival times."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    span = t_max - t_min
+    arrivals = np.cumsum(rng.standard_exponential(q))
+    out = []
+    for i in range(q):
+        l = int(rng.integers(3, 7))
+        k = int(rng.integers(3, min(5, l + 1) + 1))
+        edges = random_motif(rng, l, k)
+        mot = Motif(edges=edges, delta=_log_uniform_int(rng, 600, 86400))
+        if i % 2 == 1:
+            mot.pred_edge = int(rng.integers(0, l))
+            mot.pred_op = PRED_GE if rng.random() < 0.5 else PRED_LT
+            mot.pred_theta = float(np.float32(math.exp(rng.standard_normal())))
+        f = rng.uniform(0.01, 1.0)
+        width = int(f * span)
+        lo = int(t_min + rng.integers(0, max(span - width, 0) + 1))
+        out.append(Query(motif=mot, t_lo=lo, t_hi=lo + width,
+                         enumerate=bool(rng.random() < enum_frac),
+                         arrival=float(arrivals[i])))
+    return out
+
+
+# Named motifs of the at-scale workloads.
+TRIANGLE = [(0, 1), (1, 2), (2, 0)]
+FOUR_CYCLE = [(0, 1), (1, 2), (2, 3), (3, 0)]
+OUT_STAR3 = [(0, 1), (0, 2), (0, 3)]
+SKEW_MOTIF = [(0, 1), (1, 2), (2, 3), (3, 0), (0, 2)]
+
+
+def wiki_queries() -> List[Motif]:
+    """The six count runs on the wiki-shaped graph."""
+    out = []
+    for d in (3600, 86400):
+        for e in (TRIANGLE, FOUR_CYCLE, OUT_STAR3):
+            out.append(Motif(edges=list(e), delta=d))
+    return out
+
+
+def skew_query() -> Motif:
+    return Motif(edges=list(SKEW_MOTIF), delta=3600, gap=[600, 600, 600, 600])
+
+
+def tiny_query() -> Motif:
+    return Motif(edges=list(TRIANGLE), delta=10_000)
+
+
+def content_hash(g: TemporalGraph) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for a in (g.src, g.dst, g.t) + ((g.w,) if g.w is not None else ()):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()[:16]
