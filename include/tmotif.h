@@ -1,0 +1,248 @@
+/*
+ * tmotif.h — C ABI of the MI355X temporal motif miner.
+ *
+ * The library counts and enumerates the instances of a temporal motif in a
+ * time-ordered edge list that stays resident in the GPU's HBM.
+ *
+ * Problem (Sec. 2.1, "Problem definition"): a temporal graph is a list of
+ * directed edges (u, v, t). A motif is an ordered list of l directed edges
+ * (a_i, b_i) on k motif nodes. An instance is an l-tuple of graph edge ids
+ * (e_0, ..., e_{l-1}) such that
+ *   1. t(e_0) < t(e_1) < ... < t(e_{l-1})      (strict; equal times never match),
+ *   2. t(e_{l-1}) - t(e_0) <= delta            (delta-temporal motif, inclusive),
+ *   3. t(e_{i+1}) - t(e_i) <= gap_max[i]       (fine-grained delta_i, Sec. 2.1),
+ *   4. phi(a_i) = src(e_i), phi(b_i) = dst(e_i) for one injective node map phi
+ *      (isomorphism semantics: a bijection between motif and matched nodes),
+ *   5. optionally w(e_j) OP theta for one motif edge j (edge-attribute
+ *      constraint, Sec. 5.4.1; an exact IEEE float32 comparison),
+ *   6. t_lo <= t(e_0) <= t_hi when a root range is given.
+ * Graph self-loops can never match (condition 4). Edge ids are positions in
+ * the time-sorted edge list (ties keep input order).
+ *
+ * Conventions for every entry point:
+ *   - Every function returns a tm_status; nothing throws across the ABI.
+ *   - On failure no output is written except where stated, and no partial
+ *     state is left behind. tm_last_error() returns a message for the last
+ *     failure on the calling thread.
+ *   - "Host" pointers are ordinary CPU memory read or written during the call;
+ *     the caller keeps ownership. "Device" pointers are GPU memory on the
+ *     context's device, owned by the caller.
+ *   - Calls on one context may come from several host threads. Calls that use
+ *     the same hipStream_t are ordered by that stream; blocking calls return
+ *     after their work on the stream has completed.
+ */
+#ifndef TMOTIF_H
+#define TMOTIF_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tm_status;
+enum {
+    TM_OK = 0,
+    TM_E_INVALID = 1,     /* bad argument, malformed motif, negative delta, node id out of range */
+    TM_E_OOM = 2,         /* device allocation failed */
+    TM_E_COMPILE = 3,     /* runtime kernel compilation failed; log in tm_last_error() */
+    TM_E_DEVICE = 4,      /* HIP runtime error */
+    TM_E_CAPACITY = 5,    /* enumeration buffer too small; the total is still written */
+    TM_E_UNSUPPORTED = 6, /* e.g. more than 8 motif edges */
+    TM_E_BUSY = 7,        /* server admission queue full */
+    TM_E_CANCELLED = 8    /* query cancelled */
+};
+
+/* Edge-attribute predicate operators: w(e_j) OP theta. */
+enum { TM_PRED_GE = 0, TM_PRED_GT = 1, TM_PRED_LE = 2, TM_PRED_LT = 3 };
+
+#define TM_MAX_EDGES 8
+#define TM_MAX_NODES 8
+
+typedef struct tm_ctx tm_ctx;
+typedef struct tm_graph tm_graph;
+typedef struct tm_motif tm_motif;
+
+/* Message of the last failed call on this host thread ("" if none). The
+ * string stays valid until the next failing call on the same thread. */
+const char *tm_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t tm_version(void);
+
+/* ------------------------------------------------------------------ context
+ * A context binds one GPU (HIP device ordinal `device`) and owns the compiled
+ * motif kernels and the internal work buffers. */
+tm_status tm_create(int32_t device, tm_ctx **out);
+void tm_destroy(tm_ctx *ctx);
+
+/* Tunables (runtime launch parameters; they never change a result).
+ *   TM_PARAM_BLOCK         threads per workgroup (64..1024, multiple of 64)
+ *   TM_PARAM_ROOT_CHUNK    roots a wavefront takes from the global queue at once (>= 1);
+ *                          also the root segment of the enumeration output
+ *   TM_PARAM_GRID          workgroups per launch (0 = fill the GPU by occupancy)
+ *   TM_PARAM_PROFILE       1 = time every mining kernel with HIP events
+ *   TM_PARAM_SPLIT         1 = hand the pending candidates of busy lanes to idle lanes
+ *   TM_PARAM_SPLIT_MIN     smallest pending window worth splitting (>= 2)
+ */
+enum {
+    TM_PARAM_BLOCK = 1,
+    TM_PARAM_ROOT_CHUNK = 2,
+    TM_PARAM_GRID = 3,
+    TM_PARAM_PROFILE = 5,
+    TM_PARAM_SPLIT = 6,
+    TM_PARAM_SPLIT_MIN = 7
+};
+tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t value);
+tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
+
+/* Duration in milliseconds of the mining kernels of the last count or
+ * enumerate call on this context (summed over their launches), measured with
+ * HIP events on the caller's stream; requires TM_PARAM_PROFILE = 1. */
+tm_status tm_last_kernel_ms(tm_ctx *ctx, double *ms, int32_t *launches);
+
+/* -------------------------------------------------------------------- graph
+ * Ingest a temporal edge list (Sec. 2.2: a chronologically sorted edge list
+ * plus CSR-like incoming and outgoing edge lists per node; Sec. 4.2 step 0:
+ * preprocessing runs on the GPU, once, off the query path).
+ *
+ *   n_nodes        node ids must lie in [0, n_nodes); 1 <= n_nodes < 2^31
+ *   n_edges        0 <= n_edges < 2^31
+ *   src, dst       host int32[n_edges]
+ *   t              host int64[n_edges]; any order (stably sorted if needed)
+ *   w              host float32[n_edges] edge weights, or NULL (then motifs
+ *                  with a predicate are rejected at count time)
+ *   flags          0 (reserved)
+ *
+ * The graph is copied to the device: the edge list in time order, and for each
+ * node its out-edges and in-edges sorted by (time, edge id). Timestamps are
+ * stored relative to the minimum (int32 when the span allows, else int64);
+ * comparisons stay exact. Errors: TM_E_INVALID (ids out of range, sizes),
+ * TM_E_OOM, TM_E_DEVICE. */
+tm_status tm_load_graph(tm_ctx *ctx, int64_t n_nodes, int64_t n_edges, const int32_t *src, const int32_t *dst,
+                        const int64_t *t, const float *w, uint32_t flags, tm_graph **out);
+void tm_free_graph(tm_graph *g);
+
+typedef struct {
+    int64_t n_nodes, n_edges;
+    int64_t t_min, t_max;    /* over all edges; 0, 0 when empty */
+    int32_t key_bytes;       /* 4 or 8: width of the stored relative timestamps */
+    int32_t has_weights;
+    int64_t device_bytes;    /* HBM held by the graph */
+    int32_t was_sorted;      /* 1 if the input was already in non-decreasing time order */
+} tm_graph_info;
+tm_status tm_graph_get_info(const tm_graph *g, tm_graph_info *info);
+
+/* perm_out: host int64[n_edges]; perm_out[id] = input position of edge id. */
+tm_status tm_graph_edge_order(const tm_graph *g, int64_t *perm_out);
+
+/* Copy one direction of the device adjacency back to host memory, for
+ * inspection (dir 0 = out-lists, 1 = in-lists). Any output may be NULL.
+ *   off     host uint32[n_nodes+1]: list of node v = positions [off[v], off[v+1])
+ *           (in-list positions start at n_edges)
+ *   nbr     host int32[n_edges]: the other endpoint, in list order
+ *   eid     host int32[n_edges]: the edge id, in list order
+ *   t_rel   host int64[n_edges]: time minus t_min, in list order
+ * Each list is sorted by (time, edge id). */
+tm_status tm_graph_copy_csr(const tm_graph *g, int32_t dir, uint32_t *off, int32_t *nbr, int32_t *eid,
+                            int64_t *t_rel);
+
+/* -------------------------------------------------------------------- motif
+ * A motif query (Sec. 4.3, user-defined query: pattern plus the coarse delta
+ * and fine-grained delta_i constraints and an attribute constraint).
+ *
+ *   n_nodes     k, 2..8; every node 0..k-1 must appear on some edge
+ *   n_edges     l, 1..8
+ *   edges       host int32[2*l]: a_0, b_0, a_1, b_1, ... in motif time order; a_i != b_i
+ *   delta       >= 0
+ *   gap_max     host int64[l-1] or NULL; entry i bounds t(e_{i+1}) - t(e_i);
+ *               INT64_MAX means none; entries must be >= 0
+ *   pred_edge   -1 for none, else the motif edge j whose weight is tested
+ *   pred_op     TM_PRED_*; pred_theta the float32 threshold
+ *
+ * Compiling specialises a GPU kernel to the motif's structure (Sec. 5.1.2:
+ * per-level candidate list, mapped-node checks and bookkeeping fixed ahead of
+ * time) with the runtime compiler. Kernels are cached per structure: delta,
+ * gaps, threshold and root range are launch arguments and never recompile.
+ * A motif whose edge i shares no node with edges 0..i-1 is accepted; that
+ * level scans the whole edge list (Algorithm 1, GetCandidateEdgeList, case
+ * neither endpoint mapped). Errors: TM_E_INVALID, TM_E_UNSUPPORTED,
+ * TM_E_COMPILE. */
+typedef struct {
+    int32_t n_nodes;
+    int32_t n_edges;
+    const int32_t *edges;
+    int64_t delta;
+    const int64_t *gap_max;
+    int32_t pred_edge;
+    int32_t pred_op;
+    float pred_theta;
+} tm_motif_desc;
+
+tm_status tm_compile_motif(tm_ctx *ctx, const tm_motif_desc *desc, tm_motif **out);
+void tm_free_motif(tm_motif *m);
+
+/* The HIP source the motif compiler emits for `desc` (key_bytes 4 or 8 = the
+ * width of relative timestamps), for inspection; needs no device. Writes at
+ * most `cap` bytes including the terminating NUL into `buf` (host, may be
+ * NULL when cap is 0); *len (host) receives the full length. */
+tm_status tm_motif_source(const tm_motif_desc *desc, int32_t key_bytes, char *buf, int64_t cap, int64_t *len);
+
+/* Run the motif compiler down to a gfx950 code object without loading it
+ * (needs no device): q = 1 compiles the single-query module of descs[0],
+ * q > 1 the batched module of descs[0..q-1] (host array). *code_bytes (host,
+ * may be NULL) receives the code object's size. Errors: TM_E_INVALID,
+ * TM_E_COMPILE (log in tm_last_error()). */
+tm_status tm_motif_compile_check(const tm_motif_desc *descs, int32_t q, int32_t key_bytes, int64_t *code_bytes);
+
+/* Root range: only instances whose first edge has t_lo <= t <= t_hi (both
+ * inclusive); later edges may exceed t_hi. Counts add over disjoint ranges.
+ * A NULL range pointer means every root. */
+typedef struct {
+    int64_t t_lo, t_hi;
+} tm_root_range;
+
+/* ------------------------------------------------------------------ mining
+ * Count instances (Sec. 2.1, "count" flavour). Blocking: the work is queued
+ * on `stream` (0 = the null stream) and the call returns after it finished.
+ * count_out: host uint64. Errors: TM_E_INVALID (a predicate on a graph
+ * without weights, graph and motif from different contexts), TM_E_DEVICE,
+ * TM_E_OOM, TM_E_COMPILE. */
+tm_status tm_count(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
+                   hipStream_t stream, uint64_t *count_out);
+
+/* Enumerate instances (Sec. 2.1, "enumerate" flavour). A first pass counts the
+ * instances of every segment of consecutive roots, an exclusive prefix sum
+ * turns those counts into output offsets, and a second pass writes each
+ * instance (e_0, ..., e_{l-1}) as l int64 edge ids into its segment.
+ *   d_out      device int64[capacity][l] (row-major), caller-owned; may be
+ *              NULL when capacity is 0 (size query)
+ *   capacity   rows available in d_out
+ *   n_out      host uint64: total number of instances (always written on
+ *              TM_OK and TM_E_CAPACITY)
+ * Rows are grouped by root segment in root order; the order inside a segment
+ * is unspecified. With capacity < total, returns TM_E_CAPACITY and leaves
+ * d_out unspecified. */
+tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
+                       hipStream_t stream, int64_t *d_out, uint64_t capacity, uint64_t *n_out);
+
+/* Work counters of one query, for the byte model of the benchmark: roots
+ * read, candidate windows opened, sum over windows of ceil(log2(L+1)) where
+ * L is the searched list's length (the shorter of the two lists when both
+ * endpoints are mapped), candidates read (including the read that ends a
+ * window), candidate reads at the predicate level, and instances.
+ * stats_out: host uint64[6]. Blocking like tm_count. */
+tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
+                        hipStream_t stream, uint64_t *stats_out);
+
+/* Batched count: q queries (motifs[i] with ranges[i], ranges may be NULL) in
+ * one persistent launch; work items (query, root chunk) are drawn from one
+ * device queue. counts_out: host uint64[q]. Blocking. */
+tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
+                         const tm_root_range *ranges, hipStream_t stream, uint64_t *counts_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TMOTIF_H */

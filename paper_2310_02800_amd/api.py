@@ -1,0 +1,271 @@
+"""Python binding of the C ABI (argument marshalling only).
+
+Every step of the mining runs in the native HIP library; PyTorch is used only
+for device buffers (enumeration output) and stream handles.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _native as N
+
+I64_MAX = np.iinfo(np.int64).max
+I64_MIN = np.iinfo(np.int64).min
+
+
+def _ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _range(t_lo, t_hi):
+    if t_lo is None and t_hi is None:
+        return None
+    r = N.RootRange(I64_MIN if t_lo is None else int(t_lo), I64_MAX if t_hi is None else int(t_hi))
+    return r
+
+
+def _np(a, dtype):
+    if a is None:
+        return None
+    if hasattr(a, "detach"):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Graph:
+    def __init__(self, ctx: "Context", handle):
+        self._ctx = ctx
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        inf = N.GraphInfo()
+        N.check(N.lib().tm_graph_get_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in N.GraphInfo._fields_}
+
+    def edge_order(self) -> np.ndarray:
+        m = self.info()["n_edges"]
+        out = np.zeros(m, np.int64)
+        N.check(N.lib().tm_graph_edge_order(self._h, _ptr(out)))
+        return out
+
+    def csr(self, direction: int):
+        """(off, nbr, eid, t_rel) of the out- (0) or in- (1) adjacency."""
+        inf = self.info()
+        n, m = inf["n_nodes"], inf["n_edges"]
+        off = np.zeros(n + 1, np.uint32)
+        nbr = np.zeros(max(m, 1), np.int32)
+        eid = np.zeros(max(m, 1), np.int32)
+        t = np.zeros(max(m, 1), np.int64)
+        N.check(N.lib().tm_graph_copy_csr(self._h, int(direction), _ptr(off), _ptr(nbr), _ptr(eid), _ptr(t)))
+        return off, nbr[:m], eid[:m], t[:m]
+
+    def close(self):
+        if self._h:
+            N.lib().tm_free_graph(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Motif:
+    def __init__(self, ctx: "Context", handle, l: int):
+        self._ctx = ctx
+        self._h = handle
+        self.l = l
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            N.lib().tm_free_motif(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_desc(edges, delta, gap=None, pred_edge=-1, pred_op=0, pred_theta=0.0, n_nodes=None):
+    e = np.ascontiguousarray(np.array(edges, dtype=np.int32).reshape(-1))
+    l = e.size // 2
+    k = int(n_nodes) if n_nodes is not None else (int(e.max()) + 1 if e.size else 0)
+    g = None if gap is None else np.ascontiguousarray(np.array(gap, dtype=np.int64))
+    d = N.MotifDesc(k, l, ctypes.c_void_p(e.ctypes.data), int(delta),
+                    None if g is None else ctypes.c_void_p(g.ctypes.data), int(pred_edge), int(pred_op),
+                    float(pred_theta))
+    return d, (e, g)  # keep arrays alive with the descriptor
+
+
+def motif_desc_of(m):
+    """Descriptor of a synth.Motif-like object."""
+    return make_desc(m.edges, m.delta, None if m.gap is None else m.gaps(), m.pred_edge, m.pred_op, m.pred_theta)
+
+
+def motif_source(edges, delta=0, key_bytes=4, **kw) -> str:
+    d, keep = make_desc(edges, delta, **kw)
+    n = ctypes.c_int64(0)
+    N.check(N.lib().tm_motif_source(ctypes.byref(d), key_bytes, None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    N.check(N.lib().tm_motif_source(ctypes.byref(d), key_bytes, buf, n.value + 1, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def motif_compile_check(edges, delta=0, key_bytes=4, **kw) -> int:
+    d, keep = make_desc(edges, delta, **kw)
+    n = ctypes.c_int64(0)
+    N.check(N.lib().tm_motif_compile_check(ctypes.byref(d), 1, key_bytes, ctypes.byref(n)))
+    return n.value
+
+
+def batch_compile_check(motifs, key_bytes=4) -> int:
+    """Compile the batched module of synth.Motif-like objects (no device)."""
+    descs = (N.MotifDesc * len(motifs))()
+    keep = []
+    for i, m in enumerate(motifs):
+        d, k = motif_desc_of(m)
+        descs[i] = d
+        keep.append(k)
+    n = ctypes.c_int64(0)
+    N.check(N.lib().tm_motif_compile_check(descs, len(motifs), key_bytes, ctypes.byref(n)))
+    return n.value
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        N.check(N.lib().tm_create(int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if self._h:
+            N.lib().tm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- params
+    def set_param(self, param: int, value: int):
+        N.check(N.lib().tm_set_param(self._h, int(param), int(value)))
+
+    def get_param(self, param: int) -> int:
+        v = ctypes.c_int64()
+        N.check(N.lib().tm_get_param(self._h, int(param), ctypes.byref(v)))
+        return v.value
+
+    def last_kernel_ms(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int32()
+        N.check(N.lib().tm_last_kernel_ms(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    # ---- graph / motif
+    def load_graph(self, n_nodes, src, dst, t, w=None) -> Graph:
+        s = _np(src, np.int32)
+        d = _np(dst, np.int32)
+        tt = _np(t, np.int64)
+        ww = _np(w, np.float32)
+        h = ctypes.c_void_p()
+        N.check(N.lib().tm_load_graph(self._h, int(n_nodes), int(s.size), _ptr(s), _ptr(d), _ptr(tt), _ptr(ww), 0,
+                                      ctypes.byref(h)))
+        return Graph(self, h)
+
+    def load_synth(self, g) -> Graph:
+        return self.load_graph(g.n, g.src, g.dst, g.t, g.w)
+
+    def compile_motif(self, edges, delta, gap=None, pred_edge=-1, pred_op=0, pred_theta=0.0,
+                      n_nodes=None) -> Motif:
+        d, keep = make_desc(edges, delta, gap, pred_edge, pred_op, pred_theta, n_nodes)
+        h = ctypes.c_void_p()
+        N.check(N.lib().tm_compile_motif(self._h, ctypes.byref(d), ctypes.byref(h)))
+        return Motif(self, h, d.n_edges)
+
+    def compile(self, m) -> Motif:
+        """Compile a synth.Motif-like object."""
+        return self.compile_motif(m.edges, m.delta, None if m.gap is None else m.gaps(), m.pred_edge, m.pred_op,
+                                  m.pred_theta)
+
+    # ---- mining
+    def count(self, g: Graph, m: Motif, t_lo=None, t_hi=None, stream=None) -> int:
+        rr = _range(t_lo, t_hi)
+        out = ctypes.c_uint64()
+        N.check(N.lib().tm_count(self._h, g.handle, m.handle, None if rr is None else ctypes.byref(rr),
+                                 _stream_handle(stream), ctypes.byref(out)))
+        return out.value
+
+    def work_stats(self, g: Graph, m: Motif, t_lo=None, t_hi=None, stream=None) -> dict:
+        rr = _range(t_lo, t_hi)
+        st = np.zeros(6, np.uint64)
+        N.check(N.lib().tm_work_stats(self._h, g.handle, m.handle, None if rr is None else ctypes.byref(rr),
+                                      _stream_handle(stream), _ptr(st)))
+        keys = ("roots", "windows", "probes", "visits", "pred_visits", "matches")
+        return {k: int(v) for k, v in zip(keys, st)}
+
+    def enumerate_into(self, g: Graph, m: Motif, out_ptr: int, capacity: int, t_lo=None, t_hi=None,
+                       stream=None):
+        """Enumerate into caller-owned device memory; returns (status, n)."""
+        rr = _range(t_lo, t_hi)
+        n = ctypes.c_uint64()
+        st = N.lib().tm_enumerate(self._h, g.handle, m.handle, None if rr is None else ctypes.byref(rr),
+                                  _stream_handle(stream), ctypes.c_void_p(out_ptr) if out_ptr else None,
+                                  int(capacity), ctypes.byref(n))
+        if st not in (N.TM_OK, N.TM_E_CAPACITY):
+            N.check(st)
+        return st, n.value
+
+    def enumerate(self, g: Graph, m: Motif, t_lo=None, t_hi=None, stream=None, capacity=None):
+        """All instances as a device int64 tensor [count, l] (rows grouped by
+        root chunk; the order inside a chunk is unspecified)."""
+        import torch
+        if capacity is None:
+            _, capacity = self.enumerate_into(g, m, 0, 0, t_lo, t_hi, stream)
+        out = torch.empty((max(int(capacity), 1), m.l), dtype=torch.int64, device=f"cuda:{self.device}")
+        st, n = self.enumerate_into(g, m, out.data_ptr(), int(capacity), t_lo, t_hi, stream)
+        if st == N.TM_E_CAPACITY:
+            raise N.NativeError(st, f"capacity {capacity} < {n}")
+        return out[:n]
+
+    def count_batch(self, g: Graph, motifs: Sequence[Motif], ranges=None, stream=None):
+        q = len(motifs)
+        arr = (ctypes.c_void_p * max(q, 1))(*[mm.handle.value if hasattr(mm.handle, "value") else mm.handle
+                                              for mm in motifs])
+        rr = None
+        if ranges is not None:
+            rr = (N.RootRange * q)(*[N.RootRange(I64_MIN if a is None else int(a), I64_MAX if b is None else int(b))
+                                     for a, b in ranges])
+        out = np.zeros(max(q, 1), np.uint64)
+        N.check(N.lib().tm_count_batch(self._h, g.handle, q, arr, rr, _stream_handle(stream), _ptr(out)))
+        return [int(x) for x in out[:q]]

@@ -1,0 +1,769 @@
+// C ABI of the temporal motif library: contexts, graph ingest, motif
+// compilation and the count / enumerate / batch entry points.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "tm_internal.h"
+
+using tmo::GArgs;
+using tmo::QArgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+tm_status fail(tm_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+tm_status hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? TM_E_OOM : TM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                     \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
+void free_graph_buffers(tm_graph *g) {
+    void *ptrs[] = {g->d_src, g->d_dst, g->d_tk, g->d_w, g->d_adj_t, g->d_adj_nbr, g->d_adj_eid, g->d_adj_w,
+                    g->d_off_out, g->d_off_in};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+}
+
+template <typename T>
+hipError_t dmalloc(T **p, int64_t count, int64_t *acc) {
+    size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e == hipSuccess && acc) *acc += (int64_t)bytes;
+    return e;
+}
+
+// A per-call set of device buffers. Calls may run concurrently on several
+// streams; each takes its own workspace for the duration of the call.
+struct WsLease {
+    tm_ctx *ctx;
+    tm_ctx::Workspace *w = nullptr;
+    explicit WsLease(tm_ctx *c) : ctx(c) {
+        std::lock_guard<std::mutex> lk(ctx->ws_mu);
+        for (auto &p : ctx->ws)
+            if (!p->busy) { w = p.get(); break; }
+        if (!w) {
+            ctx->ws.emplace_back(new tm_ctx::Workspace());
+            w = ctx->ws.back().get();
+        }
+        w->busy = true;
+    }
+    ~WsLease() {
+        std::lock_guard<std::mutex> lk(ctx->ws_mu);
+        w->busy = false;
+    }
+};
+
+hipError_t ws_prepare(tm_ctx::Workspace *w, int64_t chunks, int nq) {
+    hipError_t e = hipSuccess;
+    if (!w->ctl) {
+        e = hipMalloc(&w->ctl, tmo::CTL_WORDS * sizeof(uint64_t));
+        if (e != hipSuccess) return e;
+        e = hipHostMalloc(&w->h_ctl, 4096, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&w->ev0);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&w->ev1);
+        if (e != hipSuccess) return e;
+    }
+    if (nq > w->q_cap) {
+        if (w->counts) hipFree(w->counts);
+        if (w->qa) hipFree(w->qa);
+        if (w->h_qa) hipHostFree(w->h_qa);
+        if (w->h_counts) hipHostFree(w->h_counts);
+        w->counts = nullptr; w->qa = nullptr; w->h_qa = nullptr; w->h_counts = nullptr; w->q_cap = 0;
+        int cap = std::max(nq, 64);
+        e = hipMalloc(&w->counts, cap * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipMalloc(&w->qa, cap * sizeof(QArgs));
+        if (e == hipSuccess) e = hipHostMalloc(&w->h_qa, cap * sizeof(QArgs), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc(&w->h_counts, cap * sizeof(uint64_t), hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        w->q_cap = cap;
+    }
+    if (chunks > w->chunk_cap) {
+        if (w->chunk_cnt) hipFree(w->chunk_cnt);
+        if (w->chunk_off) hipFree(w->chunk_off);
+        w->chunk_cnt = w->chunk_off = nullptr;
+        w->chunk_cap = 0;
+        int64_t cap = std::max<int64_t>(chunks + 1, 1024);
+        e = hipMalloc(&w->chunk_cnt, cap * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipMalloc(&w->chunk_off, cap * sizeof(uint64_t));
+        if (e != hipSuccess) return e;
+        w->chunk_cap = cap;
+    }
+    return hipSuccess;
+}
+
+void root_ids(const tm_graph *g, const tm_root_range *rr, int64_t *r0, int64_t *r1) {
+    if (!rr) { *r0 = 0; *r1 = g->m; return; }
+    *r0 = std::lower_bound(g->h_t.begin(), g->h_t.end(), rr->t_lo) - g->h_t.begin();
+    *r1 = std::upper_bound(g->h_t.begin(), g->h_t.end(), rr->t_hi) - g->h_t.begin();
+    if (*r1 < *r0) *r1 = *r0;
+}
+
+// Fill one query's launch arguments. Delta is clamped to the time span (a
+// larger window admits nothing more) and each gap to delta (consecutive gaps
+// never exceed the whole window), so the kernel's window ends never overflow.
+void fill_qargs(const tm_graph *g, const tm_motif *m, int64_t r0, int64_t r1, int64_t c0, int64_t rch, int fn,
+                QArgs *q) {
+    std::memset(q, 0, sizeof(*q));
+    const int64_t span = g->m ? g->t_max - g->t_min : 0;
+    q->r0 = r0;
+    q->r1 = r1;
+    q->delta = std::min<int64_t>(m->delta, span);
+    for (int i = 0; i < 8; i++) q->gap[i] = std::min<int64_t>(m->gaps[i], q->delta);
+    q->c0 = c0;
+    q->nchunks = (r1 - r0 + rch - 1) / rch;
+    q->theta = m->theta;
+    q->pred_op = m->pred_op;
+    q->fn = fn;
+}
+
+GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w) {
+    GArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.src = g->d_src;
+    a.dst = g->d_dst;
+    a.tk = g->d_tk;
+    a.w = g->d_w;
+    a.adj_t = g->d_adj_t;
+    a.adj_nbr = g->d_adj_nbr;
+    a.adj_eid = g->d_adj_eid;
+    a.adj_w = g->d_adj_w;
+    a.off_out = g->d_off_out;
+    a.off_in = g->d_off_in;
+    a.qa = (const QArgs *)w->qa;
+    a.ctl = w->ctl;
+    a.counts = w->counts;
+    a.chunk_cnt = w->chunk_cnt;
+    a.chunk_off = w->chunk_off;
+    a.m_edges = g->m;
+    return a;
+}
+
+int grid_for(tm_ctx *ctx, const tmo::Module *mod) {
+    if (ctx->grid > 0) return (int)ctx->grid;
+    int per_cu = mod->max_blocks_per_cu > 0 ? mod->max_blocks_per_cu : 1;
+    return std::max(1, per_cu * std::max(ctx->num_cus, 1));
+}
+
+tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int mode, GArgs *a,
+                 hipStream_t stream, bool timed) {
+    hipFunction_t fn = mod->fn[mode];
+    if (!fn) return fail(TM_E_DEVICE, "kernel variant missing from module");
+    HIP_TRY(tmo::dev_fill_u64(w->ctl, 0, tmo::CTL_WORDS, stream), "reset counters");
+    void *params[] = {a};
+    if (timed) HIP_TRY(hipEventRecord(w->ev0, stream), "hipEventRecord");
+    HIP_TRY(hipModuleLaunchKernel(fn, grid_for(ctx, mod), 1, 1, ctx->block, 1, 1, 0, stream, params, nullptr),
+            "hipModuleLaunchKernel");
+    if (timed) HIP_TRY(hipEventRecord(w->ev1, stream), "hipEventRecord");
+    return TM_OK;
+}
+
+tm_status check_pair(tm_ctx *ctx, const tm_graph *g, const tm_motif *m) {
+    if (!ctx || !g || !m) return fail(TM_E_INVALID, "null context, graph or motif");
+    if (g->ctx != ctx || m->ctx != ctx) return fail(TM_E_INVALID, "graph or motif belongs to another context");
+    if (m->plan.pred_level >= 0 && !g->has_w) return fail(TM_E_INVALID, "motif has a weight predicate but the graph has no weights");
+    return TM_OK;
+}
+
+tm_status get_module(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, std::shared_ptr<tmo::Module> *out) {
+    std::string err;
+    auto mod = ctx->compiler.get(m->plan, g->key_bytes, ctx->block, &err);
+    if (!mod) return fail(TM_E_COMPILE, err);
+    *out = mod;
+    return TM_OK;
+}
+
+void record_time(tm_ctx *ctx, tm_ctx::Workspace *w, int launches, bool timed) {
+    if (!timed) return;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, w->ev0, w->ev1) != hipSuccess) ms = 0.f;
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
+    ctx->last_ms = ms;
+    ctx->last_launches = launches;
+}
+
+// One single-query pass in the given mode; leaves results in the workspace.
+tm_status run_single(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
+                     hipStream_t stream, int mode, tm_ctx::Workspace *w, tmo::Module *mod, int64_t *chunks_out,
+                     int64_t *r0_out, double *ms_acc) {
+    int64_t r0, r1;
+    root_ids(g, range, &r0, &r1);
+    const int64_t rch = ctx->root_chunk;
+    const int64_t chunks = (r1 - r0 + rch - 1) / rch;
+    HIP_TRY(ws_prepare(w, chunks, 1), "workspace");
+    fill_qargs(g, m, r0, r1, 0, rch, 0, (QArgs *)w->h_qa);
+    HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload query");
+    HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 1, stream), "reset count");
+    *chunks_out = chunks;
+    *r0_out = r0;
+    if (chunks == 0) return TM_OK;
+    GArgs a = base_args(g, w);
+    a.total_chunks = chunks;
+    a.rch = (int32_t)rch;
+    a.nq = 1;
+    const bool timed = ctx->profile != 0;
+    tm_status s = launch(ctx, w, mod, mode, &a, stream, timed);
+    if (s != TM_OK) return s;
+    if (timed) {
+        HIP_TRY(hipEventSynchronize(w->ev1), "hipEventSynchronize");
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, w->ev0, w->ev1) == hipSuccess && ms_acc) *ms_acc += ms;
+    }
+    return TM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tm_last_error(void) { return g_err.c_str(); }
+
+int32_t tm_version(void) { return 100; }
+
+tm_status tm_create(int32_t device, tm_ctx **out) {
+    if (!out) return fail(TM_E_INVALID, "out is null");
+    *out = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(TM_E_INVALID, "device ordinal out of range");
+    DeviceGuard dg(device);
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    tm_ctx *ctx = new (std::nothrow) tm_ctx();
+    if (!ctx) return fail(TM_E_OOM, "host allocation");
+    ctx->device = device;
+    ctx->num_cus = prop.multiProcessorCount;
+    ctx->compiler.device = device;
+    *out = ctx;
+    return TM_OK;
+}
+
+void tm_destroy(tm_ctx *ctx) {
+    if (!ctx) return;
+    DeviceGuard dg(ctx->device);
+    hipDeviceSynchronize();
+    for (auto &w : ctx->ws) {
+        if (w->ctl) hipFree(w->ctl);
+        if (w->h_ctl) hipHostFree(w->h_ctl);
+        if (w->chunk_cnt) hipFree(w->chunk_cnt);
+        if (w->chunk_off) hipFree(w->chunk_off);
+        if (w->scan_tmp) hipFree(w->scan_tmp);
+        if (w->counts) hipFree(w->counts);
+        if (w->qa) hipFree(w->qa);
+        if (w->h_qa) hipHostFree(w->h_qa);
+        if (w->h_counts) hipHostFree(w->h_counts);
+        if (w->ev0) hipEventDestroy(w->ev0);
+        if (w->ev1) hipEventDestroy(w->ev1);
+    }
+    for (auto &kv : ctx->compiler.cache)
+        if (kv.second->mod) hipModuleUnload(kv.second->mod);
+    delete ctx;
+}
+
+tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t v) {
+    if (!ctx) return fail(TM_E_INVALID, "null context");
+    switch (param) {
+    case TM_PARAM_BLOCK:
+        if (v < 64 || v > 1024 || v % 64) return fail(TM_E_INVALID, "block must be a multiple of 64 in [64,1024]");
+        ctx->block = (int)v;
+        return TM_OK;
+    case TM_PARAM_ROOT_CHUNK:
+        if (v < 1 || v > (1 << 24)) return fail(TM_E_INVALID, "root chunk out of range");
+        ctx->root_chunk = v;
+        return TM_OK;
+    case TM_PARAM_GRID:
+        if (v < 0 || v > (1 << 20)) return fail(TM_E_INVALID, "grid out of range");
+        ctx->grid = v;
+        return TM_OK;
+    case TM_PARAM_PROFILE:
+        ctx->profile = v ? 1 : 0;
+        return TM_OK;
+    case TM_PARAM_SPLIT:
+        ctx->split = v ? 1 : 0;
+        return TM_OK;
+    case TM_PARAM_SPLIT_MIN:
+        if (v < 2) return fail(TM_E_INVALID, "split minimum must be >= 2");
+        ctx->split_min = v;
+        return TM_OK;
+    default:
+        return fail(TM_E_INVALID, "unknown parameter");
+    }
+}
+
+tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *v) {
+    if (!ctx || !v) return fail(TM_E_INVALID, "null argument");
+    switch (param) {
+    case TM_PARAM_BLOCK: *v = ctx->block; return TM_OK;
+    case TM_PARAM_ROOT_CHUNK: *v = ctx->root_chunk; return TM_OK;
+    case TM_PARAM_GRID: *v = ctx->grid; return TM_OK;
+    case TM_PARAM_PROFILE: *v = ctx->profile; return TM_OK;
+    case TM_PARAM_SPLIT: *v = ctx->split; return TM_OK;
+    case TM_PARAM_SPLIT_MIN: *v = ctx->split_min; return TM_OK;
+    default: return fail(TM_E_INVALID, "unknown parameter");
+    }
+}
+
+tm_status tm_last_kernel_ms(tm_ctx *ctx, double *ms, int32_t *launches) {
+    if (!ctx || !ms) return fail(TM_E_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
+    *ms = ctx->last_ms;
+    if (launches) *launches = ctx->last_launches;
+    return TM_OK;
+}
+
+// ------------------------------------------------------------------- graph
+
+tm_status tm_load_graph(tm_ctx *ctx, int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const int64_t *t,
+                        const float *w, uint32_t flags, tm_graph **out) {
+    if (!ctx || !out) return fail(TM_E_INVALID, "null context or out");
+    *out = nullptr;
+    if (flags != 0) return fail(TM_E_INVALID, "unknown flags");
+    if (n < 1 || n >= (int64_t(1) << 31) - 1) return fail(TM_E_INVALID, "n_nodes out of range");
+    if (m < 0 || m >= (int64_t(1) << 31) - 1) return fail(TM_E_INVALID, "n_edges out of range");
+    if (m > 0 && (!src || !dst || !t)) return fail(TM_E_INVALID, "null edge arrays");
+    DeviceGuard dg(ctx->device);
+    tm_graph *g = new (std::nothrow) tm_graph();
+    if (!g) return fail(TM_E_OOM, "host allocation");
+    g->ctx = ctx;
+    g->n = n;
+    g->m = m;
+    g->has_w = w != nullptr;
+    hipStream_t s = nullptr;
+    auto cleanup = [&](tm_status st) {
+        if (s) { hipStreamSynchronize(s); hipStreamDestroy(s); }
+        free_graph_buffers(g);
+        delete g;
+        return st;
+    };
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) { s = nullptr; return cleanup(hip_fail(e, "hipStreamCreate")); }
+
+    // sortedness and time range on the host (the input is host memory)
+    bool sorted = true;
+    for (int64_t i = 1; i < m && sorted; i++) sorted = t[i - 1] <= t[i];
+    g->was_sorted = sorted;
+
+    int64_t *d_t = nullptr;
+    int64_t acc = 0;
+    e = dmalloc(&g->d_src, m, &acc);
+    if (e == hipSuccess) e = dmalloc(&g->d_dst, m, &acc);
+    if (e == hipSuccess && g->has_w) e = dmalloc(&g->d_w, m, &acc);
+    if (e == hipSuccess) e = dmalloc(&d_t, m, nullptr);
+    if (e != hipSuccess) { if (d_t) hipFree(d_t); return cleanup(hip_fail(e, "graph allocation")); }
+    e = hipMemcpyAsync(d_t, t, m * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (sorted) {
+        if (e == hipSuccess) e = hipMemcpyAsync(g->d_src, src, m * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(g->d_dst, dst, m * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && g->has_w) e = hipMemcpyAsync(g->d_w, w, m * sizeof(float), hipMemcpyHostToDevice, s);
+    } else {
+        int32_t *s_in = nullptr, *d_in = nullptr;
+        float *w_in = nullptr;
+        int64_t *d_perm = nullptr;
+        if (e == hipSuccess) e = dmalloc(&s_in, m, nullptr);
+        if (e == hipSuccess) e = dmalloc(&d_in, m, nullptr);
+        if (e == hipSuccess && g->has_w) e = dmalloc(&w_in, m, nullptr);
+        if (e == hipSuccess) e = dmalloc(&d_perm, m, nullptr);
+        if (e == hipSuccess) e = hipMemcpyAsync(s_in, src, m * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_in, dst, m * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && g->has_w) e = hipMemcpyAsync(w_in, w, m * sizeof(float), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = tmo::dev_sort_by_time(m, d_t, d_perm, s);
+        if (e == hipSuccess)
+            e = tmo::dev_gather_edges(m, d_perm, s_in, d_in, w_in, g->d_src, g->d_dst, g->d_w, s);
+        if (e == hipSuccess) {
+            g->perm.resize(m);
+            e = hipMemcpyAsync(g->perm.data(), d_perm, m * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        hipFree(s_in); hipFree(d_in); if (w_in) hipFree(w_in); hipFree(d_perm);
+    }
+    g->h_t.resize(m);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->h_t.data(), d_t, m * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { hipFree(d_t); return cleanup(hip_fail(e, "graph upload")); }
+    g->t_min = m ? g->h_t[0] : 0;
+    g->t_max = m ? g->h_t[m - 1] : 0;
+    // relative times fit int32 when the span (plus the clamped window end) does
+    const int64_t span = g->t_max - g->t_min;
+    if (span < 0) { hipFree(d_t); return cleanup(fail(TM_E_INVALID, "time span overflows int64")); }
+    g->key_bytes = span <= (int64_t)0x7ffffffe ? 4 : 8;
+
+    // node ids in range
+    uint32_t *d_bad = nullptr;
+    uint32_t h_bad = 0;
+    e = hipMalloc(&d_bad, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemsetAsync(d_bad, 0, sizeof(uint32_t), s);
+    if (e == hipSuccess) e = tmo::dev_check_ids(m, n, g->d_src, g->d_dst, d_bad, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_bad, d_bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (d_bad) hipFree(d_bad);
+    if (e != hipSuccess) { hipFree(d_t); return cleanup(hip_fail(e, "id check")); }
+    if (h_bad) { hipFree(d_t); return cleanup(fail(TM_E_INVALID, "node id out of range [0, n_nodes)")); }
+
+    e = hipMalloc(&g->d_tk, std::max<int64_t>(m, 1) * g->key_bytes);
+    if (e == hipSuccess) acc += std::max<int64_t>(m, 1) * g->key_bytes;
+    if (e == hipSuccess) e = tmo::dev_make_keys(m, d_t, g->t_min, g->key_bytes, g->d_tk, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(d_t);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "time keys"));
+
+    e = hipMalloc(&g->d_adj_t, std::max<int64_t>(2 * m, 1) * g->key_bytes);
+    if (e == hipSuccess) acc += std::max<int64_t>(2 * m, 1) * g->key_bytes;
+    if (e == hipSuccess) e = dmalloc(&g->d_adj_nbr, 2 * m, &acc);
+    if (e == hipSuccess) e = dmalloc(&g->d_adj_eid, 2 * m, &acc);
+    if (e == hipSuccess && g->has_w) e = dmalloc(&g->d_adj_w, 2 * m, &acc);
+    if (e == hipSuccess) e = dmalloc(&g->d_off_out, n + 1, &acc);
+    if (e == hipSuccess) e = dmalloc(&g->d_off_in, n + 1, &acc);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "adjacency allocation"));
+    e = tmo::dev_build_csr(n, m, g->d_src, g->d_dst, g->d_tk, g->key_bytes, g->d_w, 0u, g->d_off_out, g->d_adj_t,
+                          g->d_adj_nbr, g->d_adj_eid, g->d_adj_w, s);
+    if (e == hipSuccess)
+        e = tmo::dev_build_csr(n, m, g->d_dst, g->d_src, g->d_tk, g->key_bytes, g->d_w, (uint32_t)m, g->d_off_in,
+                              g->d_adj_t, g->d_adj_nbr, g->d_adj_eid, g->d_adj_w, s);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "adjacency build"));
+    g->device_bytes = acc;
+    hipStreamDestroy(s);
+    *out = g;
+    return TM_OK;
+}
+
+void tm_free_graph(tm_graph *g) {
+    if (!g) return;
+    DeviceGuard dg(g->ctx->device);
+    hipDeviceSynchronize();
+    free_graph_buffers(g);
+    delete g;
+}
+
+tm_status tm_graph_get_info(const tm_graph *g, tm_graph_info *info) {
+    if (!g || !info) return fail(TM_E_INVALID, "null argument");
+    info->n_nodes = g->n;
+    info->n_edges = g->m;
+    info->t_min = g->t_min;
+    info->t_max = g->t_max;
+    info->key_bytes = g->key_bytes;
+    info->has_weights = g->has_w ? 1 : 0;
+    info->device_bytes = g->device_bytes;
+    info->was_sorted = g->was_sorted ? 1 : 0;
+    return TM_OK;
+}
+
+tm_status tm_graph_edge_order(const tm_graph *g, int64_t *perm_out) {
+    if (!g || (!perm_out && g->m)) return fail(TM_E_INVALID, "null argument");
+    for (int64_t i = 0; i < g->m; i++) perm_out[i] = g->perm.empty() ? i : g->perm[i];
+    return TM_OK;
+}
+
+tm_status tm_graph_copy_csr(const tm_graph *g, int32_t dir, uint32_t *off, int32_t *nbr, int32_t *eid,
+                            int64_t *t_rel) {
+    if (!g || (dir != 0 && dir != 1)) return fail(TM_E_INVALID, "bad argument");
+    DeviceGuard dg(g->ctx->device);
+    const int64_t m = g->m, base = dir ? m : 0;
+    if (off) HIP_TRY(hipMemcpy(off, dir ? g->d_off_in : g->d_off_out, (g->n + 1) * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost), "copy offsets");
+    if (m == 0) return TM_OK;
+    if (nbr) HIP_TRY(hipMemcpy(nbr, g->d_adj_nbr + base, m * sizeof(int32_t), hipMemcpyDeviceToHost), "copy nbr");
+    if (eid) HIP_TRY(hipMemcpy(eid, g->d_adj_eid + base, m * sizeof(int32_t), hipMemcpyDeviceToHost), "copy eid");
+    if (t_rel) {
+        if (g->key_bytes == 8) {
+            HIP_TRY(hipMemcpy(t_rel, (const int64_t *)g->d_adj_t + base, m * sizeof(int64_t), hipMemcpyDeviceToHost),
+                    "copy t");
+        } else {
+            std::vector<int32_t> tmp(m);
+            HIP_TRY(hipMemcpy(tmp.data(), (const int32_t *)g->d_adj_t + base, m * sizeof(int32_t),
+                              hipMemcpyDeviceToHost), "copy t");
+            for (int64_t i = 0; i < m; i++) t_rel[i] = tmp[i];
+        }
+    }
+    return TM_OK;
+}
+
+// ------------------------------------------------------------------- motif
+
+tm_status tm_compile_motif(tm_ctx *ctx, const tm_motif_desc *desc, tm_motif **out) {
+    if (!ctx || !out) return fail(TM_E_INVALID, "null context or out");
+    *out = nullptr;
+    if (desc && (desc->n_edges > TM_MAX_EDGES || desc->n_nodes > TM_MAX_NODES))
+        return fail(TM_E_UNSUPPORTED, "motif too large (at most 8 edges and 8 nodes)");
+    tm_motif *m = new (std::nothrow) tm_motif();
+    if (!m) return fail(TM_E_OOM, "host allocation");
+    std::string err;
+    if (!tmo::build_plan(desc, &m->plan, m->gaps, &err)) {
+        delete m;
+        return fail(TM_E_INVALID, err);
+    }
+    m->ctx = ctx;
+    m->delta = desc->delta;
+    m->pred_op = desc->pred_op;
+    m->theta = desc->pred_theta;
+    DeviceGuard dg(ctx->device);
+    // compile eagerly for 32-bit time keys (the common case) so errors surface here
+    if (!ctx->compiler.get(m->plan, 4, ctx->block, &err)) {
+        delete m;
+        return fail(TM_E_COMPILE, err);
+    }
+    *out = m;
+    return TM_OK;
+}
+
+void tm_free_motif(tm_motif *m) { delete m; }
+
+// Emitted HIP source of a motif's kernel (for inspection). Writes at most
+// `cap` bytes including the terminator; *len gets the full length.
+tm_status tm_motif_source(const tm_motif_desc *desc, int32_t key_bytes, char *buf, int64_t cap, int64_t *len) {
+    tmo::Plan p;
+    int64_t gaps[TM_MAX_EDGES];
+    std::string err;
+    if (!tmo::build_plan(desc, &p, gaps, &err)) return fail(TM_E_INVALID, err);
+    if (key_bytes != 4 && key_bytes != 8) return fail(TM_E_INVALID, "key_bytes must be 4 or 8");
+    std::string s = tmo::generate_source(p, key_bytes, 256);
+    if (len) *len = (int64_t)s.size();
+    if (buf && cap > 0) {
+        int64_t n = std::min<int64_t>(cap - 1, (int64_t)s.size());
+        std::memcpy(buf, s.data(), n);
+        buf[n] = '\0';
+    }
+    return TM_OK;
+}
+
+tm_status tm_motif_compile_check(const tm_motif_desc *descs, int32_t q, int32_t key_bytes, int64_t *code_bytes) {
+    if (!descs || q < 1) return fail(TM_E_INVALID, "need at least one motif");
+    if (key_bytes != 4 && key_bytes != 8) return fail(TM_E_INVALID, "key_bytes must be 4 or 8");
+    std::vector<tmo::Plan> plans(q);
+    std::vector<const tmo::Plan *> uniq;
+    std::map<std::string, int> seen;
+    for (int i = 0; i < q; i++) {
+        int64_t gaps[TM_MAX_EDGES];
+        std::string err;
+        if (!tmo::build_plan(&descs[i], &plans[i], gaps, &err)) return fail(TM_E_INVALID, err);
+        if (seen.emplace(plans[i].key(), 1).second) uniq.push_back(&plans[i]);
+    }
+    std::string src = q == 1 ? tmo::generate_source(plans[0], key_bytes, 256)
+                             : tmo::generate_batch_source(uniq, key_bytes, 256);
+    std::vector<char> code;
+    std::string err;
+    if (!tmo::compile_to_code(src, &code, &err)) return fail(TM_E_COMPILE, err);
+    if (code_bytes) *code_bytes = (int64_t)code.size();
+    return TM_OK;
+}
+
+// ------------------------------------------------------------------ mining
+
+tm_status tm_count(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range, hipStream_t stream,
+                   uint64_t *count_out) {
+    tm_status st = check_pair(ctx, g, m);
+    if (st != TM_OK) return st;
+    if (!count_out) return fail(TM_E_INVALID, "count_out is null");
+    DeviceGuard dg(ctx->device);
+    std::shared_ptr<tmo::Module> mod;
+    if ((st = get_module(ctx, g, m, &mod)) != TM_OK) return st;
+    WsLease lease(ctx);
+    tm_ctx::Workspace *w = lease.w;
+    int64_t chunks = 0, r0 = 0;
+    double ms = 0;
+    st = run_single(ctx, g, m, range, stream, tmo::MODE_COUNT, w, mod.get(), &chunks, &r0, &ms);
+    if (st != TM_OK) return st;
+    HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "read count");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (ctx->profile) {
+        std::lock_guard<std::mutex> lk(ctx->prof_mu);
+        ctx->last_ms = ms;
+        ctx->last_launches = chunks ? 1 : 0;
+    }
+    *count_out = w->h_counts[0];
+    return TM_OK;
+}
+
+tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
+                        hipStream_t stream, uint64_t *stats_out) {
+    tm_status st = check_pair(ctx, g, m);
+    if (st != TM_OK) return st;
+    if (!stats_out) return fail(TM_E_INVALID, "stats_out is null");
+    DeviceGuard dg(ctx->device);
+    std::shared_ptr<tmo::Module> mod;
+    if ((st = get_module(ctx, g, m, &mod)) != TM_OK) return st;
+    WsLease lease(ctx);
+    tm_ctx::Workspace *w = lease.w;
+    int64_t chunks = 0, r0 = 0;
+    st = run_single(ctx, g, m, range, stream, tmo::MODE_STATS, w, mod.get(), &chunks, &r0, nullptr);
+    if (st != TM_OK) return st;
+    if (chunks == 0) HIP_TRY(tmo::dev_fill_u64(w->ctl, 0, tmo::CTL_WORDS, stream), "reset counters");
+    HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+            "read stats");
+    HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "read count");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    for (int i = 0; i < 5; i++) stats_out[i] = w->h_ctl[tmo::CTL_STATS + i];
+    stats_out[5] = w->h_counts[0];
+    return TM_OK;
+}
+
+tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
+                       hipStream_t stream, int64_t *d_out, uint64_t capacity, uint64_t *n_out) {
+    tm_status st = check_pair(ctx, g, m);
+    if (st != TM_OK) return st;
+    if (!n_out) return fail(TM_E_INVALID, "n_out is null");
+    if (capacity > 0 && !d_out) return fail(TM_E_INVALID, "d_out is null with capacity > 0");
+    DeviceGuard dg(ctx->device);
+    std::shared_ptr<tmo::Module> mod;
+    if ((st = get_module(ctx, g, m, &mod)) != TM_OK) return st;
+    WsLease lease(ctx);
+    tm_ctx::Workspace *w = lease.w;
+    int64_t r0, r1;
+    root_ids(g, range, &r0, &r1);
+    const int64_t rch = ctx->root_chunk;
+    const int64_t chunks = (r1 - r0 + rch - 1) / rch;
+    HIP_TRY(ws_prepare(w, chunks, 1), "workspace");
+    if (chunks == 0) {
+        *n_out = 0;
+        return TM_OK;
+    }
+    // pass 1: per-chunk counts
+    HIP_TRY(tmo::dev_fill_u64(w->chunk_cnt, 0, chunks, stream), "reset chunk counts");
+    int64_t c0 = 0, rr0 = 0;
+    double ms = 0;
+    st = run_single(ctx, g, m, range, stream, tmo::MODE_ENUM_COUNT, w, mod.get(), &c0, &rr0, &ms);
+    if (st != TM_OK) return st;
+    // exclusive scan -> per-chunk output offsets (one extra entry: the total)
+    HIP_TRY(tmo::dev_fill_u64(w->chunk_cnt + chunks, 0, 1, stream), "scan tail");
+    size_t need = 0;
+    HIP_TRY(tmo::dev_exclusive_scan_u64(w->chunk_cnt, w->chunk_off, chunks + 1, nullptr, &need, stream), "scan size");
+    if (need > w->scan_tmp_bytes) {
+        if (w->scan_tmp) hipFree(w->scan_tmp);
+        w->scan_tmp = nullptr;
+        w->scan_tmp_bytes = 0;
+        HIP_TRY(hipMalloc(&w->scan_tmp, need), "scan workspace");
+        w->scan_tmp_bytes = need;
+    }
+    size_t have = w->scan_tmp_bytes;
+    HIP_TRY(tmo::dev_exclusive_scan_u64(w->chunk_cnt, w->chunk_off, chunks + 1, w->scan_tmp, &have, stream), "scan");
+    HIP_TRY(hipMemcpyAsync(w->h_ctl + 8, w->chunk_off + chunks, sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+            "read total");
+    HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "read count");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    const uint64_t total = w->h_ctl[8];
+    if (total != w->h_counts[0]) return fail(TM_E_DEVICE, "enumeration pass 1 disagrees with its own total");
+    *n_out = total;
+    if (total == 0) return TM_OK;
+    if (capacity < total) {
+        return d_out ? fail(TM_E_CAPACITY, "enumeration buffer too small") : TM_OK;
+    }
+    // pass 2: write rows; chunk_cnt is reused as the per-chunk write cursor
+    HIP_TRY(tmo::dev_fill_u64(w->chunk_cnt, 0, chunks, stream), "reset cursors");
+    HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload query");
+    HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 1, stream), "reset count");
+    GArgs a = base_args(g, w);
+    a.total_chunks = chunks;
+    a.rch = (int32_t)rch;
+    a.nq = 1;
+    a.out = d_out;
+    a.capacity = capacity;
+    const bool timed = ctx->profile != 0;
+    st = launch(ctx, w, mod.get(), tmo::MODE_ENUM_WRITE, &a, stream, timed);
+    if (st != TM_OK) return st;
+    HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+            "read overflow");
+    HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "read count");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (timed) {
+        float k = 0.f;
+        if (hipEventElapsedTime(&k, w->ev0, w->ev1) == hipSuccess) ms += k;
+        std::lock_guard<std::mutex> lk(ctx->prof_mu);
+        ctx->last_ms = ms;
+        ctx->last_launches = 2;
+    }
+    if (w->h_ctl[tmo::CTL_OVERFLOW] != 0 || w->h_counts[0] != total)
+        return fail(TM_E_DEVICE, "enumeration pass 2 wrote a different number of rows than pass 1 counted");
+    return TM_OK;
+}
+
+tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
+                         const tm_root_range *ranges, hipStream_t stream, uint64_t *counts_out) {
+    if (!ctx || !g || q < 0 || (q > 0 && (!motifs || !counts_out))) return fail(TM_E_INVALID, "bad argument");
+    if (q == 0) return TM_OK;
+    for (int i = 0; i < q; i++) {
+        tm_status st = check_pair(ctx, g, motifs[i]);
+        if (st != TM_OK) return st;
+    }
+    DeviceGuard dg(ctx->device);
+    // one matcher per distinct structure
+    std::vector<const tmo::Plan *> plans;
+    std::vector<int> fn(q);
+    std::map<std::string, int> seen;
+    for (int i = 0; i < q; i++) {
+        std::string k = motifs[i]->plan.key();
+        auto it = seen.find(k);
+        if (it == seen.end()) {
+            it = seen.emplace(k, (int)plans.size()).first;
+            plans.push_back(&motifs[i]->plan);
+        }
+        fn[i] = it->second;
+    }
+    std::string err;
+    auto mod = ctx->compiler.get_batch(plans, g->key_bytes, ctx->block, &err);
+    if (!mod) return fail(TM_E_COMPILE, err);
+    WsLease lease(ctx);
+    tm_ctx::Workspace *w = lease.w;
+    HIP_TRY(ws_prepare(w, 0, q), "workspace");
+    const int64_t rch = ctx->root_chunk;
+    int64_t c0 = 0;
+    QArgs *h = (QArgs *)w->h_qa;
+    for (int i = 0; i < q; i++) {
+        int64_t r0, r1;
+        root_ids(g, ranges ? &ranges[i] : nullptr, &r0, &r1);
+        fill_qargs(g, motifs[i], r0, r1, c0, rch, fn[i], &h[i]);
+        c0 += h[i].nchunks;
+    }
+    HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, q * sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload queries");
+    HIP_TRY(tmo::dev_fill_u64(w->counts, 0, q, stream), "reset counts");
+    double ms = 0;
+    if (c0 > 0) {
+        GArgs a = base_args(g, w);
+        a.total_chunks = c0;
+        a.rch = (int32_t)rch;
+        a.nq = q;
+        const bool timed = ctx->profile != 0;
+        tm_status st = launch(ctx, w, mod.get(), tmo::MODE_COUNT, &a, stream, timed);
+        if (st != TM_OK) return st;
+        if (timed) {
+            HIP_TRY(hipEventSynchronize(w->ev1), "hipEventSynchronize");
+            float k = 0.f;
+            if (hipEventElapsedTime(&k, w->ev0, w->ev1) == hipSuccess) ms = k;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, q * sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "read counts");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (ctx->profile) {
+        std::lock_guard<std::mutex> lk(ctx->prof_mu);
+        ctx->last_ms = ms;
+        ctx->last_launches = c0 > 0 ? 1 : 0;
+    }
+    for (int i = 0; i < q; i++) counts_out[i] = w->h_counts[i];
+    return TM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,231 @@
+// Device-side graph preprocessing and small utility kernels.
+//
+// Graph ingest (Sec. 2.2: a chronologically sorted temporal edge list plus
+// CSR-like incoming and outgoing edge lists per node; Sec. 4.2, pipeline step
+// 0: the data loader does all preprocessing on the GPU):
+//   1. if the input is not time-ordered, a stable radix sort of (t, input
+//      position) gives the edge order, and src/dst/w are gathered into it;
+//   2. times are rebased to the minimum (int32 when the span allows);
+//   3. per direction, a stable radix sort of (node, edge id) groups edge ids by
+//      node while keeping id order, which is time order, inside each node; a
+//      degree histogram and an exclusive scan give the offsets;
+//   4. a gather writes the adjacency as structure-of-arrays (time, neighbour,
+//      edge id, weight), so the search kernels read contiguous windows.
+// Out-lists occupy positions [0, m) and in-lists [m, 2m) of one unified
+// adjacency, so a candidate window is a plain index range whichever list a
+// motif level uses.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include "tm_internal.h"
+
+namespace tmo {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int blocks_for(int64_t n) {
+    int64_t b = (n + kThreads - 1) / kThreads;
+    if (b > 65535LL * 32) b = 65535LL * 32;
+    return (int)(b < 1 ? 1 : b);
+}
+
+__global__ void k_iota_i64(int64_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = i;
+}
+
+__global__ void k_iota_i32(int32_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_gather_edges(int64_t m, const int64_t *perm, const int32_t *src_in, const int32_t *dst_in,
+                               const float *w_in, int32_t *src_out, int32_t *dst_out, float *w_out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t j = perm[i];
+        src_out[i] = src_in[j];
+        dst_out[i] = dst_in[j];
+        if (w_in) w_out[i] = w_in[j];
+    }
+}
+
+template <typename K>
+__global__ void k_make_keys(int64_t m, const int64_t *t, int64_t t_min, K *tk) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        tk[i] = (K)(t[i] - t_min);
+}
+
+__global__ void k_check_ids(int64_t m, int64_t n, const int32_t *src, const int32_t *dst, uint32_t *bad) {
+    uint32_t any = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t s = src[i], d = dst[i];
+        any |= (s < 0 || s >= n || d < 0 || d >= n) ? 1u : 0u;
+    }
+    if (any) atomicOr(bad, 1u);
+}
+
+__global__ void k_degree(int64_t m, const int32_t *key, uint32_t *deg) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&deg[key[i]], 1u);
+}
+
+__global__ void k_add_u32(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] += v;
+}
+
+template <typename K>
+__global__ void k_gather_adj(int64_t m, const int32_t *eids, const int32_t *other, const K *tk, const float *w,
+                             K *adj_t, int32_t *adj_nbr, int32_t *adj_eid, float *adj_w) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x) {
+        int32_t e = eids[p];
+        adj_t[p] = tk[e];
+        adj_nbr[p] = other[e];
+        adj_eid[p] = e;
+        if (w) adj_w[p] = w[e];
+    }
+}
+
+int bits_for(int64_t n) {
+    int b = 1;
+    while (b < 31 && (int64_t(1) << b) < n) b++;
+    return b;
+}
+
+}  // namespace
+
+hipError_t dev_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_fill_u64<<<blocks_for(n), kThreads, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t dev_exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, void *tmp, size_t *tmp_bytes,
+                                  hipStream_t s) {
+    return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, in, out, (int)n, s);
+}
+
+hipError_t dev_check_ids(int64_t m, int64_t n, const int32_t *d_src, const int32_t *d_dst, uint32_t *d_bad,
+                         hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    k_check_ids<<<blocks_for(m), kThreads, 0, s>>>(m, n, d_src, d_dst, d_bad);
+    return hipGetLastError();
+}
+
+hipError_t dev_sort_by_time(int64_t m, int64_t *d_t, int64_t *d_perm, hipStream_t s) {
+    // stable sort of (t, position): returns sorted t in d_t and the input
+    // position of each sorted edge in d_perm
+    if (m <= 1) {
+        if (m == 1) k_iota_i64<<<1, kThreads, 0, s>>>(d_perm, m);
+        return hipGetLastError();
+    }
+    int64_t *t_out = nullptr, *idx_in = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    hipError_t e = hipMalloc(&t_out, m * sizeof(int64_t));
+    if (e != hipSuccess) return e;
+    e = hipMalloc(&idx_in, m * sizeof(int64_t));
+    if (e != hipSuccess) { hipFree(t_out); return e; }
+    k_iota_i64<<<blocks_for(m), kThreads, 0, s>>>(idx_in, m);
+    e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, d_t, t_out, idx_in, d_perm, (int)m, 0, 64, s);
+    if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes);
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, d_t, t_out, idx_in, d_perm, (int)m, 0, 64, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_t, t_out, m * sizeof(int64_t), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(tmp);
+    hipFree(t_out);
+    hipFree(idx_in);
+    return e;
+}
+
+hipError_t dev_gather_edges(int64_t m, const int64_t *d_perm, const int32_t *src_in, const int32_t *dst_in,
+                            const float *w_in, int32_t *src_out, int32_t *dst_out, float *w_out, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    k_gather_edges<<<blocks_for(m), kThreads, 0, s>>>(m, d_perm, src_in, dst_in, w_in, src_out, dst_out, w_out);
+    return hipGetLastError();
+}
+
+hipError_t dev_make_keys(int64_t m, const int64_t *d_t, int64_t t_min, int key_bytes, void *d_tk, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    if (key_bytes == 4)
+        k_make_keys<int32_t><<<blocks_for(m), kThreads, 0, s>>>(m, d_t, t_min, (int32_t *)d_tk);
+    else
+        k_make_keys<int64_t><<<blocks_for(m), kThreads, 0, s>>>(m, d_t, t_min, (int64_t *)d_tk);
+    return hipGetLastError();
+}
+
+// Build one direction of the adjacency. d_key = the node that owns the list
+// (src for out-lists, dst for in-lists), d_other = the neighbour. Positions
+// are offset by `add` (0 for out-lists, m for in-lists).
+hipError_t dev_build_csr(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
+                         int key_bytes, const float *d_w, uint32_t add, uint32_t *d_off, void *d_adj_t,
+                         int32_t *d_adj_nbr, int32_t *d_adj_eid, float *d_adj_w, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    uint32_t *deg = nullptr;
+    int32_t *keys_out = nullptr, *ids_in = nullptr, *ids_out = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0, scan_bytes = 0;
+    const int nbits = bits_for(n);
+    e = hipMalloc(&deg, (n + 1) * sizeof(uint32_t));
+    if (e != hipSuccess) return e;
+    k_fill_u32<<<blocks_for(n + 1), kThreads, 0, s>>>(deg, 0u, n + 1);
+    if (m > 0) {
+        e = hipMalloc(&keys_out, m * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&ids_in, m * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&ids_out, m * sizeof(int32_t));
+        if (e != hipSuccess) goto done;
+        k_degree<<<blocks_for(m), kThreads, 0, s>>>(m, d_key, deg);
+        k_iota_i32<<<blocks_for(m), kThreads, 0, s>>>(ids_in, m);
+        e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, d_key, keys_out, ids_in, ids_out, (int)m, 0,
+                                               nbits, s);
+        if (e != hipSuccess) goto done;
+    }
+    e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, deg, d_off, (int)(n + 1), s);
+    if (e != hipSuccess) goto done;
+    if (scan_bytes > tmp_bytes) tmp_bytes = scan_bytes;
+    e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1);
+    if (e != hipSuccess) goto done;
+    if (m > 0) {
+        e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, d_key, keys_out, ids_in, ids_out, (int)m, 0, nbits,
+                                               s);
+        if (e != hipSuccess) goto done;
+    }
+    e = hipcub::DeviceScan::ExclusiveSum(tmp, scan_bytes, deg, d_off, (int)(n + 1), s);
+    if (e != hipSuccess) goto done;
+    if (add) k_add_u32<<<blocks_for(n + 1), kThreads, 0, s>>>(d_off, add, n + 1);
+    if (m > 0) {
+        if (key_bytes == 4)
+            k_gather_adj<int32_t><<<blocks_for(m), kThreads, 0, s>>>(
+                m, ids_out, d_other, (const int32_t *)d_tk, d_w, (int32_t *)d_adj_t + add, d_adj_nbr + add,
+                d_adj_eid + add, d_w ? d_adj_w + add : nullptr);
+        else
+            k_gather_adj<int64_t><<<blocks_for(m), kThreads, 0, s>>>(
+                m, ids_out, d_other, (const int64_t *)d_tk, d_w, (int64_t *)d_adj_t + add, d_adj_nbr + add,
+                d_adj_eid + add, d_w ? d_adj_w + add : nullptr);
+    }
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+done:
+    hipStreamSynchronize(s);
+    hipFree(tmp);
+    hipFree(ids_out);
+    hipFree(ids_in);
+    hipFree(keys_out);
+    hipFree(deg);
+    return e;
+}
+
+}  // namespace tmo

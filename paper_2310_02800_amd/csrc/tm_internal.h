@@ -1,0 +1,172 @@
+// Internal structures of the temporal motif library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tmotif.h"
+
+namespace tmo {
+
+// Launch arguments of the mining kernels. The generated device source declares
+// the same two structs (QArgs per query, GArgs per launch); sizes are checked
+// by static_assert on both sides.
+struct QArgs {
+    int64_t r0, r1;     // root id range [r0, r1)
+    int64_t delta;      // clamped to the graph's time span
+    int64_t gap[8];     // fine-grained limits, clamped to delta
+    int64_t c0, nchunks;  // this query's slice of the launch's root-chunk queue
+    float theta;
+    int32_t pred_op;
+    int32_t fn;         // which specialised matcher of the module runs it
+    int32_t pad;
+    int64_t reserved;
+};
+static_assert(sizeof(QArgs) == 128, "QArgs layout");
+
+struct GArgs {
+    const int32_t *src;
+    const int32_t *dst;
+    const void *tk;        // relative edge times, int32 or int64, edge-id order
+    const float *w;        // edge weights or null
+    const void *adj_t;     // unified adjacency: out-lists at [0,m), in-lists at [m,2m)
+    const int32_t *adj_nbr;
+    const int32_t *adj_eid;
+    const float *adj_w;
+    const uint32_t *off_out;  // n+1 offsets into [0,m)
+    const uint32_t *off_in;   // n+1 offsets into [m,2m)
+    const QArgs *qa;          // device array of nq queries
+    uint64_t *ctl;            // [0] chunk cursor [1] output overflow [2..6] work counters
+    uint64_t *counts;         // per query
+    uint64_t *chunk_cnt;      // enumeration: per-chunk counts, then write cursors
+    const uint64_t *chunk_off;
+    int64_t *out;
+    uint64_t capacity;
+    int64_t m_edges;
+    int64_t total_chunks;
+    int32_t rch;              // roots per chunk
+    int32_t nq;
+};
+static_assert(sizeof(GArgs) == 160, "GArgs layout");
+
+enum { CTL_CURSOR = 0, CTL_OVERFLOW = 1, CTL_STATS = 2, CTL_WORDS = 8 };
+enum Mode { MODE_COUNT = 0, MODE_STATS = 1, MODE_ENUM_COUNT = 2, MODE_ENUM_WRITE = 3, MODE_COUNT_ = 4 };
+
+// Where a level takes its candidates from (Algorithm 1, GetCandidateEdgeList).
+enum ListKind { LIST_OUT = 0, LIST_IN = 1, LIST_BOTH = 2, LIST_GLOBAL = 3 };
+
+struct Plan {
+    int l = 0, k = 0;
+    int a[TM_MAX_EDGES] = {}, b[TM_MAX_EDGES] = {};
+    int kind[TM_MAX_EDGES] = {};            // per level >= 1
+    std::vector<int> mapped[TM_MAX_EDGES];  // motif nodes bound before level i
+    int pred_level = -1;
+    std::string key() const;
+};
+
+struct Module {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn[MODE_COUNT_] = {};
+    int max_blocks_per_cu = 0;
+    double compile_ms = 0.0;
+};
+
+struct Graph;
+
+// Module cache key: plan structure + timestamp width + block size.
+struct Compiler {
+    std::mutex mu;
+    std::map<std::string, std::shared_ptr<Module>> cache;
+    int device = 0;
+    std::shared_ptr<Module> get(const Plan &p, int key_bytes, int block, std::string *err);
+    std::shared_ptr<Module> get_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
+                                      std::string *err);
+};
+
+std::string generate_source(const Plan &p, int key_bytes, int block);
+std::string generate_batch_source(const std::vector<const Plan *> &plans, int key_bytes, int block);
+bool build_plan(const tm_motif_desc *d, Plan *p, int64_t *gaps, std::string *err);
+bool compile_to_code(const std::string &src, std::vector<char> *code, std::string *err);
+
+// device helpers (tm_device.hip)
+hipError_t dev_build_csr(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
+                         int key_bytes, const float *d_w, uint32_t add, uint32_t *d_off, void *d_adj_t,
+                         int32_t *d_adj_nbr, int32_t *d_adj_eid, float *d_adj_w, hipStream_t s);
+hipError_t dev_sort_by_time(int64_t m, int64_t *d_t, int64_t *d_perm, hipStream_t s);
+hipError_t dev_gather_edges(int64_t m, const int64_t *d_perm, const int32_t *src_in, const int32_t *dst_in,
+                            const float *w_in, int32_t *src_out, int32_t *dst_out, float *w_out, hipStream_t s);
+hipError_t dev_make_keys(int64_t m, const int64_t *d_t, int64_t t_min, int key_bytes, void *d_tk, hipStream_t s);
+hipError_t dev_check_ids(int64_t m, int64_t n, const int32_t *d_src, const int32_t *d_dst, uint32_t *d_bad,
+                         hipStream_t s);
+hipError_t dev_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+hipError_t dev_exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, void *tmp, size_t *tmp_bytes,
+                                  hipStream_t s);
+
+}  // namespace tmo
+
+struct tm_ctx {
+    int device = 0;
+    int num_cus = 0;
+    int block = 256;
+    int64_t root_chunk = 64;
+    int64_t grid = 0;
+    int profile = 0;
+    int split = 0;
+    int64_t split_min = 4;
+    tmo::Compiler compiler;
+    std::mutex ws_mu;
+    struct Workspace {
+        uint64_t *ctl = nullptr;     // CTL_WORDS
+        uint64_t *h_ctl = nullptr;   // pinned host mirror
+        uint64_t *chunk_cnt = nullptr;
+        uint64_t *chunk_off = nullptr;
+        int64_t chunk_cap = 0;
+        void *scan_tmp = nullptr;
+        size_t scan_tmp_bytes = 0;
+        uint64_t *counts = nullptr;  // per query results
+        void *qa = nullptr;          // device QArgs[q_cap]
+        void *h_qa = nullptr;        // pinned staging for qa
+        uint64_t *h_counts = nullptr;
+        int q_cap = 0;
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        bool busy = false;
+    };
+    std::vector<std::unique_ptr<Workspace>> ws;
+    std::mutex prof_mu;
+    double last_ms = 0.0;
+    int last_launches = 0;
+};
+
+struct tm_graph {
+    tm_ctx *ctx = nullptr;
+    int64_t n = 0, m = 0;
+    int64_t t_min = 0, t_max = 0;
+    int key_bytes = 4;
+    bool has_w = false;
+    bool was_sorted = true;
+    int32_t *d_src = nullptr, *d_dst = nullptr;
+    void *d_tk = nullptr;
+    float *d_w = nullptr;
+    void *d_adj_t = nullptr;
+    int32_t *d_adj_nbr = nullptr, *d_adj_eid = nullptr;
+    float *d_adj_w = nullptr;
+    uint32_t *d_off_out = nullptr, *d_off_in = nullptr;
+    std::vector<int64_t> h_t;     // sorted absolute times (root-range lookup)
+    std::vector<int64_t> perm;    // empty when the input was sorted
+    int64_t device_bytes = 0;
+};
+
+struct tm_motif {
+    tm_ctx *ctx = nullptr;
+    tmo::Plan plan;
+    int64_t delta = 0;
+    int64_t gaps[TM_MAX_EDGES] = {};
+    int32_t pred_op = 0;
+    float theta = 0.0f;
+};

@@ -1,0 +1,98 @@
+"""The C-ABI library loads, exports what the header declares, and its motif
+compiler emits and compiles gfx950 code without a GPU. CPU only."""
+from __future__ import annotations
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2310_02800_amd import _native as N
+from paper_2310_02800_amd import api, synth
+from helpers import all_connected_motifs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "tmotif.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = N.lib()
+    declared = header_functions()
+    assert declared, "no declarations parsed"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(N.EXPORTED) == declared
+    assert lib.tm_version() >= 100
+
+
+def test_no_device_calls_fail_cleanly():
+    # tm_create with no GPU reports an error status, never crashes
+    import ctypes
+    h = ctypes.c_void_p()
+    st = N.lib().tm_create(0, ctypes.byref(h))
+    if st == N.TM_OK:
+        N.lib().tm_destroy(h)  # a GPU is present
+    else:
+        assert st in (N.TM_E_DEVICE, N.TM_E_INVALID)
+        assert N.lib().tm_last_error()
+
+
+@pytest.mark.parametrize("edges", [synth.TRIANGLE, synth.FOUR_CYCLE, synth.OUT_STAR3, synth.SKEW_MOTIF,
+                                   [(0, 1)], [(0, 1), (2, 3), (1, 2)], [(1, 0), (0, 1), (1, 0)]])
+@pytest.mark.parametrize("key_bytes", [4, 8])
+def test_motif_compiles_for_gfx950(edges, key_bytes):
+    n = api.motif_compile_check(edges, 100, key_bytes=key_bytes, pred_edge=len(edges) - 1)
+    assert n > 1000
+
+
+def test_random_batch_motifs_compile():
+    for m in synth.batch_queries()[:6]:
+        assert api.motif_compile_check(m.edges, m.delta, pred_edge=m.pred_edge, pred_op=m.pred_op,
+                                       pred_theta=m.pred_theta) > 1000
+
+
+@pytest.mark.parametrize("bad", [
+    dict(edges=[(0, 0)], delta=1),                   # a == b
+    dict(edges=[(0, 1)], delta=-1),                  # negative delta
+    dict(edges=[(0, 2)], delta=1, n_nodes=3),        # node 1 unused
+    dict(edges=[(0, 1), (1, 2)], delta=1, gap=[-1]),  # negative gap
+    dict(edges=[(0, 1)], delta=1, pred_edge=1),      # predicate edge out of range
+    dict(edges=[(0, 1)], delta=1, pred_edge=0, pred_op=9),
+])
+def test_invalid_motifs_rejected(bad):
+    with pytest.raises(N.NativeError) as ei:
+        api.motif_compile_check(**bad)
+    assert ei.value.status == N.TM_E_INVALID
+
+
+def test_too_many_edges_rejected():
+    edges = [(i % 2, 1 - i % 2) for i in range(9)]
+    with pytest.raises(N.NativeError) as ei:
+        api.motif_compile_check(edges, 10)
+    assert ei.value.status == N.TM_E_INVALID
+
+
+def test_plan_list_choice_in_source():
+    """Sec. 5.1.2: the candidate list of each level is fixed ahead of time:
+    triangle level 1 reads the out-list of b, level 2 has both ends mapped
+    and picks the shorter list at run time."""
+    src = api.motif_source(synth.TRIANGLE, 100)
+    assert "lo_ = g.off_out[m1]; hi_ = g.off_out[m1 + 1];" in src
+    assert "bool uo = (ha - la) <= (hb - lb);" in src
+    assert "bool ok = true && nb != m0 && nb != m1;" in src  # only bound nodes are compared
+    src_in = api.motif_source([(0, 1), (2, 1)], 100)
+    assert "lo_ = g.off_in[m1]; hi_ = g.off_in[m1 + 1];" in src_in
+    src_gl = api.motif_source([(0, 1), (2, 3)], 100)
+    assert "lo_ = 0u; hi_ = (u32)g.m_edges;" in src_gl
+
+
+def test_motif_relabelled_to_first_appearance():
+    a = api.motif_source([(2, 0), (0, 1)], 100)
+    b = api.motif_source([(0, 1), (1, 2)], 100)
+    assert a == b
