@@ -80,7 +80,8 @@ void tm_destroy(tm_ctx *ctx);
 /* Tunables (runtime launch parameters; they never change a result).
  *   TM_PARAM_BLOCK         threads per workgroup (64..1024, multiple of 64)
  *   TM_PARAM_ROOT_CHUNK    roots a wavefront takes from the global queue at once (>= 1);
- *                          also the root segment of the enumeration output
+ *                          a chunk interleaves its roots across the range (see
+ *                          tm_enumerate) and is the enumeration output segment
  *   TM_PARAM_GRID          workgroups per launch (0 = fill the GPU by occupancy)
  *   TM_PARAM_PROFILE       1 = time every mining kernel with HIP events
  *   TM_PARAM_SPLIT         1 = hand the pending candidates of busy lanes to idle lanes
@@ -221,7 +222,8 @@ tm_status tm_count(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_r
  *   capacity   rows available in d_out
  *   n_out      host uint64: total number of instances (always written on
  *              TM_OK and TM_E_CAPACITY)
- * Rows are grouped by root segment in root order; the order inside a segment
+ * Rows are grouped by root chunk (chunk j of C holds the roots j, j+C, j+2C,
+ * ... of the range); the order of chunks is fixed, the order inside a chunk
  * is unspecified. With capacity < total, returns TM_E_CAPACITY and leaves
  * d_out unspecified. */
 tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,

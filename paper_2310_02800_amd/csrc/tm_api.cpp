@@ -44,7 +44,7 @@ struct DeviceGuard {
 
 void free_graph_buffers(tm_graph *g) {
     void *ptrs[] = {g->d_src, g->d_dst, g->d_tk, g->d_w, g->d_adj_t, g->d_adj_nbr, g->d_adj_eid, g->d_adj_w,
-                    g->d_off_out, g->d_off_in};
+                    g->d_off_out, g->d_off_in, g->d_pos_out, g->d_pos_in};
     for (void *p : ptrs)
         if (p) hipFree(p);
 }
@@ -93,11 +93,14 @@ hipError_t ws_prepare(tm_ctx::Workspace *w, int64_t chunks, int nq) {
     if (nq > w->q_cap) {
         if (w->counts) hipFree(w->counts);
         if (w->qa) hipFree(w->qa);
+        if (w->qctl) hipFree(w->qctl);
         if (w->h_qa) hipHostFree(w->h_qa);
         if (w->h_counts) hipHostFree(w->h_counts);
-        w->counts = nullptr; w->qa = nullptr; w->h_qa = nullptr; w->h_counts = nullptr; w->q_cap = 0;
+        w->counts = nullptr; w->qa = nullptr; w->qctl = nullptr; w->h_qa = nullptr; w->h_counts = nullptr;
+        w->q_cap = 0;
         int cap = std::max(nq, 64);
         e = hipMalloc(&w->counts, cap * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipMalloc(&w->qctl, 2 * cap * sizeof(uint64_t));
         if (e == hipSuccess) e = hipMalloc(&w->qa, cap * sizeof(QArgs));
         if (e == hipSuccess) e = hipHostMalloc(&w->h_qa, cap * sizeof(QArgs), hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc(&w->h_counts, cap * sizeof(uint64_t), hipHostMallocDefault);
@@ -156,12 +159,16 @@ GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w) {
     a.adj_w = g->d_adj_w;
     a.off_out = g->d_off_out;
     a.off_in = g->d_off_in;
+    a.pos_out = g->d_pos_out;
+    a.pos_in = g->d_pos_in;
     a.qa = (const QArgs *)w->qa;
     a.ctl = w->ctl;
     a.counts = w->counts;
     a.chunk_cnt = w->chunk_cnt;
     a.chunk_off = w->chunk_off;
     a.m_edges = g->m;
+    a.split = g->ctx->split;
+    a.split_min = (int32_t)g->ctx->split_min;
     return a;
 }
 
@@ -176,6 +183,25 @@ tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int 
     hipFunction_t fn = mod->fn[mode];
     if (!fn) return fail(TM_E_DEVICE, "kernel variant missing from module");
     HIP_TRY(tmo::dev_fill_u64(w->ctl, 0, tmo::CTL_WORDS, stream), "reset counters");
+    // cross-wavefront work donation: a zeroed item buffer, fresh queue
+    // heads/tails and a new epoch so items of earlier launches never look ready
+    if (a->split && mode != tmo::MODE_STATS && a->nq > 0) {
+        if (!w->items) {
+            const size_t bytes = tmo::kItemsTotal * tmo::kItemWords * sizeof(uint32_t);
+            HIP_TRY(hipMalloc(&w->items, bytes), "work item buffer");
+            HIP_TRY(hipMemset(w->items, 0, bytes), "work item buffer");
+        }
+        HIP_TRY(tmo::dev_fill_u64(w->qctl, 0, 2 * (int64_t)a->nq, stream), "reset queues");
+        a->items = w->items;
+        a->qctl = w->qctl;
+        a->item_cap = (uint32_t)(tmo::kItemsTotal / (uint64_t)a->nq);
+        a->epoch = ++w->epoch;
+    } else {
+        a->items = nullptr;
+        a->qctl = w->qctl;
+        a->item_cap = 0;
+        a->epoch = 0;
+    }
     void *params[] = {a};
     if (timed) HIP_TRY(hipEventRecord(w->ev0, stream), "hipEventRecord");
     HIP_TRY(hipModuleLaunchKernel(fn, grid_for(ctx, mod), 1, 1, ctx->block, 1, 1, 0, stream, params, nullptr),
@@ -276,6 +302,8 @@ void tm_destroy(tm_ctx *ctx) {
         if (w->scan_tmp) hipFree(w->scan_tmp);
         if (w->counts) hipFree(w->counts);
         if (w->qa) hipFree(w->qa);
+        if (w->qctl) hipFree(w->qctl);
+        if (w->items) hipFree(w->items);
         if (w->h_qa) hipHostFree(w->h_qa);
         if (w->h_counts) hipHostFree(w->h_counts);
         if (w->ev0) hipEventDestroy(w->ev0);
@@ -439,12 +467,14 @@ tm_status tm_load_graph(tm_ctx *ctx, int64_t n, int64_t m, const int32_t *src, c
     if (e == hipSuccess && g->has_w) e = dmalloc(&g->d_adj_w, 2 * m, &acc);
     if (e == hipSuccess) e = dmalloc(&g->d_off_out, n + 1, &acc);
     if (e == hipSuccess) e = dmalloc(&g->d_off_in, n + 1, &acc);
+    if (e == hipSuccess) e = dmalloc(&g->d_pos_out, m, &acc);
+    if (e == hipSuccess) e = dmalloc(&g->d_pos_in, m, &acc);
     if (e != hipSuccess) return cleanup(hip_fail(e, "adjacency allocation"));
     e = tmo::dev_build_csr(n, m, g->d_src, g->d_dst, g->d_tk, g->key_bytes, g->d_w, 0u, g->d_off_out, g->d_adj_t,
-                          g->d_adj_nbr, g->d_adj_eid, g->d_adj_w, s);
+                          g->d_adj_nbr, g->d_adj_eid, g->d_adj_w, g->d_pos_out, s);
     if (e == hipSuccess)
         e = tmo::dev_build_csr(n, m, g->d_dst, g->d_src, g->d_tk, g->key_bytes, g->d_w, (uint32_t)m, g->d_off_in,
-                              g->d_adj_t, g->d_adj_nbr, g->d_adj_eid, g->d_adj_w, s);
+                              g->d_adj_t, g->d_adj_nbr, g->d_adj_eid, g->d_adj_w, g->d_pos_in, s);
     if (e != hipSuccess) return cleanup(hip_fail(e, "adjacency build"));
     g->device_bytes = acc;
     hipStreamDestroy(s);
@@ -589,7 +619,10 @@ tm_status tm_count(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_r
     st = run_single(ctx, g, m, range, stream, tmo::MODE_COUNT, w, mod.get(), &chunks, &r0, &ms);
     if (st != TM_OK) return st;
     HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "read count");
+    HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+            "read control words");
     HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (chunks && w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
     if (ctx->profile) {
         std::lock_guard<std::mutex> lk(ctx->prof_mu);
         ctx->last_ms = ms;
@@ -661,11 +694,14 @@ tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const 
     }
     size_t have = w->scan_tmp_bytes;
     HIP_TRY(tmo::dev_exclusive_scan_u64(w->chunk_cnt, w->chunk_off, chunks + 1, w->scan_tmp, &have, stream), "scan");
-    HIP_TRY(hipMemcpyAsync(w->h_ctl + 8, w->chunk_off + chunks, sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+    HIP_TRY(hipMemcpyAsync(w->h_ctl + 64, w->chunk_off + chunks, sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
             "read total");
     HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "read count");
+    HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+            "read control words");
     HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
-    const uint64_t total = w->h_ctl[8];
+    if (w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
+    const uint64_t total = w->h_ctl[64];
     if (total != w->h_counts[0]) return fail(TM_E_DEVICE, "enumeration pass 1 disagrees with its own total");
     *n_out = total;
     if (total == 0) return TM_OK;
@@ -689,6 +725,7 @@ tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const 
             "read overflow");
     HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "read count");
     HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
     if (timed) {
         float k = 0.f;
         if (hipEventElapsedTime(&k, w->ev0, w->ev1) == hipSuccess) ms += k;
@@ -756,7 +793,10 @@ tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_mot
         }
     }
     HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, q * sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "read counts");
+    HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+            "read control words");
     HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (c0 > 0 && w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
     if (ctx->profile) {
         std::lock_guard<std::mutex> lk(ctx->prof_mu);
         ctx->last_ms = ms;

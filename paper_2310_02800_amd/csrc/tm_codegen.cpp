@@ -115,9 +115,13 @@ struct GArgs {
   u64* counts;
   u64* chunk_cnt; const u64* chunk_off; i64* out; u64 capacity;
   i64 m_edges; i64 total_chunks; int rch; int nq;
+  int split; int split_min;
+  u32* items; u64* qctl; u32 item_cap; u32 epoch;
+  const u32* pos_out; const u32* pos_in;
 };
 static_assert(sizeof(QArgs) == 128, "QArgs layout");
-static_assert(sizeof(GArgs) == 160, "GArgs layout");
+static_assert(sizeof(GArgs) == 208, "GArgs layout");
+
 
 __device__ __forceinline__ int lane_id() {
   return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -145,6 +149,88 @@ __device__ __forceinline__ bool pred_ok(float w, int op, float th) {
   return op == 0 ? (w >= th) : op == 1 ? (w > th) : op == 2 ? (w <= th) : (w < th);
 }
 __device__ __forceinline__ u32 bitlen(u32 x) { return x ? 32u - (u32)__builtin_clz(x) : 0u; }
+// read lane `src`'s value (all 64 lanes must be active)
+__device__ __forceinline__ int shf(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+__device__ __forceinline__ u32 shf(u32 v, int src) { return (u32)__builtin_amdgcn_ds_bpermute(src << 2, (int)v); }
+__device__ __forceinline__ i64 shf(i64 v, int src) {
+  u32 lo = shf((u32)(u64)v, src), hi = shf((u32)((u64)v >> 32), src);
+  return (i64)(((u64)hi << 32) | lo);
+}
+// value of a register in lane j (j uniform)
+__device__ __forceinline__ int rl(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
+__device__ __forceinline__ u32 rl(u32 v, int j) { return (u32)__builtin_amdgcn_readlane((int)v, j); }
+__device__ __forceinline__ i64 rl(i64 v, int j) {
+  const u32 lo = rl((u32)(u64)v, j), hi = rl((u32)((u64)v >> 32), j);
+  return (i64)(((u64)hi << 32) | lo);
+}
+// lane index of the r-th set bit of mask (r < popcount(mask))
+__device__ __forceinline__ int nth_bit(u64 mask, int r) {
+  int pos = 0;
+  for (int step = 32; step >= 1; step >>= 1) {
+    const int cand = pos + step;
+    if (__builtin_popcountll(mask & ((1ull << cand) - 1ull)) <= r) pos = cand;
+  }
+  return pos;
+}
+// Control words (g.ctl): 0 root-chunk cursor, 1 output overflow, 2..6 work
+// counters, 7 handoff error, 8 wavefronts inside a matcher, 9 wavefronts
+// waiting for donated work. g.qctl holds (head, tail) of each query's queue.
+// A donated work item is 32 words: 0 ready (= launch epoch), 1 level,
+// 2 window start, 3 window end, 4-5 window time bound, 6 wanted neighbour,
+// 7 root edge, 8-9 output chunk, 10-11 time limit, 12-19 bound motif nodes,
+// 20-26 edge ids of levels 1..7.
+#define ITEM_WORDS 32u
+// Item words are written and read with device-coherent (agent-scope) relaxed
+// atomics, so no whole-cache writeback or invalidation is needed; ordering
+// comes from waiting for the field stores before the ready word is stored,
+// and for the ready word before the fields are read.
+__device__ __forceinline__ void st_ag(u32* p, u32 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u32 ld_ag(const u32* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_ag64(u32* p, i64 v) { st_ag(p, (u32)(u64)v); st_ag(p + 1, (u32)((u64)v >> 32)); }
+__device__ __forceinline__ i64 ld_ag64(const u32* p) { return (i64)(((u64)ld_ag(p + 1) << 32) | (u64)ld_ag(p)); }
+__device__ __forceinline__ void mem_order() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+__device__ __forceinline__ u64 ld_rlx64(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u32* item_at(const GArgs& g, int qi, u64 slot) {
+  return g.items + ((u64)qi * (u64)g.item_cap + slot) * ITEM_WORDS;
+}
+// Reserve up to `want` donated items of query qi for this wavefront (uniform
+// call, all lanes active). Returns the first slot; *n receives the count.
+__device__ __forceinline__ i64 try_pop(const GArgs& g, int qi, int want, int* n) {
+  i64 h = 0; int k = 0;
+  if (lane_id() == 0 && want > 0) {
+    u64* qc = g.qctl + 2 * qi;
+    const u64 hh = ld_rlx64(&qc[0]);
+    u64 tt = ld_rlx64(&qc[1]);
+    if (tt > (u64)g.item_cap) tt = (u64)g.item_cap;
+    if (hh < tt) {
+      u64 kk = tt - hh;
+      if (kk > (u64)want) kk = (u64)want;
+      if (atomicCAS(&qc[0], hh, hh + kk) == hh) { h = (i64)hh; k = (int)kk; }
+    }
+  }
+  *n = __builtin_amdgcn_readfirstlane(k);
+  return bcast64(h);
+}
+// Wait until a reserved item has been published by its donor.
+__device__ __forceinline__ bool item_ready(const GArgs& g, const u32* it) {
+  u32 spins = 0u;
+  while (ld_ag(it) != g.epoch) {
+    if (++spins > (1u << 22)) { atomicOr((u32*)&g.ctl[7], 1u); return false; }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  mem_order();
+  return true;
+}
 )HIP";
 
 namespace {
@@ -160,8 +246,52 @@ struct Emitter {
         return false;
     }
 
-    // Open the candidate window of level i after binding edge i-1 at time `tp`.
+    // Where level i's window can start without a search: when level i reads
+    // the list that holds the edge matched at level i-1 (the out-list of its
+    // source or the in-list of its destination), the window begins right after
+    // that edge's position, then skips equal timestamps. Returns the position
+    // expression ("" if a search is needed); `c` is the scan position of level
+    // i-1, `r` the root edge.
+    std::string jump_of(int i) const {
+        if (i < 1 || p.kind[i] == LIST_BOTH || p.kind[i] == LIST_GLOBAL) return "";
+        if (p.kind[i] == LIST_OUT && p.a[i] == p.a[i - 1]) {
+            if (i == 1) return "g.pos_out[r] + 1u";
+            if (p.kind[i - 1] == LIST_OUT) return "c + 1u";
+        }
+        if (p.kind[i] == LIST_IN && p.b[i] == p.b[i - 1]) {
+            if (i == 1) return "g.pos_in[r] + 1u";
+            if (p.kind[i - 1] == LIST_IN) return "c + 1u";
+        }
+        return "";
+    }
+
+    // Open level i's window after binding edge i-1 at time `tp`; with a known
+    // start the search collapses to the tie skip (not in the work-counter mode,
+    // which follows the byte model's one search per window).
     void open(int i, const char *tp, const char *ind) {
+        const std::string jump = jump_of(i);
+        if (jump.empty()) {
+            open_search(i, tp, ind);
+            return;
+        }
+        std::string in2 = std::string(ind) + "  ";
+        o << ind << "if (MODE == 1) {\n";
+        open_search(i, tp, in2.c_str());
+        o << ind << "} else {\n";
+        o << in2 << "const u32 lo_ = " << jump << ";\n";
+        if (p.kind[i] == LIST_OUT)
+            o << in2 << "const u32 hi_ = g.off_out[m" << p.a[i] << " + 1];\n";
+        else
+            o << in2 << "const u32 hi_ = g.off_in[m" << p.b[i] << " + 1];\n";
+        o << in2 << "end" << i << " = hi_; exact &= ~" << (1 << i) << "u;\n";
+        o << in2 << "{ i64 h_ = (i64)(" << tp << ") + gap" << (i - 1) << "; hi" << i
+          << " = (tkey)(h_ < (i64)tmaxk ? h_ : (i64)tmaxk); }\n";
+        o << in2 << "sb = lo_; sn = hi_ - lo_; sx = (" << tp << "); lvl = " << i << ";\n";
+        o << in2 << "if (sn == 0u) { cur" << i << " = lo_; ph = 0; } else { ph = 2; }\n";
+        o << ind << "}\n";
+    }
+
+    void open_search(int i, const char *tp, const char *ind) {
         const int A = p.a[i], B = p.b[i];
         o << ind << "{ // open level " << i << "\n";
         o << ind << "  u32 lo_, hi_;\n";
@@ -182,7 +312,7 @@ struct Emitter {
         default:
             o << ind << "  lo_ = 0u; hi_ = (u32)g.m_edges;\n";
         }
-        o << ind << "  end" << i << " = hi_;\n";
+        o << ind << "  end" << i << " = hi_; exact &= ~" << (1 << i) << "u;\n";
         o << ind << "  { i64 h_ = (i64)(" << tp << ") + gap" << (i - 1) << "; hi" << i
           << " = (tkey)(h_ < (i64)tmaxk ? h_ : (i64)tmaxk); }\n";
         o << ind << "  sb = lo_; sn = hi_ - lo_; sx = (" << tp << "); lvl = " << i << ";\n";
@@ -206,18 +336,243 @@ struct Emitter {
         o << ind << "}\n";
     }
 
+    // Intra-wavefront work splitting (sub-tree-level parallelism, Sec. 5.2,
+    // in the spirit of intra-warp work stealing, Sec. 5.2.1). Once the root
+    // queue is drained, every busy lane finds its shallowest level that still
+    // holds at least two candidates inside the time window (an upper-bound
+    // search on the window's end also trims the cached window to its exact
+    // extent, as the paper's context refinement does), and gives a later part
+    // of those pending candidates, with the bound state above that level, to
+    // one idle lane through cross-lane permutes. Donor and thief keep disjoint
+    // candidate ranges, so every instance is still found exactly once.
+    void steal() {
+        const int L = p.l, K = p.k;
+        o << "    if (g.split && drained && MODE != 1) {\n";
+        o << "      iter++;\n";
+        o << "      if ((iter & 31u) == 0u && g.items != 0) {\n";
+        o << "        i64 hv = 0; if (lane == 0) hv = (i64)ld_rlx64(&g.ctl[9]); ghungry = bcast64(hv);\n";
+        o << "      }\n";
+        o << "      const u64 idle = ballot(lvl < 0);\n";
+        o << "      const bool gl = g.items != 0 && ghungry > 0 && (iter & 31u) == 0u;\n";
+        o << "      if ((idle != 0ull || gl) && cool == 0) {\n";
+        o << "        const u64 busy = ballot(lvl > 0);\n";
+        o << "        if (busy != 0ull) {\n";
+        o << "          int dj = 0; u32 ds = 0u, de = 0u; tkey dh = 0; int dw = 0;\n";
+        o << "          if (lvl > 0) {\n";
+        o << "            const int top = ph >= 1 ? lvl - 1 : lvl;\n";
+        for (int i = 1; i < L; i++) {
+            // wide last-level windows are scanned by the whole wavefront already
+            if (i == L - 1 && coop_ok()) continue;
+            const char *arr = p.kind[i] == LIST_GLOBAL ? "g.tk" : "g.adj_t";
+            o << "            if (dj == 0 && base <= " << i << " && " << i << " <= top && end" << i << " - cur" << i
+              << " >= (u32)g.split_min) {\n";
+            o << "              u32 lo = cur" << i << ", n = end" << i << " - cur" << i << ";\n";
+            o << "              if (exact & " << (1 << i) << "u) { lo = end" << i << "; n = 0u; }\n";
+            o << "              while (n > 0u) { const u32 h2 = n >> 1; if (" << arr << "[lo + h2] <= hi" << i
+              << ") { lo += h2 + 1u; n -= h2 + 1u; } else { n = h2; } }\n";
+            o << "              const u32 P = lo - cur" << i << ";\n";
+            o << "              end" << i << " = lo; exact |= " << (1 << i) << "u;\n";
+            o << "              if (P >= 2u) {\n";
+            o << "                dj = " << i << "; de = lo; dh = hi" << i << ";";
+            if (p.kind[i] == LIST_BOTH) o << " dw = want" << i << ";";
+            o << "\n";
+            if (i == L - 1)
+                o << "                ds = cur" << i << " + (P >> 1);\n";
+            else
+                o << "                { u32 f = (P * 3u) / 10u; ds = cur" << i << " + (f < 1u ? 1u : f); }\n";
+            o << "              }\n";
+            o << "            }\n";
+        }
+        o << "          }\n";
+        o << "          const u64 donors = ballot(dj > 0);\n";
+        o << "          const int ni = __builtin_popcountll(idle), nd = __builtin_popcountll(donors);\n";
+        o << "          const int np = ni < nd ? ni : nd;\n";
+        o << "          const int rd = rank_in(donors);\n";
+        o << "          if (np > 0) {\n";
+        o << "            const int rt = rank_in(idle);\n";
+        o << "            const bool thief = lvl < 0 && rt < np;\n";
+        o << "            const int srcl = thief ? nth_bit(donors, rt) : lane;\n";
+        o << "            const int t_dj = shf(dj, srcl); const u32 t_ds = shf(ds, srcl), t_de = shf(de, srcl);\n";
+        o << "            const tkey t_dh = shf(dh, srcl); const int t_dw = shf(dw, srcl);\n";
+        o << "            const int t_root = shf(root, srcl); const i64 t_mych = shf(mych, srcl);\n";
+        o << "            const tkey t_tmax = shf(tmaxk, srcl);\n";
+        for (int v = 0; v < K; v++) o << "            const int t_m" << v << " = shf(m" << v << ", srcl);\n";
+        for (int j = 1; j + 1 < L; j++)
+            o << "            const int t_e" << j << " = MODE == 3 ? shf(e" << j << ", srcl) : 0;\n";
+        o << "            if (thief) {\n";
+        o << "              lvl = t_dj; base = t_dj; ph = 0; root = t_root; mych = t_mych; tmaxk = t_tmax;\n";
+        o << "              exact = 1u << t_dj;\n";
+        for (int v = 0; v < K; v++) o << "              m" << v << " = t_m" << v << ";\n";
+        for (int j = 1; j + 1 < L; j++) o << "              if (MODE == 3) e" << j << " = t_e" << j << ";\n";
+        o << "              switch (t_dj) {\n";
+        for (int i = 1; i < L; i++) {
+            o << "                case " << i << ": cur" << i << " = t_ds; end" << i << " = t_de; hi" << i
+              << " = t_dh;";
+            if (p.kind[i] == LIST_BOTH) o << " want" << i << " = t_dw;";
+            o << " break;\n";
+        }
+        o << "                default: break;\n";
+        o << "              }\n";
+        o << "            } else if (dj > 0 && rd < np) {\n";
+        o << "              switch (dj) {\n";
+        for (int i = 1; i < L; i++) o << "                case " << i << ": end" << i << " = ds; break;\n";
+        o << "                default: break;\n";
+        o << "              }\n";
+        o << "            }\n";
+        o << "          }\n";
+        // donors not paired inside the wavefront publish their split part for
+        // wavefronts that ran out of work (cross-wavefront redistribution)
+        o << "          bool pushed = false;\n";
+        o << "          if (gl && dj > 0 && rd >= np && rd - np < 16) {\n";
+        o << "            const u64 slot = atomicAdd(&g.qctl[2 * qi + 1], 1ull);\n";
+        o << "            if (slot < (u64)g.item_cap) {\n";
+        o << "              u32* it = item_at(g, qi, slot);\n";
+        o << "              st_ag(it + 1, (u32)dj); st_ag(it + 2, ds); st_ag(it + 3, de); st_ag64(it + 4, (i64)dh);\n";
+        o << "              st_ag(it + 6, (u32)dw); st_ag(it + 7, (u32)root); st_ag64(it + 8, mych);\n";
+        o << "              st_ag64(it + 10, (i64)tmaxk);\n";
+        for (int v = 0; v < K; v++) o << "              st_ag(it + " << 12 + v << ", (u32)m" << v << ");\n";
+        for (int j = 1; j + 1 < L; j++)
+            o << "              if (MODE == 3) st_ag(it + " << 19 + j << ", (u32)e" << j << ");\n";
+        o << "              mem_order();\n";
+        o << "              st_ag(it, g.epoch);\n";
+        o << "              pushed = true;\n";
+        o << "              switch (dj) {\n";
+        for (int i = 1; i < L; i++) o << "                case " << i << ": end" << i << " = ds; break;\n";
+        o << "                default: break;\n";
+        o << "              }\n";
+        o << "            }\n";
+        o << "          }\n";
+        o << "          const bool any_push = ballot(pushed) != 0ull;\n";
+        o << "          cool = (np > 0 || any_push) ? 0 : 16;\n";
+        o << "        }\n";
+        o << "      }\n";
+        o << "      if (cool > 0) cool--;\n";
+        // idle lanes still without work take donated items of this query
+        o << "      if (g.items != 0 && (iter & 31u) == 16u) {\n";
+        o << "        const u64 idle2 = ballot(lvl < 0);\n";
+        o << "        if (idle2 != 0ull) {\n";
+        o << "          int n = 0;\n";
+        o << "          const i64 h = try_pop(g, qi, __builtin_popcountll(idle2), &n);\n";
+        o << "          const int r2 = rank_in(idle2);\n";
+        o << "          if (n > 0 && lvl < 0 && r2 < n) {\n";
+        adopt("            ", "(u64)(h + r2)");
+        o << "          }\n";
+        o << "        }\n";
+        o << "      }\n";
+        o << "    }\n";
+    }
+
+    // A lane takes over a donated work item (same state a thief receives).
+    void adopt(const char *ind, const char *slot) {
+        const int L = p.l, K = p.k;
+        o << ind << "const u32* it = item_at(g, qi, " << slot << ");\n";
+        o << ind << "if (item_ready(g, it)) {\n";
+        o << ind << "  const int j = (int)ld_ag(it + 1);\n";
+        o << ind << "  lvl = j; base = j; ph = 0; exact = 1u << j;\n";
+        o << ind << "  root = (int)ld_ag(it + 7); mych = ld_ag64(it + 8); tmaxk = (tkey)ld_ag64(it + 10);\n";
+        for (int v = 0; v < K; v++) o << ind << "  m" << v << " = (int)ld_ag(it + " << 12 + v << ");\n";
+        for (int j = 1; j + 1 < L; j++) o << ind << "  if (MODE == 3) e" << j << " = (int)ld_ag(it + " << 19 + j << ");\n";
+        o << ind << "  const u32 i_s = ld_ag(it + 2), i_e = ld_ag(it + 3); const tkey i_h = (tkey)ld_ag64(it + 4);\n";
+        o << ind << "  const int i_w = (int)ld_ag(it + 6);\n";
+        o << ind << "  switch (j) {\n";
+        for (int i = 1; i < L; i++) {
+            o << ind << "    case " << i << ": cur" << i << " = i_s; end" << i << " = i_e; hi" << i << " = i_h;";
+            if (p.kind[i] == LIST_BOTH) o << " want" << i << " = i_w;";
+            o << " break;\n";
+        }
+        o << ind << "    default: break;\n";
+        o << ind << "  }\n";
+        o << ind << "}\n";
+    }
+
+    bool coop_ok() const { return p.l > 1 && p.kind[p.l - 1] != LIST_GLOBAL; }
+
+    // Wavefront-cooperative last level. A lane whose last-level window is
+    // wide hands it to the whole wavefront: the 64 lanes read 64 consecutive
+    // candidates per step (coalesced), apply the owner's checks, and one
+    // ballot counts (or places) the matches. Owners are served one at a time;
+    // each owner's window is finished and the owner backtracks.
+    void coop() {
+        const int L = p.l, K = p.k, i = p.l - 1;
+        o << "    if (MODE != 1) {\n";
+        o << "      u64 lm = ballot(lvl == " << i << " && ph == 0 && wide);\n";
+        o << "      while (lm != 0ull) {\n";
+        o << "        const int j = __builtin_ctzll(lm); lm &= lm - 1ull;\n";
+        o << "        u32 c = rl(cur" << i << ", j); const u32 e = rl(end" << i << ", j); const tkey h = rl(hi" << i
+          << ", j);\n";
+        std::ostringstream ok;
+        if (p.kind[i] == LIST_BOTH) {
+            o << "        const int w_ = rl(want" << i << ", j);\n";
+            ok << "nb == w_";
+        } else {
+            ok << "true";
+            for (int v : p.mapped[i]) {
+                o << "        const int x" << v << " = rl(m" << v << ", j);\n";
+                ok << " && nb != x" << v;
+            }
+        }
+        o << "        int o_root = 0; i64 o_ch = 0;\n";
+        o << "        if (MODE == 3) { o_root = rl(root, j); o_ch = rl(mych, j); }\n";
+        for (int k = 1; k + 1 < L; k++) o << "        const int o_e" << k << " = MODE == 3 ? rl(e" << k << ", j) : 0;\n";
+        o << "        u64 tot = 0;\n";
+        o << "        for (;;) {\n";
+        o << "          const u32 idx = c + (u32)lane;\n";
+        o << "          bool v = idx < e;\n";
+        o << "          tkey t = 0; int nb = 0;\n";
+        o << "          if (v) { t = g.adj_t[idx]; nb = g.adj_nbr[idx]; }\n";
+        o << "          v = v && t <= h;\n";
+        o << "          bool ok = v && " << ok.str() << ";\n";
+        if (p.pred_level == i) o << "          if (ok) ok = pred_ok(g.adj_w[idx], pop, theta);\n";
+        o << "          const u64 okm = ballot(ok);\n";
+        o << "          tot += (u64)__builtin_popcountll(okm);\n";
+        o << "          if (MODE == 3 && okm != 0ull) {\n";
+        o << "            i64 b0 = 0;\n";
+        o << "            if (lane == 0) b0 = (i64)(g.chunk_off[o_ch] + atomicAdd(&g.chunk_cnt[o_ch], (u64)__builtin_popcountll(okm)));\n";
+        o << "            b0 = bcast64(b0);\n";
+        o << "            if (ok) {\n";
+        o << "              const u64 slot = (u64)b0 + (u64)rank_in(okm);\n";
+        o << "              if (slot < g.capacity) {\n";
+        o << "                i64* row = g.out + slot * " << L << "ull;\n";
+        o << "                row[0] = (i64)o_root;\n";
+        for (int k = 1; k + 1 < L; k++) o << "                row[" << k << "] = (i64)o_e" << k << ";\n";
+        o << "                row[" << (L - 1) << "] = (i64)g.adj_eid[idx];\n";
+        o << "              } else { atomicAdd(&g.ctl[1], 1ull); }\n";
+        o << "            }\n";
+        o << "          }\n";
+        o << "          if (ballot(v) != ~0ull) break;\n";
+        o << "          c += 64u;\n";
+        o << "        }\n";
+        o << "        if (lane == j) {\n";
+        o << "          if (MODE == 2) rcnt += tot; else cnt += tot;\n";
+        o << "          wide = false;\n";
+        o << "          lvl -= 1;\n";
+        o << "          if (lvl < base) {\n";
+        o << "            lvl = 0;\n";
+        o << "            if (MODE == 2 && rcnt) { atomicAdd(&g.chunk_cnt[mych], rcnt); cnt += rcnt; rcnt = 0; }\n";
+        o << "          }\n";
+        o << "        }\n";
+        o << "      }\n";
+        o << "    }\n";
+        (void)K;
+    }
+
     void matcher(int fi) {
         const int L = p.l, K = p.k;
         const bool glob = has_global();
         o << "// motif " << p.key() << "\n";
         o << "template <int MODE>\n__device__ __forceinline__ i64 match" << fi
-          << "(const GArgs& g, int qi, i64 chunk) {\n";
+          << "(const GArgs& g, int qi, i64 chunk, i64 ih, int in) {\n";
         o << "  const int lane = lane_id();\n";
         o << "  const QArgs* q = g.qa + qi;\n";
-        o << "  const i64 q_r0 = q->r0, q_r1 = q->r1, q_delta = q->delta, q_c0 = q->c0, q_c1 = q->c0 + q->nchunks;\n";
+        o << "  const i64 q_r0 = q->r0, q_delta = q->delta, q_c0 = q->c0, q_c1 = q->c0 + q->nchunks;\n";
+        o << "  // chunk j of a query holds its roots j, j + nchunks, j + 2 nchunks, ...: a burst of\n";
+        o << "  // consecutive heavy roots spreads over many wavefronts\n";
+        o << "  const i64 q_nch = q->nchunks, q_n = q->r1 - q->r0;\n";
         for (int i = 0; i + 1 < L; i++) o << "  const i64 gap" << i << " = q->gap[" << i << "];\n";
         if (p.pred_level >= 0) o << "  const float theta = q->theta; const int pop = q->pred_op;\n";
-        o << "  int lvl = 0, ph = 0, root = 0;\n";
+        o << "  int lvl = 0, ph = 0, root = 0, base = 1, cool = 0;\n";
+        o << "  u32 exact = 0u;  // bit i: end of level i's window is its exact extent\n";
+        o << "  bool wide = false;  // last-level window reaches 32+ candidates\n";
         o << "  i64 mych = 0;\n";
         o << "  int";
         for (int v = 0; v < K; v++) o << (v ? ", " : " ") << "m" << v << " = 0";
@@ -230,10 +585,20 @@ struct Emitter {
         }
         o << "  tkey tmaxk = 0, sx = 0; u32 sb = 0u, sn = 0u;\n";
         o << "  u64 cnt = 0, rcnt = 0, st_win = 0, st_probe = 0, st_visit = 0, st_pv = 0, st_root = 0;\n";
-        o << "  i64 pnext = q_r0 + (chunk - q_c0) * (i64)g.rch;\n";
-        o << "  i64 pend = pnext + (i64)g.rch < q_r1 ? pnext + (i64)g.rch : q_r1;\n";
-        o << "  i64 pchunk = chunk, pending = -1;\n";
-        o << "  bool drained = false;\n";
+        o << "  u32 iter = 0u; i64 ghungry = 0;\n";
+        o << "  i64 pnext = 0, pend = 0, pchunk = chunk, pending = -1;\n";
+        o << "  bool drained = chunk < 0;\n";
+        o << "  if (chunk >= 0) {\n";
+        o << "    pnext = 0; pend = (q_n - (chunk - q_c0) + q_nch - 1) / q_nch;\n";
+        o << "  } else {\n";
+        o << "    // start from donated work items [ih, ih + in) of this query\n";
+        o << "    lvl = -1;\n";
+        if (L > 1) {
+            o << "    if (lane < in) {\n";
+            adopt("      ", "(u64)(ih + lane)");
+            o << "    }\n";
+        }
+        o << "  }\n";
         o << "  for (;;) {\n";
         // ---------------- refill
         o << "    const u64 need = ballot(lvl == 0);\n";
@@ -242,7 +607,7 @@ struct Emitter {
         o << "      const i64 rk = (i64)rank_in(need);\n";
         o << "      const i64 avail = pend - pnext;\n";
         o << "      i64 myr = -1, myc = pchunk;\n";
-        o << "      if (lvl == 0 && rk < avail) myr = pnext + rk;\n";
+        o << "      if (lvl == 0 && rk < avail) myr = q_r0 + (pchunk - q_c0) + (pnext + rk) * q_nch;\n";
         o << "      if (avail >= nneed) { pnext += nneed; }\n";
         o << "      else {\n";
         o << "        pnext = pend;\n";
@@ -253,10 +618,9 @@ struct Emitter {
         o << "          if (c >= q_c1) { drained = true; pending = c < g.total_chunks ? c : -1; }\n";
         o << "          else {\n";
         o << "            pchunk = c;\n";
-        o << "            pnext = q_r0 + (c - q_c0) * (i64)g.rch;\n";
-        o << "            pend = pnext + (i64)g.rch < q_r1 ? pnext + (i64)g.rch : q_r1;\n";
+        o << "            pnext = 0; pend = (q_n - (c - q_c0) + q_nch - 1) / q_nch;\n";
         o << "            const i64 k2 = rk - avail;\n";
-        o << "            if (lvl == 0 && myr < 0 && k2 < pend - pnext) { myr = pnext + k2; myc = c; }\n";
+        o << "            if (lvl == 0 && myr < 0 && k2 < pend) { myr = q_r0 + (c - q_c0) + k2 * q_nch; myc = c; }\n";
         o << "            const i64 take = nneed - avail < pend - pnext ? nneed - avail : pend - pnext;\n";
         o << "            pnext += take;\n";
         o << "          }\n";
@@ -271,7 +635,7 @@ struct Emitter {
         o << "          bool ok = s != d;\n";
         if (p.pred_level == 0) o << "          ok = ok && pred_ok(g.w[r], pop, theta);\n";
         o << "          if (ok) {\n";
-        o << "            root = r; mych = myc;\n";
+        o << "            root = r; mych = myc; base = 1;\n";
         if (L == 1) {
             leaf("            ", "0");
             o << "            if (MODE == 2 && rcnt) { atomicAdd(&g.chunk_cnt[mych], rcnt); cnt += rcnt; rcnt = 0; }\n";
@@ -287,9 +651,11 @@ struct Emitter {
         o << "      }\n";
         o << "    }\n";
         o << "    if (ballot(lvl >= 0) == 0ull) break;\n";
+        if (L > 1) steal();
+        if (L > 1 && coop_ok()) coop();
         if (L > 1) {
             // ---------------- search probe
-            o << "    if (lvl > 0 && ph == 1) {\n";
+            o << "    if (lvl > 0 && ph >= 1) {\n";
             if (glob) {
                 o << "      bool gl = false;\n";
                 for (int i = 1; i < L; i++)
@@ -298,12 +664,25 @@ struct Emitter {
             } else {
                 o << "      const tkey* sarr = g.adj_t;\n";
             }
-            o << "      const u32 half = sn >> 1; const u32 mid = sb + half;\n";
+            // ph 2: first probe at the window start (tie skip after a jump)
+            o << "      const u32 half = ph == 2 ? 0u : (sn >> 1); const u32 mid = sb + half;\n";
             o << "      const tkey v = sarr[mid];\n";
             o << "      if (v <= sx) { sb = mid + 1u; sn = sn - half - 1u; } else { sn = half; }\n";
+            o << "      ph = 1;\n";
             o << "      if (sn == 0u) {\n";
             o << "        switch (lvl) {\n";
-            for (int i = 1; i < L; i++) o << "          case " << i << ": cur" << i << " = sb; break;\n";
+            for (int i = 1; i < L; i++) {
+                if (i == L - 1 && coop_ok()) {
+                    // peek 32 candidates ahead: a window that reaches that far is
+                    // scanned by the whole wavefront
+                    o << "          case " << i << ": cur" << i << " = sb;\n";
+                    o << "            if (MODE != 1) { const u32 pk = sb + 31u; wide = pk < end" << i
+                      << " && g.adj_t[pk] <= hi" << i << "; }\n";
+                    o << "            break;\n";
+                } else {
+                    o << "          case " << i << ": cur" << i << " = sb; break;\n";
+                }
+            }
             o << "          default: break;\n";
             o << "        }\n";
             o << "        ph = 0;\n";
@@ -343,7 +722,10 @@ struct Emitter {
             o << "      }\n";
             o << "      if (!inwin) {\n";
             o << "        lvl -= 1;\n";
-            o << "        if (lvl == 0 && MODE == 2 && rcnt) { atomicAdd(&g.chunk_cnt[mych], rcnt); cnt += rcnt; rcnt = 0; }\n";
+            o << "        if (lvl < base) {\n";
+            o << "          lvl = 0;\n";
+            o << "          if (MODE == 2 && rcnt) { atomicAdd(&g.chunk_cnt[mych], rcnt); cnt += rcnt; rcnt = 0; }\n";
+            o << "        }\n";
             o << "      } else {\n";
             o << "        switch (lvl) {\n";
             for (int i = 1; i < L; i++) {
@@ -411,23 +793,69 @@ void emit_kernels(std::ostringstream &o, int nfn, int block, bool all_modes) {
     static const char *names[4] = {"tm_count", "tm_stats", "tm_enum_count", "tm_enum_write"};
     const int nmodes = all_modes ? 4 : 1;
     for (int mode = 0; mode < nmodes; mode++) {
+        auto run = [&](const char *ind, const char *qv, const char *cv, const char *ih, const char *in) {
+            o << ind << "{ const int fn = __builtin_amdgcn_readfirstlane(g.qa[" << qv << "].fn);\n";
+            o << ind << "  switch (fn) {\n";
+            for (int f = 0; f < nfn; f++)
+                o << ind << "    case " << f << ": c = match" << f << "<" << mode << ">(g, " << qv << ", " << cv
+                  << ", " << ih << ", " << in << "); break;\n";
+            o << ind << "    default: c = -1; break;\n";
+            o << ind << "  } }\n";
+        };
         o << "extern \"C\" __global__ __launch_bounds__(" << block << ") void " << names[mode] << "(GArgs g) {\n";
         o << "  const int lane = lane_id();\n";
         o << "  i64 c = 0;\n";
-        o << "  if (lane == 0) c = (i64)atomicAdd(&g.ctl[0], 1ull);\n";
+        o << "  if (lane == 0) { atomicAdd(&g.ctl[8], 1ull); c = (i64)atomicAdd(&g.ctl[0], 1ull); }\n";
         o << "  c = bcast64(c);\n";
-        o << "  while (c >= 0 && c < g.total_chunks) {\n";
-        o << "    int qi = 0;\n";
-        o << "    if (g.nq > 1) { int lo = 0, hi = g.nq - 1;\n";
-        o << "      while (lo < hi) { int md = (lo + hi + 1) >> 1; if (g.qa[md].c0 <= c) lo = md; else hi = md - 1; }\n";
-        o << "      qi = lo; }\n";
-        o << "    qi = __builtin_amdgcn_readfirstlane(qi);\n";
-        o << "    const int fn = __builtin_amdgcn_readfirstlane(g.qa[qi].fn);\n";
-        o << "    switch (fn) {\n";
-        for (int f = 0; f < nfn; f++) o << "      case " << f << ": c = match" << f << "<" << mode << ">(g, qi, c); break;\n";
-        o << "      default: c = -1; break;\n";
+        o << "  bool busy = true, hung = false;\n";
+        o << "  u32 polls = 0u;\n";
+        o << "  for (;;) {\n";
+        o << "    if (c >= 0 && c < g.total_chunks) {\n";
+        o << "      int qi = 0;\n";
+        o << "      if (g.nq > 1) { int lo = 0, hi = g.nq - 1;\n";
+        o << "        while (lo < hi) { int md = (lo + hi + 1) >> 1; if (g.qa[md].c0 <= c) lo = md; else hi = md - 1; }\n";
+        o << "        qi = lo; }\n";
+        o << "      qi = __builtin_amdgcn_readfirstlane(qi);\n";
+        run("      ", "qi", "c", "0", "0");
+        o << "      continue;\n";
         o << "    }\n";
+        // root chunks are gone: wait for work donated by busy wavefronts
+        o << "    if (busy) { if (lane == 0) atomicAdd(&g.ctl[8], ~0ull); busy = false; }\n";
+        o << "    if (" << mode << " == 1 || !g.split || g.items == 0) break;\n";
+        o << "    if (!hung) { if (lane == 0) atomicAdd(&g.ctl[9], 1ull); hung = true; }\n";
+        o << "    int fq = -1, n = 0; i64 h = 0;\n";
+        o << "    for (int qq = 0; qq < g.nq; ++qq) {\n";
+        o << "      int ne = 0;\n";
+        o << "      if (lane == 0) {\n";
+        o << "        const u64 hh = ld_rlx64(&g.qctl[2 * qq]);\n";
+        o << "        u64 tt = ld_rlx64(&g.qctl[2 * qq + 1]);\n";
+        o << "        if (tt > (u64)g.item_cap) tt = (u64)g.item_cap;\n";
+        o << "        ne = hh < tt ? 1 : 0;\n";
+        o << "      }\n";
+        o << "      ne = __builtin_amdgcn_readfirstlane(ne);\n";
+        o << "      if (ne) {\n";
+        o << "        if (lane == 0) atomicAdd(&g.ctl[8], 1ull);  // counted busy before taking items\n";
+        o << "        h = try_pop(g, qq, 64, &n);\n";
+        o << "        if (n > 0) { fq = qq; break; }\n";
+        o << "        if (lane == 0) atomicAdd(&g.ctl[8], ~0ull);\n";
+        o << "      }\n";
+        o << "    }\n";
+        o << "    if (fq >= 0) {\n";
+        o << "      busy = true;\n";
+        o << "      if (lane == 0) atomicAdd(&g.ctl[9], ~0ull);\n";
+        o << "      hung = false; polls = 0u;\n";
+        run("      ", "fq", "-1", "h", "n");
+        o << "      continue;\n";
+        o << "    }\n";
+        o << "    i64 b = 0;\n";
+        o << "    if (lane == 0) b = (i64)ld_rlx64(&g.ctl[8]);\n";
+        o << "    b = bcast64(b);\n";
+        o << "    if (b == 0) break;\n";
+        o << "    if (++polls > (1u << 20)) break;\n";
+        o << "    __builtin_amdgcn_s_sleep(8);\n";
         o << "  }\n";
+        o << "  if (busy && lane == 0) atomicAdd(&g.ctl[8], ~0ull);\n";
+        o << "  if (hung && lane == 0) atomicAdd(&g.ctl[9], ~0ull);\n";
         o << "}\n";
     }
 }

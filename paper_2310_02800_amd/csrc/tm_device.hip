@@ -88,13 +88,15 @@ __global__ void k_add_u32(uint32_t *p, uint32_t v, int64_t n) {
 
 template <typename K>
 __global__ void k_gather_adj(int64_t m, const int32_t *eids, const int32_t *other, const K *tk, const float *w,
-                             K *adj_t, int32_t *adj_nbr, int32_t *adj_eid, float *adj_w) {
+                             K *adj_t, int32_t *adj_nbr, int32_t *adj_eid, float *adj_w, uint32_t *pos,
+                             uint32_t add) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x) {
         int32_t e = eids[p];
         adj_t[p] = tk[e];
         adj_nbr[p] = other[e];
         adj_eid[p] = e;
         if (w) adj_w[p] = w[e];
+        pos[e] = add + (uint32_t)p;
     }
 }
 
@@ -172,7 +174,7 @@ hipError_t dev_make_keys(int64_t m, const int64_t *d_t, int64_t t_min, int key_b
 // are offset by `add` (0 for out-lists, m for in-lists).
 hipError_t dev_build_csr(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
                          int key_bytes, const float *d_w, uint32_t add, uint32_t *d_off, void *d_adj_t,
-                         int32_t *d_adj_nbr, int32_t *d_adj_eid, float *d_adj_w, hipStream_t s) {
+                         int32_t *d_adj_nbr, int32_t *d_adj_eid, float *d_adj_w, uint32_t *d_pos, hipStream_t s) {
     hipError_t e = hipSuccess;
     uint32_t *deg = nullptr;
     int32_t *keys_out = nullptr, *ids_in = nullptr, *ids_out = nullptr;
@@ -210,11 +212,11 @@ hipError_t dev_build_csr(int64_t n, int64_t m, const int32_t *d_key, const int32
         if (key_bytes == 4)
             k_gather_adj<int32_t><<<blocks_for(m), kThreads, 0, s>>>(
                 m, ids_out, d_other, (const int32_t *)d_tk, d_w, (int32_t *)d_adj_t + add, d_adj_nbr + add,
-                d_adj_eid + add, d_w ? d_adj_w + add : nullptr);
+                d_adj_eid + add, d_w ? d_adj_w + add : nullptr, d_pos, add);
         else
             k_gather_adj<int64_t><<<blocks_for(m), kThreads, 0, s>>>(
                 m, ids_out, d_other, (const int64_t *)d_tk, d_w, (int64_t *)d_adj_t + add, d_adj_nbr + add,
-                d_adj_eid + add, d_w ? d_adj_w + add : nullptr);
+                d_adj_eid + add, d_w ? d_adj_w + add : nullptr, d_pos, add);
     }
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -52,10 +52,20 @@ struct GArgs {
     int64_t total_chunks;
     int32_t rch;              // roots per chunk
     int32_t nq;
+    int32_t split;            // 1 = idle lanes take pending candidates from busy lanes
+    int32_t split_min;        // smallest pending index range worth a split search
+    uint32_t *items;          // donated work items, item_cap per query, 32 words each
+    uint64_t *qctl;           // per query: (head, tail) of its item queue
+    uint32_t item_cap;
+    uint32_t epoch;           // launch number; an item is ready when its word 0 equals it
+    const uint32_t *pos_out;  // per edge: its position in its source's out-list
+    const uint32_t *pos_in;   // per edge: its position in its destination's in-list
 };
-static_assert(sizeof(GArgs) == 160, "GArgs layout");
+static_assert(sizeof(GArgs) == 208, "GArgs layout");
 
-enum { CTL_CURSOR = 0, CTL_OVERFLOW = 1, CTL_STATS = 2, CTL_WORDS = 8 };
+enum { CTL_CURSOR = 0, CTL_OVERFLOW = 1, CTL_STATS = 2, CTL_ERROR = 7, CTL_BUSY = 8, CTL_HUNGRY = 9, CTL_WORDS = 16 };
+constexpr uint32_t kItemWords = 32;
+constexpr uint64_t kItemsTotal = uint64_t(1) << 20;  // donated work items per launch (128 MiB)
 enum Mode { MODE_COUNT = 0, MODE_STATS = 1, MODE_ENUM_COUNT = 2, MODE_ENUM_WRITE = 3, MODE_COUNT_ = 4 };
 
 // Where a level takes its candidates from (Algorithm 1, GetCandidateEdgeList).
@@ -97,7 +107,7 @@ bool compile_to_code(const std::string &src, std::vector<char> *code, std::strin
 // device helpers (tm_device.hip)
 hipError_t dev_build_csr(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
                          int key_bytes, const float *d_w, uint32_t add, uint32_t *d_off, void *d_adj_t,
-                         int32_t *d_adj_nbr, int32_t *d_adj_eid, float *d_adj_w, hipStream_t s);
+                         int32_t *d_adj_nbr, int32_t *d_adj_eid, float *d_adj_w, uint32_t *d_pos, hipStream_t s);
 hipError_t dev_sort_by_time(int64_t m, int64_t *d_t, int64_t *d_perm, hipStream_t s);
 hipError_t dev_gather_edges(int64_t m, const int64_t *d_perm, const int32_t *src_in, const int32_t *dst_in,
                             const float *w_in, int32_t *src_out, int32_t *dst_out, float *w_out, hipStream_t s);
@@ -118,7 +128,7 @@ struct tm_ctx {
     int64_t grid = 0;
     int profile = 0;
     int split = 0;
-    int64_t split_min = 4;
+    int64_t split_min = 2;
     tmo::Compiler compiler;
     std::mutex ws_mu;
     struct Workspace {
@@ -134,6 +144,9 @@ struct tm_ctx {
         void *h_qa = nullptr;        // pinned staging for qa
         uint64_t *h_counts = nullptr;
         int q_cap = 0;
+        uint64_t *qctl = nullptr;    // 2 words per query
+        uint32_t *items = nullptr;   // kItemsTotal * kItemWords, zeroed once
+        uint32_t epoch = 0;
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
         bool busy = false;
     };
@@ -157,6 +170,7 @@ struct tm_graph {
     int32_t *d_adj_nbr = nullptr, *d_adj_eid = nullptr;
     float *d_adj_w = nullptr;
     uint32_t *d_off_out = nullptr, *d_off_in = nullptr;
+    uint32_t *d_pos_out = nullptr, *d_pos_in = nullptr;
     std::vector<int64_t> h_t;     // sorted absolute times (root-range lookup)
     std::vector<int64_t> perm;    // empty when the input was sorted
     int64_t device_bytes = 0;

@@ -131,12 +131,26 @@ def test_small_random_graphs_count_and_enumerate(ctx, seed):
 
 @pytest.mark.parametrize("me", [synth.TRIANGLE, synth.FOUR_CYCLE, synth.OUT_STAR3,
                                 [(0, 1), (1, 2), (0, 2), (2, 3)], [(0, 1), (1, 0), (0, 1)],
-                                [(0, 1), (2, 1), (1, 3), (3, 0), (2, 0)]])
+                                [(0, 1), (2, 1), (1, 3), (3, 0), (2, 0)], [(1, 0), (2, 0), (3, 0)],
+                                [(0, 1), (0, 2), (0, 3), (0, 4)]])
 def test_tiny_graph_motifs(ctx, tiny_g, tiny_og, me):
     for d in (0, 600, 10_000, 86_400):
         mot = Motif(me, d)
         say("tiny", me, d)
         assert ctx.count(tiny_g, ctx.compile(mot)) == oracle.count(tiny_og, mot)
+
+
+@pytest.mark.parametrize("mot", [Motif(synth.OUT_STAR3, 86_400), Motif([(1, 0), (2, 0), (3, 0)], 86_400),
+                                 Motif([(0, 1), (0, 2), (2, 3)], 60_000, pred_edge=2, pred_op=0, pred_theta=0.8),
+                                 Motif([(0, 1), (0, 1), (0, 2)], 200_000, gap=[50_000, 90_000]),
+                                 Motif([(0, 1), (2, 1), (3, 1), (1, 0)], 100_000)])
+def test_wide_windows_enumerate(ctx, tiny_g, tiny_og, mot):
+    """Hub windows on the tiny graph are wide enough (32+ candidates) for
+    the wavefront-cooperative last level and the same-list window start."""
+    mm = ctx.compile(mot)
+    want = oracle.enumerate(tiny_og, mot)
+    assert ctx.count(tiny_g, mm) == want.shape[0] > 0
+    assert rows(ctx.enumerate(tiny_g, mm)) == rows(want)
 
 
 def test_tiny_enumerate_with_gaps_and_predicate(ctx, tiny_g, tiny_og):
@@ -177,7 +191,9 @@ def test_root_ranges_are_additive(ctx, tiny_g, tiny_og):
 
 @pytest.mark.parametrize("param,values", [(N.TM_PARAM_ROOT_CHUNK, [1, 7, 64, 4096]),
                                           (N.TM_PARAM_BLOCK, [64, 1024, 256]),
-                                          (N.TM_PARAM_GRID, [1, 3, 0])])
+                                          (N.TM_PARAM_GRID, [1, 3, 0]),
+                                          (N.TM_PARAM_SPLIT, [0, 1]),
+                                          (N.TM_PARAM_SPLIT_MIN, [3, 1000, 2])])
 def test_launch_parameters_do_not_change_results(ctx, tiny_g, tiny_og, param, values):
     mot = Motif(synth.FOUR_CYCLE, 30_000, pred_edge=1, pred_op=0, pred_theta=0.5)
     want = oracle.count(tiny_og, mot)
@@ -195,6 +211,27 @@ def test_launch_parameters_do_not_change_results(ctx, tiny_g, tiny_og, param, va
             assert got == want_rows
     finally:
         ctx.set_param(param, old)
+
+
+@pytest.mark.parametrize("grid,chunk", [(1, 1), (2, 3), (4, 64)])
+def test_splitting_stress(ctx, tiny_g, tiny_og, grid, chunk):
+    """Few workgroups and small root chunks make lanes go idle early, so most
+    of the work moves between lanes by splitting; results stay exact."""
+    old = {p: ctx.get_param(p) for p in (N.TM_PARAM_GRID, N.TM_PARAM_ROOT_CHUNK, N.TM_PARAM_SPLIT)}
+    try:
+        ctx.set_param(N.TM_PARAM_GRID, grid)
+        ctx.set_param(N.TM_PARAM_ROOT_CHUNK, chunk)
+        ctx.set_param(N.TM_PARAM_SPLIT, 1)
+        for mot in (Motif(synth.OUT_STAR3, 60_000), Motif(synth.FOUR_CYCLE, 86_400, gap=[40_000] * 3),
+                    Motif([(0, 1), (1, 2), (0, 2), (2, 3)], 50_000, pred_edge=3, pred_op=2, pred_theta=1.2)):
+            say("split stress", grid, chunk, mot.edges)
+            mm = ctx.compile(mot)
+            assert ctx.count(tiny_g, mm) == oracle.count(tiny_og, mot)
+            if mot.edges != synth.OUT_STAR3:
+                assert rows(ctx.enumerate(tiny_g, mm)) == rows(oracle.enumerate(tiny_og, mot))
+    finally:
+        for p, v in old.items():
+            ctx.set_param(p, v)
 
 
 def test_batch_equals_single_and_oracle(ctx, tiny_g, tiny_og):
