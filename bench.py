@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--plain-only", action="store_true", help="time only the plain form")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after timing, copy 1 GiB once (a known-size kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the method shards by root-time "
@@ -221,6 +223,14 @@ def main():
                   "kernel_source_hash": src_hash},
         "per_query": [{"edges": m.edges, "delta": m.delta, "count": c} for m, c in zip(motifs, counts)],
     }
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+        del src, dst
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(g, motifs, args.cpu_budget)

@@ -86,6 +86,10 @@ void tm_destroy(tm_ctx *ctx);
  *   TM_PARAM_PROFILE       1 = time every mining kernel with HIP events
  *   TM_PARAM_SPLIT         1 = hand the pending candidates of busy lanes to idle lanes
  *   TM_PARAM_SPLIT_MIN     smallest pending window worth splitting (>= 2)
+ *   TM_PARAM_TIER          0 = kernels specialised to each motif structure (compiled
+ *                          once per structure); 1 = table-driven kernels, one per
+ *                          motif length, that read the motif's plan at run time (no
+ *                          compilation per structure)
  */
 enum {
     TM_PARAM_BLOCK = 1,
@@ -93,7 +97,8 @@ enum {
     TM_PARAM_GRID = 3,
     TM_PARAM_PROFILE = 5,
     TM_PARAM_SPLIT = 6,
-    TM_PARAM_SPLIT_MIN = 7
+    TM_PARAM_SPLIT_MIN = 7,
+    TM_PARAM_TIER = 8
 };
 tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t value);
 tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
@@ -196,6 +201,11 @@ tm_status tm_motif_source(const tm_motif_desc *desc, int32_t key_bytes, char *bu
  * may be NULL) receives the code object's size. Errors: TM_E_INVALID,
  * TM_E_COMPILE (log in tm_last_error()). */
 tm_status tm_motif_compile_check(const tm_motif_desc *descs, int32_t q, int32_t key_bytes, int64_t *code_bytes);
+
+/* Compile a table-driven module (TM_PARAM_TIER = 1) without loading it: l in
+ * 1..8 the single-query module for motifs of l edges, l = 0 the batched module
+ * covering every length. Needs no device. Errors: TM_E_INVALID, TM_E_COMPILE. */
+tm_status tm_generic_compile_check(int32_t l, int32_t key_bytes, int64_t *code_bytes);
 
 /* Root range: only instances whose first edge has t_lo <= t <= t_hi (both
  * inclusive); later edges may exceed t_hi. Counts add over disjoint ranges.

@@ -17,13 +17,14 @@ STATUS_NAMES = {0: "TM_OK", 1: "TM_E_INVALID", 2: "TM_E_OOM", 3: "TM_E_COMPILE",
                 5: "TM_E_CAPACITY", 6: "TM_E_UNSUPPORTED", 7: "TM_E_BUSY", 8: "TM_E_CANCELLED"}
 
 TM_PARAM_BLOCK, TM_PARAM_ROOT_CHUNK, TM_PARAM_GRID = 1, 2, 3
-TM_PARAM_PROFILE, TM_PARAM_SPLIT, TM_PARAM_SPLIT_MIN = 5, 6, 7
+TM_PARAM_PROFILE, TM_PARAM_SPLIT, TM_PARAM_SPLIT_MIN, TM_PARAM_TIER = 5, 6, 7, 8
 
 # Every function the header declares, for the export check.
 EXPORTED = [
     "tm_last_error", "tm_version", "tm_create", "tm_destroy", "tm_set_param", "tm_get_param", "tm_last_kernel_ms",
     "tm_load_graph", "tm_free_graph", "tm_graph_get_info", "tm_graph_edge_order", "tm_graph_copy_csr",
-    "tm_compile_motif", "tm_free_motif", "tm_motif_source", "tm_motif_compile_check", "tm_count", "tm_enumerate",
+    "tm_compile_motif", "tm_free_motif", "tm_motif_source", "tm_motif_compile_check", "tm_generic_compile_check",
+    "tm_count", "tm_enumerate",
     "tm_work_stats", "tm_count_batch",
 ]
 
@@ -86,6 +87,7 @@ def lib():
         "tm_free_motif": (None, [P]),
         "tm_motif_source": (i32, [P, i32, P, i64, P]),
         "tm_motif_compile_check": (i32, [P, i32, i32, P]),
+        "tm_generic_compile_check": (i32, [i32, i32, P]),
         "tm_count": (i32, [P, P, P, P, P, P]),
         "tm_enumerate": (i32, [P, P, P, P, P, P, ctypes.c_uint64, P]),
         "tm_work_stats": (i32, [P, P, P, P, P, P]),

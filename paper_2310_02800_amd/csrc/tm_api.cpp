@@ -144,6 +144,7 @@ void fill_qargs(const tm_graph *g, const tm_motif *m, int64_t r0, int64_t r1, in
     q->theta = m->theta;
     q->pred_op = m->pred_op;
     q->fn = fn;
+    tmo::fill_plan_tables(m->plan, q);
 }
 
 GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w) {
@@ -219,7 +220,8 @@ tm_status check_pair(tm_ctx *ctx, const tm_graph *g, const tm_motif *m) {
 
 tm_status get_module(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, std::shared_ptr<tmo::Module> *out) {
     std::string err;
-    auto mod = ctx->compiler.get(m->plan, g->key_bytes, ctx->block, &err);
+    const tmo::Plan gp = tmo::generic_plan(m->plan.l);
+    auto mod = ctx->compiler.get(ctx->tier ? gp : m->plan, g->key_bytes, ctx->block, &err);
     if (!mod) return fail(TM_E_COMPILE, err);
     *out = mod;
     return TM_OK;
@@ -339,6 +341,10 @@ tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t v) {
         if (v < 2) return fail(TM_E_INVALID, "split minimum must be >= 2");
         ctx->split_min = v;
         return TM_OK;
+    case TM_PARAM_TIER:
+        if (v != 0 && v != 1) return fail(TM_E_INVALID, "tier must be 0 or 1");
+        ctx->tier = (int)v;
+        return TM_OK;
     default:
         return fail(TM_E_INVALID, "unknown parameter");
     }
@@ -353,6 +359,7 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *v) {
     case TM_PARAM_PROFILE: *v = ctx->profile; return TM_OK;
     case TM_PARAM_SPLIT: *v = ctx->split; return TM_OK;
     case TM_PARAM_SPLIT_MIN: *v = ctx->split_min; return TM_OK;
+    case TM_PARAM_TIER: *v = ctx->tier; return TM_OK;
     default: return fail(TM_E_INVALID, "unknown parameter");
     }
 }
@@ -552,8 +559,10 @@ tm_status tm_compile_motif(tm_ctx *ctx, const tm_motif_desc *desc, tm_motif **ou
     m->pred_op = desc->pred_op;
     m->theta = desc->pred_theta;
     DeviceGuard dg(ctx->device);
-    // compile eagerly for 32-bit time keys (the common case) so errors surface here
-    if (!ctx->compiler.get(m->plan, 4, ctx->block, &err)) {
+    // compile eagerly for 32-bit time keys (the common case) so errors surface
+    // here; with the generic tier this is the shared module of the motif length
+    const tmo::Plan gp = tmo::generic_plan(m->plan.l);
+    if (!ctx->compiler.get(ctx->tier ? gp : m->plan, 4, ctx->block, &err)) {
         delete m;
         return fail(TM_E_COMPILE, err);
     }
@@ -597,7 +606,27 @@ tm_status tm_motif_compile_check(const tm_motif_desc *descs, int32_t q, int32_t 
                              : tmo::generate_batch_source(uniq, key_bytes, 256);
     std::vector<char> code;
     std::string err;
-    if (!tmo::compile_to_code(src, &code, &err)) return fail(TM_E_COMPILE, err);
+    if (!tmo::cached_code(src, &code, &err)) return fail(TM_E_COMPILE, err);
+    if (code_bytes) *code_bytes = (int64_t)code.size();
+    return TM_OK;
+}
+
+tm_status tm_generic_compile_check(int32_t l, int32_t key_bytes, int64_t *code_bytes) {
+    if (l < 0 || l > TM_MAX_EDGES) return fail(TM_E_INVALID, "motif length out of range");
+    if (key_bytes != 4 && key_bytes != 8) return fail(TM_E_INVALID, "key_bytes must be 4 or 8");
+    std::string src;
+    if (l > 0) {
+        src = tmo::generate_source(tmo::generic_plan(l), key_bytes, 256);
+    } else {
+        std::vector<tmo::Plan> gplans;
+        for (int k = 1; k <= TM_MAX_EDGES; k++) gplans.push_back(tmo::generic_plan(k));
+        std::vector<const tmo::Plan *> ptrs;
+        for (auto &gp : gplans) ptrs.push_back(&gp);
+        src = tmo::generate_batch_source(ptrs, key_bytes, 256);
+    }
+    std::vector<char> code;
+    std::string err;
+    if (!tmo::cached_code(src, &code, &err)) return fail(TM_E_COMPILE, err);
     if (code_bytes) *code_bytes = (int64_t)code.size();
     return TM_OK;
 }
@@ -747,18 +776,26 @@ tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_mot
         if (st != TM_OK) return st;
     }
     DeviceGuard dg(ctx->device);
-    // one matcher per distinct structure
+    // one matcher per distinct structure, or with the generic tier one
+    // table-driven matcher per motif length (a module that never recompiles)
     std::vector<const tmo::Plan *> plans;
     std::vector<int> fn(q);
-    std::map<std::string, int> seen;
-    for (int i = 0; i < q; i++) {
-        std::string k = motifs[i]->plan.key();
-        auto it = seen.find(k);
-        if (it == seen.end()) {
-            it = seen.emplace(k, (int)plans.size()).first;
-            plans.push_back(&motifs[i]->plan);
+    std::vector<tmo::Plan> gplans;
+    if (ctx->tier) {
+        for (int l = 1; l <= TM_MAX_EDGES; l++) gplans.push_back(tmo::generic_plan(l));
+        for (auto &gp : gplans) plans.push_back(&gp);
+        for (int i = 0; i < q; i++) fn[i] = motifs[i]->plan.l - 1;
+    } else {
+        std::map<std::string, int> seen;
+        for (int i = 0; i < q; i++) {
+            std::string k = motifs[i]->plan.key();
+            auto it = seen.find(k);
+            if (it == seen.end()) {
+                it = seen.emplace(k, (int)plans.size()).first;
+                plans.push_back(&motifs[i]->plan);
+            }
+            fn[i] = it->second;
         }
-        fn[i] = it->second;
     }
     std::string err;
     auto mod = ctx->compiler.get_batch(plans, g->key_bytes, ctx->block, &err);

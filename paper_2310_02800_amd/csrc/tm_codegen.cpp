@@ -21,9 +21,14 @@
 //     binary-search probe, or one candidate read. Lanes at different stages
 //     therefore issue their dependent loads together instead of waiting for
 //     each other's searches to finish.
+#include <dlfcn.h>
 #include <hip/hiprtc.h>
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <sstream>
 
@@ -31,7 +36,39 @@
 
 namespace tmo {
 
+Plan generic_plan(int l) {
+    Plan p;
+    p.l = l;
+    p.k = TM_MAX_NODES;
+    p.generic = true;
+    p.pred_level = -1;
+    p.a[0] = 0;
+    p.b[0] = 1;
+    return p;
+}
+
+void fill_plan_tables(const Plan &p, QArgs *q) {
+    q->pred_level = p.pred_level;
+    q->glob_mask = 0;
+    for (int i = 0; i < 8; i++) q->pk[i] = q->pa[i] = q->pb[i] = q->pm[i] = q->pj[i] = 0;
+    for (int i = 1; i < p.l; i++) {
+        q->pk[i] = (uint8_t)p.kind[i];
+        q->pa[i] = (uint8_t)p.a[i];
+        q->pb[i] = (uint8_t)p.b[i];
+        uint32_t mask = 0;
+        for (int v : p.mapped[i]) mask |= 1u << v;
+        q->pm[i] = (uint8_t)mask;
+        if (p.kind[i] == LIST_GLOBAL) q->glob_mask |= 1 << i;
+        // window-start rule, as in the specialised emitter
+        int j = 0;
+        if (p.kind[i] == LIST_OUT && p.a[i] == p.a[i - 1]) j = i == 1 ? 1 : (p.kind[i - 1] == LIST_OUT ? 3 : 0);
+        if (p.kind[i] == LIST_IN && p.b[i] == p.b[i - 1]) j = i == 1 ? 2 : (p.kind[i - 1] == LIST_IN ? 3 : 0);
+        q->pj[i] = (uint8_t)j;
+    }
+}
+
 std::string Plan::key() const {
+    if (generic) return "G" + std::to_string(l);
     std::ostringstream o;
     o << "l" << l << "k" << k << "p" << pred_level << ":";
     for (int i = 0; i < l; i++) o << a[i] << b[i] << ",";
@@ -104,6 +141,9 @@ struct QArgs {
   int fn;
   int pad;
   i64 reserved;
+  unsigned char pk[8], pa[8], pb[8], pm[8], pj[8];
+  int pred_level;
+  int glob_mask;
 };
 
 struct GArgs {
@@ -119,8 +159,20 @@ struct GArgs {
   u32* items; u64* qctl; u32 item_cap; u32 epoch;
   const u32* pos_out; const u32* pos_in;
 };
-static_assert(sizeof(QArgs) == 128, "QArgs layout");
+static_assert(sizeof(QArgs) == 176, "QArgs layout");
 static_assert(sizeof(GArgs) == 208, "GArgs layout");
+// generic matchers: motif node slot by run-time index, and the bound-node check
+#define mget(ix) ((ix) == 0 ? m0 : (ix) == 1 ? m1 : (ix) == 2 ? m2 : (ix) == 3 ? m3 : \
+                  (ix) == 4 ? m4 : (ix) == 5 ? m5 : (ix) == 6 ? m6 : m7)
+#define mset(ix, val) do { const int v_ = (val); const int i_ = (ix); \
+    m0 = i_ == 0 ? v_ : m0; m1 = i_ == 1 ? v_ : m1; m2 = i_ == 2 ? v_ : m2; m3 = i_ == 3 ? v_ : m3; \
+    m4 = i_ == 4 ? v_ : m4; m5 = i_ == 5 ? v_ : m5; m6 = i_ == 6 ? v_ : m6; m7 = i_ == 7 ? v_ : m7; } while (0)
+__device__ __forceinline__ bool notin(u32 mask, int x, int a0, int a1, int a2, int a3, int a4, int a5, int a6,
+                                      int a7) {
+  return !(((mask & 1u) && x == a0) || ((mask & 2u) && x == a1) || ((mask & 4u) && x == a2) ||
+           ((mask & 8u) && x == a3) || ((mask & 16u) && x == a4) || ((mask & 32u) && x == a5) ||
+           ((mask & 64u) && x == a6) || ((mask & 128u) && x == a7));
+}
 
 
 __device__ __forceinline__ int lane_id() {
@@ -235,12 +287,22 @@ __device__ __forceinline__ bool item_ready(const GArgs& g, const u32* it) {
 
 namespace {
 
+// The emitter writes either a matcher specialised to one motif (every plan
+// property a constant) or, with `G`, a generic matcher for all motifs of p.l
+// edges whose per-level properties (list kind, motif nodes, bound-node mask,
+// window-start rule, predicate level) are read from the query's plan tables
+// at run time: it trades some instructions for needing no compilation per
+// motif (used when a query stream holds thousands of distinct structures).
 struct Emitter {
     std::ostringstream o;
     const Plan &p;
-    explicit Emitter(const Plan &pl) : p(pl) {}
+    const bool G;
+    explicit Emitter(const Plan &pl, bool generic = false) : p(pl), G(generic) {}
+
+    std::string I(int i) const { return std::to_string(i); }
 
     bool has_global() const {
+        if (G) return true;
         for (int i = 1; i < p.l; i++)
             if (p.kind[i] == LIST_GLOBAL) return true;
         return false;
@@ -269,6 +331,25 @@ struct Emitter {
     // start the search collapses to the tie skip (not in the work-counter mode,
     // which follows the byte model's one search per window).
     void open(int i, const char *tp, const char *ind) {
+        if (G) {
+            const std::string in2 = std::string(ind) + "  ";
+            o << ind << "if (MODE != 1 && gj" << i << " != 0) {\n";
+            if (i == 1)
+                o << in2 << "const u32 lo_ = (gj1 == 1 ? g.pos_out[r] : g.pos_in[r]) + 1u;\n";
+            else
+                o << in2 << "const u32 lo_ = c + 1u;\n";
+            o << in2 << "const u32 hi_ = gk" << i << " == 0 ? g.off_out[mget(ga" << i << ") + 1] : g.off_in[mget(gb"
+              << i << ") + 1];\n";
+            o << in2 << "end" << i << " = hi_; exact &= ~" << (1 << i) << "u;\n";
+            o << in2 << "{ i64 h_ = (i64)(" << tp << ") + gap" << (i - 1) << "; hi" << i
+              << " = (tkey)(h_ < (i64)tmaxk ? h_ : (i64)tmaxk); }\n";
+            o << in2 << "sb = lo_; sn = hi_ - lo_; sx = (" << tp << "); lvl = " << i << ";\n";
+            o << in2 << "if (sn == 0u) { cur" << i << " = lo_; ph = 0; } else { ph = 2; }\n";
+            o << ind << "} else {\n";
+            open_search(i, tp, in2.c_str());
+            o << ind << "}\n";
+            return;
+        }
         const std::string jump = jump_of(i);
         if (jump.empty()) {
             open_search(i, tp, ind);
@@ -295,7 +376,19 @@ struct Emitter {
         const int A = p.a[i], B = p.b[i];
         o << ind << "{ // open level " << i << "\n";
         o << ind << "  u32 lo_, hi_;\n";
-        switch (p.kind[i]) {
+        if (G) {
+            const std::string s = I(i);
+            o << ind << "  if (gk" << s << " == 0) { const int v_ = mget(ga" << s
+              << "); lo_ = g.off_out[v_]; hi_ = g.off_out[v_ + 1]; }\n";
+            o << ind << "  else if (gk" << s << " == 1) { const int v_ = mget(gb" << s
+              << "); lo_ = g.off_in[v_]; hi_ = g.off_in[v_ + 1]; }\n";
+            o << ind << "  else if (gk" << s << " == 2) {\n";
+            o << ind << "    const int va = mget(ga" << s << "), vb = mget(gb" << s << ");\n";
+            o << ind << "    const u32 la = g.off_out[va], ha = g.off_out[va + 1], lb = g.off_in[vb], hb = g.off_in[vb + 1];\n";
+            o << ind << "    const bool uo = (ha - la) <= (hb - lb);\n";
+            o << ind << "    lo_ = uo ? la : lb; hi_ = uo ? ha : hb; want" << s << " = uo ? vb : va;\n";
+            o << ind << "  } else { lo_ = 0u; hi_ = (u32)g.m_edges; }\n";
+        } else switch (p.kind[i]) {
         case LIST_OUT:
             o << ind << "  lo_ = g.off_out[m" << A << "]; hi_ = g.off_out[m" << A << " + 1];\n";
             break;
@@ -362,10 +455,15 @@ struct Emitter {
         o << "            const int top = ph >= 1 ? lvl - 1 : lvl;\n";
         for (int i = 1; i < L; i++) {
             // wide last-level windows are scanned by the whole wavefront already
-            if (i == L - 1 && coop_ok()) continue;
-            const char *arr = p.kind[i] == LIST_GLOBAL ? "g.tk" : "g.adj_t";
+            if (!G && i == L - 1 && coop_ok()) continue;
+            std::string arr = p.kind[i] == LIST_GLOBAL ? "g.tk" : "g.adj_t";
+            std::string extra;
+            if (G) {
+                arr = "(((gglob >> " + I(i) + ") & 1u) ? g.tk : g.adj_t)";
+                if (i == L - 1) extra = " && ((gglob >> " + I(i) + ") & 1u)";
+            }
             o << "            if (dj == 0 && base <= " << i << " && " << i << " <= top && end" << i << " - cur" << i
-              << " >= (u32)g.split_min) {\n";
+              << " >= (u32)g.split_min" << extra << ") {\n";
             o << "              u32 lo = cur" << i << ", n = end" << i << " - cur" << i << ";\n";
             o << "              if (exact & " << (1 << i) << "u) { lo = end" << i << "; n = 0u; }\n";
             o << "              while (n > 0u) { const u32 h2 = n >> 1; if (" << arr << "[lo + h2] <= hi" << i
@@ -374,7 +472,7 @@ struct Emitter {
             o << "              end" << i << " = lo; exact |= " << (1 << i) << "u;\n";
             o << "              if (P >= 2u) {\n";
             o << "                dj = " << i << "; de = lo; dh = hi" << i << ";";
-            if (p.kind[i] == LIST_BOTH) o << " dw = want" << i << ";";
+            if (G || p.kind[i] == LIST_BOTH) o << " dw = want" << i << ";";
             o << "\n";
             if (i == L - 1)
                 o << "                ds = cur" << i << " + (P >> 1);\n";
@@ -408,7 +506,7 @@ struct Emitter {
         for (int i = 1; i < L; i++) {
             o << "                case " << i << ": cur" << i << " = t_ds; end" << i << " = t_de; hi" << i
               << " = t_dh;";
-            if (p.kind[i] == LIST_BOTH) o << " want" << i << " = t_dw;";
+            if (G || p.kind[i] == LIST_BOTH) o << " want" << i << " = t_dw;";
             o << " break;\n";
         }
         o << "                default: break;\n";
@@ -477,7 +575,7 @@ struct Emitter {
         o << ind << "  switch (j) {\n";
         for (int i = 1; i < L; i++) {
             o << ind << "    case " << i << ": cur" << i << " = i_s; end" << i << " = i_e; hi" << i << " = i_h;";
-            if (p.kind[i] == LIST_BOTH) o << " want" << i << " = i_w;";
+            if (G || p.kind[i] == LIST_BOTH) o << " want" << i << " = i_w;";
             o << " break;\n";
         }
         o << ind << "    default: break;\n";
@@ -485,7 +583,7 @@ struct Emitter {
         o << ind << "}\n";
     }
 
-    bool coop_ok() const { return p.l > 1 && p.kind[p.l - 1] != LIST_GLOBAL; }
+    bool coop_ok() const { return p.l > 1 && (G || p.kind[p.l - 1] != LIST_GLOBAL); }
 
     // Wavefront-cooperative last level. A lane whose last-level window is
     // wide hands it to the whole wavefront: the 64 lanes read 64 consecutive
@@ -501,7 +599,11 @@ struct Emitter {
         o << "        u32 c = rl(cur" << i << ", j); const u32 e = rl(end" << i << ", j); const tkey h = rl(hi" << i
           << ", j);\n";
         std::ostringstream ok;
-        if (p.kind[i] == LIST_BOTH) {
+        if (G) {
+            o << "        const int w_ = rl(want" << i << ", j);\n";
+            for (int v = 0; v < 8; v++) o << "        const int x" << v << " = rl(m" << v << ", j);\n";
+            ok << "(gk" << i << " == 2 ? nb == w_ : notin(gm" << i << ", nb, x0, x1, x2, x3, x4, x5, x6, x7))";
+        } else if (p.kind[i] == LIST_BOTH) {
             o << "        const int w_ = rl(want" << i << ", j);\n";
             ok << "nb == w_";
         } else {
@@ -522,7 +624,10 @@ struct Emitter {
         o << "          if (v) { t = g.adj_t[idx]; nb = g.adj_nbr[idx]; }\n";
         o << "          v = v && t <= h;\n";
         o << "          bool ok = v && " << ok.str() << ";\n";
-        if (p.pred_level == i) o << "          if (ok) ok = pred_ok(g.adj_w[idx], pop, theta);\n";
+        if (G)
+            o << "          if (ok && gpl == " << i << ") ok = pred_ok(g.adj_w[idx], pop, theta);\n";
+        else if (p.pred_level == i)
+            o << "          if (ok) ok = pred_ok(g.adj_w[idx], pop, theta);\n";
         o << "          const u64 okm = ballot(ok);\n";
         o << "          tot += (u64)__builtin_popcountll(okm);\n";
         o << "          if (MODE == 3 && okm != 0ull) {\n";
@@ -569,7 +674,14 @@ struct Emitter {
         o << "  // consecutive heavy roots spreads over many wavefronts\n";
         o << "  const i64 q_nch = q->nchunks, q_n = q->r1 - q->r0;\n";
         for (int i = 0; i + 1 < L; i++) o << "  const i64 gap" << i << " = q->gap[" << i << "];\n";
-        if (p.pred_level >= 0) o << "  const float theta = q->theta; const int pop = q->pred_op;\n";
+        if (G || p.pred_level >= 0) o << "  const float theta = q->theta; const int pop = q->pred_op;\n";
+        if (G) {
+            o << "  const int gpl = q->pred_level; const u32 gglob = (u32)q->glob_mask;\n";
+            for (int i = 1; i < L; i++)
+                o << "  const int gk" << i << " = q->pk[" << i << "], ga" << i << " = q->pa[" << i << "], gb" << i
+                  << " = q->pb[" << i << "], gj" << i << " = q->pj[" << i << "]; const u32 gm" << i << " = q->pm["
+                  << i << "];\n";
+        }
         o << "  int lvl = 0, ph = 0, root = 0, base = 1, cool = 0;\n";
         o << "  u32 exact = 0u;  // bit i: end of level i's window is its exact extent\n";
         o << "  bool wide = false;  // last-level window reaches 32+ candidates\n";
@@ -579,7 +691,7 @@ struct Emitter {
         o << ";\n";
         for (int i = 1; i < L; i++) {
             o << "  u32 cur" << i << " = 0u, end" << i << " = 0u; tkey hi" << i << " = 0;";
-            if (p.kind[i] == LIST_BOTH) o << " int want" << i << " = 0;";
+            if (G || p.kind[i] == LIST_BOTH) o << " int want" << i << " = 0;";
             if (i + 1 < L) o << " int e" << i << " = 0;";
             o << "\n";
         }
@@ -631,9 +743,15 @@ struct Emitter {
         o << "          const int r = (int)myr;\n";
         o << "          const int s = g.src[r], d = g.dst[r];\n";
         o << "          const tkey tr = g.tk[r];\n";
-        o << "          if (MODE == 1) { st_root++;" << (p.pred_level == 0 ? " st_pv++;" : "") << " }\n";
-        o << "          bool ok = s != d;\n";
-        if (p.pred_level == 0) o << "          ok = ok && pred_ok(g.w[r], pop, theta);\n";
+        if (G) {
+            o << "          if (MODE == 1) { st_root++; if (gpl == 0) st_pv++; }\n";
+            o << "          bool ok = s != d;\n";
+            o << "          if (gpl == 0) ok = ok && pred_ok(g.w[r], pop, theta);\n";
+        } else {
+            o << "          if (MODE == 1) { st_root++;" << (p.pred_level == 0 ? " st_pv++;" : "") << " }\n";
+            o << "          bool ok = s != d;\n";
+            if (p.pred_level == 0) o << "          ok = ok && pred_ok(g.w[r], pop, theta);\n";
+        }
         o << "          if (ok) {\n";
         o << "            root = r; mych = myc; base = 1;\n";
         if (L == 1) {
@@ -656,7 +774,9 @@ struct Emitter {
         if (L > 1) {
             // ---------------- search probe
             o << "    if (lvl > 0 && ph >= 1) {\n";
-            if (glob) {
+            if (G) {
+                o << "      const tkey* sarr = ((gglob >> lvl) & 1u) ? g.tk : g.adj_t;\n";
+            } else if (glob) {
                 o << "      bool gl = false;\n";
                 for (int i = 1; i < L; i++)
                     if (p.kind[i] == LIST_GLOBAL) o << "      gl = gl || lvl == " << i << ";\n";
@@ -676,8 +796,8 @@ struct Emitter {
                     // peek 32 candidates ahead: a window that reaches that far is
                     // scanned by the whole wavefront
                     o << "          case " << i << ": cur" << i << " = sb;\n";
-                    o << "            if (MODE != 1) { const u32 pk = sb + 31u; wide = pk < end" << i
-                      << " && g.adj_t[pk] <= hi" << i << "; }\n";
+                    o << "            if (MODE != 1" << (G ? " && !((gglob >> " + I(i) + ") & 1u)" : std::string())
+                      << ") { const u32 pk = sb + 31u; wide = pk < end" << i << " && g.adj_t[pk] <= hi" << i << "; }\n";
                     o << "            break;\n";
                 } else {
                     o << "          case " << i << ": cur" << i << " = sb; break;\n";
@@ -696,10 +816,15 @@ struct Emitter {
             o << "        default: break;\n";
             o << "      }\n";
             o << "      bool inwin = false; tkey tt = 0; int nb = 0;";
-            if (p.pred_level >= 1) o << " float wv = 0.0f;";
+            if (G || p.pred_level >= 1) o << " float wv = 0.0f;";
             o << "\n";
             o << "      if (c < e) {\n";
-            if (glob) {
+            if (G) {
+                o << "        const bool gl = ((gglob >> lvl) & 1u) != 0u;\n";
+                o << "        tt = gl ? g.tk[c] : g.adj_t[c];\n";
+                o << "        if (!gl) nb = g.adj_nbr[c];\n";
+                o << "        if (lvl == gpl) wv = gl ? g.w[c] : g.adj_w[c];\n";
+            } else if (glob) {
                 o << "        bool gl = false;\n";
                 for (int i = 1; i < L; i++)
                     if (p.kind[i] == LIST_GLOBAL) o << "        gl = gl || lvl == " << i << ";\n";
@@ -716,9 +841,12 @@ struct Emitter {
                     o << "        if (lvl == " << p.pred_level << ") wv = g.adj_w[c];\n";
             }
             o << "        inwin = tt <= h;\n";
-            o << "        if (MODE == 1) { st_visit++;"
-              << (p.pred_level >= 1 ? " if (lvl == " + std::to_string(p.pred_level) + ") st_pv++;" : std::string())
-              << " }\n";
+            if (G)
+                o << "        if (MODE == 1) { st_visit++; if (lvl == gpl) st_pv++; }\n";
+            else
+                o << "        if (MODE == 1) { st_visit++;"
+                  << (p.pred_level >= 1 ? " if (lvl == " + std::to_string(p.pred_level) + ") st_pv++;" : std::string())
+                  << " }\n";
             o << "      }\n";
             o << "      if (!inwin) {\n";
             o << "        lvl -= 1;\n";
@@ -732,6 +860,32 @@ struct Emitter {
                 const int A = p.a[i], B = p.b[i];
                 o << "        case " << i << ": {\n";
                 o << "          cur" << i << " = c + 1u;\n";
+                if (G) {
+                    const std::string s = I(i);
+                    const std::string ms = "m0, m1, m2, m3, m4, m5, m6, m7";
+                    const std::string eidx = "(gk" + s + " == 3 ? (int)c : g.adj_eid[c])";
+                    o << "          int cs = 0, cd = 0; bool ok;\n";
+                    o << "          if (gk" << s << " == 2) ok = nb == want" << s << ";\n";
+                    o << "          else if (gk" << s << " == 3) { cs = g.src[c]; cd = g.dst[c];\n";
+                    o << "            ok = cs != cd && notin(gm" << s << ", cs, " << ms << ") && notin(gm" << s
+                      << ", cd, " << ms << "); }\n";
+                    o << "          else ok = notin(gm" << s << ", nb, " << ms << ");\n";
+                    o << "          if (gpl == " << i << ") ok = ok && pred_ok(wv, pop, theta);\n";
+                    o << "          if (ok) {\n";
+                    if (i == L - 1) {
+                        leaf("            ", eidx.c_str());
+                    } else {
+                        o << "            if (gk" << s << " == 0) mset(gb" << s << ", nb);\n";
+                        o << "            else if (gk" << s << " == 1) mset(ga" << s << ", nb);\n";
+                        o << "            else if (gk" << s << " == 3) { mset(ga" << s << ", cs); mset(gb" << s
+                          << ", cd); }\n";
+                        o << "            if (MODE == 3) e" << i << " = " << eidx << ";\n";
+                        open(i + 1, "tt", "            ");
+                    }
+                    o << "          }\n";
+                    o << "        } break;\n";
+                    continue;
+                }
                 std::ostringstream ok;
                 std::string bind;
                 std::string eid;
@@ -872,8 +1026,7 @@ static std::string header(int key_bytes) {
 }
 
 std::string generate_source(const Plan &p, int key_bytes, int block) {
-    std::vector<const Plan *> v{&p};
-    Emitter e(p);
+    Emitter e(p, p.generic);
     e.o << header(key_bytes);
     e.matcher(0);
     emit_kernels(e.o, 1, block, true);
@@ -884,7 +1037,7 @@ std::string generate_batch_source(const std::vector<const Plan *> &plans, int ke
     std::ostringstream all;
     all << header(key_bytes);
     for (size_t f = 0; f < plans.size(); f++) {
-        Emitter e(*plans[f]);
+        Emitter e(*plans[f], plans[f]->generic);
         e.matcher((int)f);
         all << e.o.str();
     }
@@ -920,10 +1073,93 @@ bool compile_to_code(const std::string &src, std::vector<char> *code, std::strin
     return true;
 }
 
+// On-disk code-object cache. A cache file holds a magic word, the full
+// source text it was compiled from and the code object; it is used only when
+// the stored source equals the requested one byte for byte, so a stale or
+// colliding entry is recompiled, never loaded. Directory: $TMOTIF_KERNEL_CACHE,
+// else `_kcache` beside the library; an unwritable directory disables it.
+static std::string cache_dir() {
+    static std::string dir = [] {
+        const char *env = std::getenv("TMOTIF_KERNEL_CACHE");
+        if (env) return std::string(env);
+        Dl_info info;
+        if (dladdr((const void *)&cache_dir, &info) && info.dli_fname) {
+            std::string p(info.dli_fname);
+            size_t s = p.find_last_of('/');
+            return (s == std::string::npos ? std::string(".") : p.substr(0, s)) + "/_kcache";
+        }
+        return std::string();
+    }();
+    return dir;
+}
+
+static std::string cache_path(const std::string &src) {
+    uint64_t h1 = 1469598103934665603ull, h2 = 0x9e3779b97f4a7c15ull;
+    for (unsigned char ch : src) {
+        h1 = (h1 ^ ch) * 1099511628211ull;
+        h2 = (h2 ^ ch) * 0x100000001b3ull + 0x7f4a7c15ull;
+    }
+    char name[64];
+    std::snprintf(name, sizeof(name), "/%016llx%016llx.co", (unsigned long long)h1, (unsigned long long)h2);
+    return cache_dir() + name;
+}
+
+static const uint64_t kCacheMagic = 0x31304f434d544d54ull;  // file format tag
+
+static bool cache_load(const std::string &src, std::vector<char> *code) {
+    const std::string dir = cache_dir();
+    if (dir.empty()) return false;
+    FILE *f = std::fopen(cache_path(src).c_str(), "rb");
+    if (!f) return false;
+    uint64_t hdr[2] = {0, 0};
+    bool ok = std::fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == kCacheMagic && hdr[1] == src.size();
+    if (ok) {
+        std::string stored(src.size(), '\0');
+        ok = std::fread(&stored[0], 1, src.size(), f) == src.size() && stored == src;
+    }
+    if (ok) {
+        std::vector<char> buf;
+        char tmp[1 << 16];
+        size_t n;
+        while ((n = std::fread(tmp, 1, sizeof(tmp), f)) > 0) buf.insert(buf.end(), tmp, tmp + n);
+        ok = !buf.empty();
+        if (ok) code->swap(buf);
+    }
+    std::fclose(f);
+    return ok;
+}
+
+static void cache_store(const std::string &src, const std::vector<char> &code) {
+    const std::string dir = cache_dir();
+    if (dir.empty()) return;
+    mkdir(dir.c_str(), 0755);
+    const std::string path = cache_path(src);
+    const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return;
+    uint64_t hdr[2] = {kCacheMagic, (uint64_t)src.size()};
+    bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1 && std::fwrite(src.data(), 1, src.size(), f) == src.size() &&
+              std::fwrite(code.data(), 1, code.size(), f) == code.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (ok) ok = std::rename(tmp.c_str(), path.c_str()) == 0;
+    if (!ok) std::remove(tmp.c_str());
+}
+
+bool cached_code(const std::string &src, std::vector<char> *code, std::string *err) {
+    // the cache key is the compiler version plus the exact source text
+    int major = 0, minor = 0;
+    hiprtcVersion(&major, &minor);
+    const std::string key = "// hiprtc " + std::to_string(major) + "." + std::to_string(minor) + "\n" + src;
+    if (cache_load(key, code)) return true;
+    if (!compile_to_code(src, code, err)) return false;
+    cache_store(key, *code);
+    return true;
+}
+
 static bool compile_module(const std::string &src, int block, int nmodes, Module *out, std::string *err) {
     auto t0 = std::chrono::steady_clock::now();
     std::vector<char> code;
-    if (!compile_to_code(src, &code, err)) return false;
+    if (!cached_code(src, &code, err)) return false;
     hipError_t he = hipModuleLoadData(&out->mod, code.data());
     if (he != hipSuccess) {
         *err = std::string("hipModuleLoadData: ") + hipGetErrorString(he);

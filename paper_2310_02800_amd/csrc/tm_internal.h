@@ -27,8 +27,16 @@ struct QArgs {
     int32_t fn;         // which specialised matcher of the module runs it
     int32_t pad;
     int64_t reserved;
+    // plan tables read by the generic (table-driven) matchers, per level:
+    // list kind, source and destination motif node, mask of motif nodes bound
+    // before the level, window-start rule (0 search, 1 after the root in its
+    // source's out-list, 2 after the root in its destination's in-list, 3 after
+    // the previous level's candidate)
+    uint8_t pk[8], pa[8], pb[8], pm[8], pj[8];
+    int32_t pred_level;
+    int32_t glob_mask;  // bit i: level i scans the whole edge list
 };
-static_assert(sizeof(QArgs) == 128, "QArgs layout");
+static_assert(sizeof(QArgs) == 176, "QArgs layout");
 
 struct GArgs {
     const int32_t *src;
@@ -77,8 +85,13 @@ struct Plan {
     int kind[TM_MAX_EDGES] = {};            // per level >= 1
     std::vector<int> mapped[TM_MAX_EDGES];  // motif nodes bound before level i
     int pred_level = -1;
+    bool generic = false;  // table-driven matcher for every motif with l edges
     std::string key() const;
 };
+
+Plan generic_plan(int l);
+// Fill the plan tables a generic matcher reads (and that specialised ones ignore).
+void fill_plan_tables(const Plan &p, QArgs *q);
 
 struct Module {
     hipModule_t mod = nullptr;
@@ -103,6 +116,7 @@ std::string generate_source(const Plan &p, int key_bytes, int block);
 std::string generate_batch_source(const std::vector<const Plan *> &plans, int key_bytes, int block);
 bool build_plan(const tm_motif_desc *d, Plan *p, int64_t *gaps, std::string *err);
 bool compile_to_code(const std::string &src, std::vector<char> *code, std::string *err);
+bool cached_code(const std::string &src, std::vector<char> *code, std::string *err);
 
 // device helpers (tm_device.hip)
 hipError_t dev_build_csr(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
@@ -124,11 +138,12 @@ struct tm_ctx {
     int device = 0;
     int num_cus = 0;
     int block = 256;
-    int64_t root_chunk = 64;
+    int64_t root_chunk = 256;
     int64_t grid = 0;
     int profile = 0;
     int split = 0;
     int64_t split_min = 2;
+    int tier = 0;  // 0: kernels specialised per motif structure, 1: generic per motif length
     tmo::Compiler compiler;
     std::mutex ws_mu;
     struct Workspace {

@@ -23,9 +23,21 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def rows(a):
-    a = a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
-    return sorted(map(tuple, a.tolist()))
+class rows:
+    """An instance set as lexicographically sorted int64 rows (compares with ==)."""
+
+    def __init__(self, a):
+        a = a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
+        a = np.ascontiguousarray(a, dtype=np.int64)
+        if a.ndim == 2 and a.shape[0] > 0:
+            a = a[np.lexsort(a.T[::-1])]
+        self.a = a
+
+    def __eq__(self, other):
+        return self.a.shape == other.a.shape and np.array_equal(self.a, other.a)
+
+    def __repr__(self):
+        return f"rows({self.a.shape[0]} x {self.a.shape[1] if self.a.ndim == 2 else 0})"
 
 
 @pytest.fixture(scope="module")
@@ -127,6 +139,48 @@ def test_small_random_graphs_count_and_enumerate(ctx, seed):
         want = oracle.enumerate(og, mot, **({} if lo is None else dict(t_lo=lo, t_hi=hi)))
         assert ctx.count(dg, mm, **kw) == want.shape[0]
         assert rows(ctx.enumerate(dg, mm, **kw)) == rows(want)
+
+
+@pytest.fixture
+def generic_tier(ctx):
+    old = ctx.get_param(N.TM_PARAM_TIER)
+    ctx.set_param(N.TM_PARAM_TIER, 1)
+    yield ctx
+    ctx.set_param(N.TM_PARAM_TIER, old)
+
+
+def test_generic_tier_small_random_graphs(generic_tier):
+    """The table-driven kernels (one per motif length) on the same random
+    cases as the specialised ones."""
+    ctx = generic_tier
+    for g, mot, lo, hi in _random_cases(3, 40):
+        og = oracle.OracleGraph.from_graph(g)
+        dg = ctx.load_synth(g)
+        mm = ctx.compile(mot)
+        kw = {} if lo is None else dict(t_lo=lo, t_hi=hi)
+        want = oracle.enumerate(og, mot, **kw)
+        say("generic case", mot, lo, hi, g.m)
+        assert ctx.count(dg, mm, **kw) == want.shape[0]
+        assert rows(ctx.enumerate(dg, mm, **kw)) == rows(want)
+
+
+def test_generic_tier_tiny_graph_and_counters(generic_tier, tiny_g, tiny_og):
+    ctx = generic_tier
+    for mot in (synth.tiny_query(), Motif(synth.OUT_STAR3, 86_400), Motif([(1, 0), (2, 0), (3, 0)], 86_400),
+                Motif([(0, 1), (2, 1), (1, 3), (3, 0), (2, 0)], 50_000, gap=[20_000] * 4, pred_edge=3,
+                      pred_op=0, pred_theta=0.7)):
+        mm = ctx.compile(mot)
+        c, st = oracle.count(tiny_og, mot, list_rule=1, with_stats=True)
+        assert ctx.count(tiny_g, mm) == c
+        assert ctx.work_stats(tiny_g, mm) == st
+        assert rows(ctx.enumerate(tiny_g, mm)) == rows(oracle.enumerate(tiny_og, mot))
+
+
+def test_generic_tier_batch(generic_tier, tiny_g, tiny_og):
+    ctx = generic_tier
+    qs = synth.batch_queries()
+    handles = [ctx.compile(m) for m in qs]
+    assert ctx.count_batch(tiny_g, handles) == [oracle.count(tiny_og, m) for m in qs]
 
 
 @pytest.mark.parametrize("me", [synth.TRIANGLE, synth.FOUR_CYCLE, synth.OUT_STAR3,
