@@ -79,9 +79,11 @@ void tm_destroy(tm_ctx *ctx);
 
 /* Tunables (runtime launch parameters; they never change a result).
  *   TM_PARAM_BLOCK         threads per workgroup (64..1024, multiple of 64)
- *   TM_PARAM_ROOT_CHUNK    roots a wavefront takes from the global queue at once (>= 1);
- *                          a chunk interleaves its roots across the range (see
- *                          tm_enumerate) and is the enumeration output segment
+ *   TM_PARAM_ROOT_CHUNK    most roots a wavefront takes from the global queue at once
+ *                          (>= 1); launches over few roots use smaller chunks (about
+ *                          four per compute unit, at least 64 roots). A chunk
+ *                          interleaves its roots across the range (see tm_enumerate)
+ *                          and is the enumeration output segment
  *   TM_PARAM_GRID          workgroups per launch (0 = fill the GPU by occupancy)
  *   TM_PARAM_PROFILE       1 = time every mining kernel with HIP events
  *   TM_PARAM_SPLIT         1 = hand the pending candidates of busy lanes to idle lanes
@@ -90,6 +92,8 @@ void tm_destroy(tm_ctx *ctx);
  *                          once per structure); 1 = table-driven kernels, one per
  *                          motif length, that read the motif's plan at run time (no
  *                          compilation per structure)
+ *   TM_PARAM_AUTOTUNE      1 = pick root chunk and splitting per key by measurement
+ *                          (see tm_tune_save); 0 (default) = use the values above
  */
 enum {
     TM_PARAM_BLOCK = 1,
@@ -98,10 +102,35 @@ enum {
     TM_PARAM_PROFILE = 5,
     TM_PARAM_SPLIT = 6,
     TM_PARAM_SPLIT_MIN = 7,
-    TM_PARAM_TIER = 8
+    TM_PARAM_TIER = 8,
+    TM_PARAM_AUTOTUNE = 9
 };
 tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t value);
 tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
+
+/* Autotuning (the launch-setting counterpart of the paper's hyper-parameter
+ * study, Appendix "Impact of Hyper-parameters": stealing threshold and
+ * signal interval there; roots per chunk and splitting here). With
+ * TM_PARAM_AUTOTUNE = 1 the first tm_count or tm_count_batch of a key runs
+ * its launch under each candidate setting (roots per chunk in {16, 64, 256,
+ * 1024}, splitting off and on), checks that every trial returns the same
+ * counts (else TM_E_DEVICE), returns them, and keeps the fastest setting for
+ * the key. Later counts, batches and enumerations with the key use it. The
+ * key is the graph (node and edge counts, time span), the kernel module, and
+ * power-of-two buckets of the largest delta (clamped to the span), of the
+ * number of roots and of the number of queries. Results never depend on
+ * tuning; only the first call of a key pays for the trials.
+ *
+ * tm_last_launch: the setting of the last count / batch / enumerate on ctx
+ * (root chunk used or its upper bound, split flag, 1 if it came from the
+ * tune table). tm_tune_save writes the table as text to path (host string);
+ * tm_tune_load merges a saved table into ctx (TM_E_INVALID if the file
+ * cannot be read or is not a table; then nothing is merged); tm_tune_clear
+ * empties it (n_removed, may be NULL, receives the number of entries). */
+tm_status tm_last_launch(tm_ctx *ctx, int64_t *root_chunk, int32_t *split, int32_t *tuned);
+tm_status tm_tune_save(tm_ctx *ctx, const char *path);
+tm_status tm_tune_load(tm_ctx *ctx, const char *path);
+tm_status tm_tune_clear(tm_ctx *ctx, int64_t *n_removed);
 
 /* Duration in milliseconds of the mining kernels of the last count or
  * enumerate call on this context (summed over their launches), measured with
@@ -233,8 +262,8 @@ tm_status tm_count(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_r
  *   n_out      host uint64: total number of instances (always written on
  *              TM_OK and TM_E_CAPACITY)
  * Rows are grouped by root chunk (chunk j of C holds the roots j, j+C, j+2C,
- * ... of the range); the order of chunks is fixed, the order inside a chunk
- * is unspecified. With capacity < total, returns TM_E_CAPACITY and leaves
+ * ... of the range, C set by the range size and TM_PARAM_ROOT_CHUNK); the
+ * order of chunks is fixed, the order inside a chunk is unspecified. With capacity < total, returns TM_E_CAPACITY and leaves
  * d_out unspecified. */
 tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
                        hipStream_t stream, int64_t *d_out, uint64_t capacity, uint64_t *n_out);
@@ -253,6 +282,74 @@ tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const
  * device queue. counts_out: host uint64[q]. Blocking. */
 tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
                          const tm_root_range *ranges, hipStream_t stream, uint64_t *counts_out);
+
+/* ----------------------------------------------------------------- serving
+ * A request loop over one resident graph with continuous batching. Queries
+ * are copied at submission into a FIFO admission queue. Each of stream_slots
+ * host threads owns a HIP stream; whenever one is free it takes what is
+ * pending: up to max_batch consecutive count queries as one batched launch,
+ * or one enumeration. Batches on different slots overlap on the GPU, so
+ * queries arriving while others run are admitted as slots free up. An
+ * enumeration is admitted by the memory its rows need (8 * l bytes per row,
+ * known after its counting pass) against a device pool of enum_pool_bytes,
+ * waiting while other results hold the pool; rows that would not fit in the
+ * whole pool complete with TM_E_CAPACITY and the count. There is no per-query
+ * compilation when tier = 1 (see TM_PARAM_TIER).
+ * Timestamps are host monotonic-clock nanoseconds (CLOCK_MONOTONIC). */
+typedef struct tm_server tm_server;
+
+typedef struct {
+    int32_t stream_slots;     /* concurrent launches (1..64) */
+    int32_t max_batch;        /* count queries per batched launch (1..4096) */
+    int64_t enum_pool_bytes;  /* device memory for enumeration rows (>= 0) */
+    int32_t queue_capacity;   /* pending queries before TM_E_BUSY (>= 1) */
+    int32_t tier;             /* kernel tier, as TM_PARAM_TIER */
+    const char *tune_path;    /* NULL, or a tune table (tm_tune_save) merged at start if the
+                                 file exists and written back at stop; launches are tuned
+                                 when the context has TM_PARAM_AUTOTUNE = 1 */
+} tm_server_cfg;
+
+typedef struct {
+    tm_motif_desc motif;      /* copied at submission (arrays may be freed after) */
+    tm_root_range range;      /* used when has_range != 0 */
+    int32_t has_range;
+    int32_t enumerate;        /* 0 = count, 1 = enumerate */
+    uint64_t tag;             /* returned with the result */
+} tm_query;
+
+typedef struct {
+    uint64_t ticket, tag;
+    tm_status status;
+    int32_t n_edges;          /* row width of rows */
+    uint64_t count;           /* instances (also for TM_E_CAPACITY) */
+    int64_t *rows;            /* device int64[n_rows][n_edges], owned by the server until tm_release */
+    uint64_t n_rows;
+    int64_t t_arrival_ns, t_admit_ns, t_launch_ns, t_done_ns;
+} tm_result;
+
+/* Start serving graph g of ctx. The graph must outlive the server. Errors:
+ * TM_E_INVALID (configuration out of range), TM_E_OOM (pool). */
+tm_status tm_server_start(tm_ctx *ctx, const tm_graph *g, const tm_server_cfg *cfg, tm_server **out);
+
+/* Submit one query (thread-safe). ticket: host uint64 (may be NULL). Errors:
+ * TM_E_INVALID (malformed motif, predicate without weights), TM_E_BUSY (queue
+ * full), TM_E_CANCELLED (server stopping). */
+tm_status tm_submit_query(tm_server *s, const tm_query *q, uint64_t *ticket);
+
+/* Collect up to max finished results into out (host array), waiting up to
+ * timeout_ms (0 = no wait, < 0 = until one is ready); *n receives how many. */
+tm_status tm_poll(tm_server *s, tm_result *out, int32_t max, int32_t *n, int32_t timeout_ms);
+
+/* Return an enumeration result's rows to the pool (no-op for other tickets). */
+tm_status tm_release(tm_server *s, uint64_t ticket);
+
+/* Queries finished, launches made and queries pending (each may be NULL). */
+tm_status tm_server_stats(tm_server *s, uint64_t *served, uint64_t *batches, uint64_t *pending);
+
+/* Finish every pending query, then stop the slots and free the pool (rows not
+ * released are freed too). With a tune_path, writes the tune table there and
+ * returns that write's status; the server is stopped and freed either way. */
+tm_status tm_server_stop(tm_server *s);
 
 #ifdef __cplusplus
 }

@@ -17,15 +17,17 @@ STATUS_NAMES = {0: "TM_OK", 1: "TM_E_INVALID", 2: "TM_E_OOM", 3: "TM_E_COMPILE",
                 5: "TM_E_CAPACITY", 6: "TM_E_UNSUPPORTED", 7: "TM_E_BUSY", 8: "TM_E_CANCELLED"}
 
 TM_PARAM_BLOCK, TM_PARAM_ROOT_CHUNK, TM_PARAM_GRID = 1, 2, 3
-TM_PARAM_PROFILE, TM_PARAM_SPLIT, TM_PARAM_SPLIT_MIN, TM_PARAM_TIER = 5, 6, 7, 8
+TM_PARAM_PROFILE, TM_PARAM_SPLIT, TM_PARAM_SPLIT_MIN, TM_PARAM_TIER, TM_PARAM_AUTOTUNE = 5, 6, 7, 8, 9
 
 # Every function the header declares, for the export check.
 EXPORTED = [
     "tm_last_error", "tm_version", "tm_create", "tm_destroy", "tm_set_param", "tm_get_param", "tm_last_kernel_ms",
+    "tm_last_launch", "tm_tune_save", "tm_tune_load", "tm_tune_clear",
     "tm_load_graph", "tm_free_graph", "tm_graph_get_info", "tm_graph_edge_order", "tm_graph_copy_csr",
     "tm_compile_motif", "tm_free_motif", "tm_motif_source", "tm_motif_compile_check", "tm_generic_compile_check",
     "tm_count", "tm_enumerate",
-    "tm_work_stats", "tm_count_batch",
+    "tm_work_stats", "tm_count_batch", "tm_server_start", "tm_submit_query", "tm_poll", "tm_release",
+    "tm_server_stats", "tm_server_stop",
 ]
 
 
@@ -37,6 +39,23 @@ class MotifDesc(ctypes.Structure):
 
 class RootRange(ctypes.Structure):
     _fields_ = [("t_lo", ctypes.c_int64), ("t_hi", ctypes.c_int64)]
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("stream_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("enum_pool_bytes", ctypes.c_int64),
+                ("queue_capacity", ctypes.c_int32), ("tier", ctypes.c_int32), ("tune_path", ctypes.c_char_p)]
+
+
+class Query(ctypes.Structure):
+    _fields_ = [("motif", MotifDesc), ("range", RootRange), ("has_range", ctypes.c_int32),
+                ("enumerate", ctypes.c_int32), ("tag", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("n_edges", ctypes.c_int32), ("count", ctypes.c_uint64), ("rows", ctypes.c_void_p),
+                ("n_rows", ctypes.c_uint64), ("t_arrival_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_launch_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -78,6 +97,10 @@ def lib():
         "tm_set_param": (i32, [P, i32, i64]),
         "tm_get_param": (i32, [P, i32, P]),
         "tm_last_kernel_ms": (i32, [P, P, P]),
+        "tm_last_launch": (i32, [P, P, P, P]),
+        "tm_tune_save": (i32, [P, ctypes.c_char_p]),
+        "tm_tune_load": (i32, [P, ctypes.c_char_p]),
+        "tm_tune_clear": (i32, [P, P]),
         "tm_load_graph": (i32, [P, i64, i64, P, P, P, P, u32, pp]),
         "tm_free_graph": (None, [P]),
         "tm_graph_get_info": (i32, [P, P]),
@@ -92,6 +115,12 @@ def lib():
         "tm_enumerate": (i32, [P, P, P, P, P, P, ctypes.c_uint64, P]),
         "tm_work_stats": (i32, [P, P, P, P, P, P]),
         "tm_count_batch": (i32, [P, P, i32, P, P, P, P]),
+        "tm_server_start": (i32, [P, P, P, pp]),
+        "tm_submit_query": (i32, [P, P, P]),
+        "tm_poll": (i32, [P, P, i32, P, i32]),
+        "tm_release": (i32, [P, ctypes.c_uint64]),
+        "tm_server_stats": (i32, [P, P, P, P]),
+        "tm_server_stop": (i32, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

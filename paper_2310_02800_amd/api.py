@@ -6,6 +6,7 @@ for device buffers (enumeration output) and stream handles.
 from __future__ import annotations
 
 import ctypes
+import os
 from typing import Optional, Sequence
 
 import numpy as np
@@ -192,6 +193,23 @@ class Context:
         N.check(N.lib().tm_last_kernel_ms(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
+    def last_launch(self):
+        """(root chunk, split flag, tuned flag) of the last mining call."""
+        r, sp, tu = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        N.check(N.lib().tm_last_launch(self._h, ctypes.byref(r), ctypes.byref(sp), ctypes.byref(tu)))
+        return r.value, sp.value, tu.value
+
+    def tune_save(self, path):
+        N.check(N.lib().tm_tune_save(self._h, os.fsencode(path)))
+
+    def tune_load(self, path):
+        N.check(N.lib().tm_tune_load(self._h, os.fsencode(path)))
+
+    def tune_clear(self) -> int:
+        n = ctypes.c_int64()
+        N.check(N.lib().tm_tune_clear(self._h, ctypes.byref(n)))
+        return n.value
+
     # ---- graph / motif
     def load_graph(self, n_nodes, src, dst, t, w=None) -> Graph:
         s = _np(src, np.int32)
@@ -269,3 +287,82 @@ class Context:
         out = np.zeros(max(q, 1), np.uint64)
         N.check(N.lib().tm_count_batch(self._h, g.handle, q, arr, rr, _stream_handle(stream), _ptr(out)))
         return [int(x) for x in out[:q]]
+
+
+class _DeviceRows:
+    """Device memory the server owns, exposed to torch without a copy."""
+
+    def __init__(self, ptr, n, l):
+        self.__cuda_array_interface__ = {"data": (int(ptr), False), "shape": (int(n), int(l)),
+                                         "typestr": "<i8", "version": 2, "strides": None}
+
+
+class Server:
+    """Continuous-batching query server over one resident graph (tm_server_*)."""
+
+    def __init__(self, ctx: Context, g: Graph, stream_slots=2, max_batch=64, enum_pool_bytes=1 << 30,
+                 queue_capacity=1 << 16, tier=1, tune_path=None):
+        self._tune_path = None if tune_path is None else os.fsencode(tune_path)  # kept alive for the call
+        cfg = N.ServerCfg(int(stream_slots), int(max_batch), int(enum_pool_bytes), int(queue_capacity), int(tier),
+                          self._tune_path)
+        h = ctypes.c_void_p()
+        N.check(N.lib().tm_server_start(ctx._h, g.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._ctx = ctx
+        self._g = g
+
+    def submit(self, motif, t_lo=None, t_hi=None, enumerate=False, tag=0) -> int:
+        """Submit a synth.Motif-like query; returns its ticket."""
+        d, keep = motif_desc_of(motif)
+        q = N.Query()
+        q.motif = d
+        q.has_range = 0 if (t_lo is None and t_hi is None) else 1
+        q.range = N.RootRange(I64_MIN if t_lo is None else int(t_lo), I64_MAX if t_hi is None else int(t_hi))
+        q.enumerate = 1 if enumerate else 0
+        q.tag = int(tag)
+        t = ctypes.c_uint64()
+        N.check(N.lib().tm_submit_query(self._h, ctypes.byref(q), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, max_results=256, timeout_ms=0):
+        buf = (N.Result * max_results)()
+        n = ctypes.c_int32()
+        N.check(N.lib().tm_poll(self._h, buf, int(max_results), ctypes.byref(n), int(timeout_ms)))
+        out = []
+        for r in buf[:n.value]:
+            out.append({"ticket": r.ticket, "tag": r.tag, "status": r.status, "count": r.count,
+                        "rows": r.rows, "n_rows": r.n_rows, "n_edges": r.n_edges,
+                        "t_arrival_ns": r.t_arrival_ns, "t_admit_ns": r.t_admit_ns,
+                        "t_launch_ns": r.t_launch_ns, "t_done_ns": r.t_done_ns})
+        return out
+
+    def rows(self, result):
+        """The result's rows as a torch tensor (a copy; release the ticket after)."""
+        import torch
+        if not result["rows"] or result["n_rows"] == 0:
+            return torch.zeros((0, result["n_edges"]), dtype=torch.int64, device=f"cuda:{self._ctx.device}")
+        dev = torch.device(f"cuda:{self._ctx.device}")
+        view = torch.as_tensor(_DeviceRows(result["rows"], result["n_rows"], result["n_edges"]), device=dev)
+        out = view.clone()
+        # the copy must be done before release() hands the memory to another result
+        torch.cuda.current_stream(dev).synchronize()
+        return out
+
+    def release(self, ticket):
+        N.check(N.lib().tm_release(self._h, ctypes.c_uint64(int(ticket))))
+
+    def stats(self):
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        N.check(N.lib().tm_server_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"served": a.value, "batches": b.value, "pending": c.value}
+
+    def stop(self):
+        if self._h:
+            N.check(N.lib().tm_server_stop(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

@@ -128,6 +128,25 @@ void root_ids(const tm_graph *g, const tm_root_range *rr, int64_t *r0, int64_t *
     if (*r1 < *r0) *r1 = *r0;
 }
 
+// Roots per chunk for a launch over `roots` roots: the configured size, cut
+// down for small ranges so that there are about four chunks (each feeds one
+// wavefront) per compute unit, but never below one root per lane.
+int64_t chunk_for(const tm_ctx *ctx, const tmo::LaunchCfg &c, int64_t roots) {
+    if (c.exact) return c.rch;
+    const int64_t target = 4 * (int64_t)std::max(ctx->num_cus, 1);
+    const int64_t want = std::max<int64_t>((roots + target - 1) / target, 64);
+    return std::min(c.rch, want);
+}
+
+tmo::LaunchCfg default_cfg(const tm_ctx *ctx) {
+    tmo::LaunchCfg c;
+    c.rch = ctx->root_chunk;
+    c.split = ctx->split;
+    c.split_min = ctx->split_min;
+    c.timed = ctx->profile != 0;
+    return c;
+}
+
 // Fill one query's launch arguments. Delta is clamped to the time span (a
 // larger window admits nothing more) and each gap to delta (consecutive gaps
 // never exceed the whole window), so the kernel's window ends never overflow.
@@ -147,7 +166,7 @@ void fill_qargs(const tm_graph *g, const tm_motif *m, int64_t r0, int64_t r1, in
     tmo::fill_plan_tables(m->plan, q);
 }
 
-GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w) {
+GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w, const tmo::LaunchCfg &c) {
     GArgs a;
     std::memset(&a, 0, sizeof(a));
     a.src = g->d_src;
@@ -168,8 +187,8 @@ GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w) {
     a.chunk_cnt = w->chunk_cnt;
     a.chunk_off = w->chunk_off;
     a.m_edges = g->m;
-    a.split = g->ctx->split;
-    a.split_min = (int32_t)g->ctx->split_min;
+    a.split = c.split;
+    a.split_min = (int32_t)c.split_min;
     return a;
 }
 
@@ -218,31 +237,23 @@ tm_status check_pair(tm_ctx *ctx, const tm_graph *g, const tm_motif *m) {
     return TM_OK;
 }
 
-tm_status get_module(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, std::shared_ptr<tmo::Module> *out) {
+tm_status get_module(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, int tier,
+                     std::shared_ptr<tmo::Module> *out) {
     std::string err;
     const tmo::Plan gp = tmo::generic_plan(m->plan.l);
-    auto mod = ctx->compiler.get(ctx->tier ? gp : m->plan, g->key_bytes, ctx->block, &err);
+    auto mod = ctx->compiler.get(tier ? gp : m->plan, g->key_bytes, ctx->block, &err);
     if (!mod) return fail(TM_E_COMPILE, err);
     *out = mod;
     return TM_OK;
 }
 
-void record_time(tm_ctx *ctx, tm_ctx::Workspace *w, int launches, bool timed) {
-    if (!timed) return;
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, w->ev0, w->ev1) != hipSuccess) ms = 0.f;
-    std::lock_guard<std::mutex> lk(ctx->prof_mu);
-    ctx->last_ms = ms;
-    ctx->last_launches = launches;
-}
-
 // One single-query pass in the given mode; leaves results in the workspace.
 tm_status run_single(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
-                     hipStream_t stream, int mode, tm_ctx::Workspace *w, tmo::Module *mod, int64_t *chunks_out,
-                     int64_t *r0_out, double *ms_acc) {
+                     hipStream_t stream, int mode, tm_ctx::Workspace *w, tmo::Module *mod, const tmo::LaunchCfg &cfg,
+                     int64_t *chunks_out, int64_t *r0_out, double *ms_acc) {
     int64_t r0, r1;
     root_ids(g, range, &r0, &r1);
-    const int64_t rch = ctx->root_chunk;
+    const int64_t rch = chunk_for(ctx, cfg, r1 - r0);
     const int64_t chunks = (r1 - r0 + rch - 1) / rch;
     HIP_TRY(ws_prepare(w, chunks, 1), "workspace");
     fill_qargs(g, m, r0, r1, 0, rch, 0, (QArgs *)w->h_qa);
@@ -251,11 +262,11 @@ tm_status run_single(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm
     *chunks_out = chunks;
     *r0_out = r0;
     if (chunks == 0) return TM_OK;
-    GArgs a = base_args(g, w);
+    GArgs a = base_args(g, w, cfg);
     a.total_chunks = chunks;
     a.rch = (int32_t)rch;
     a.nq = 1;
-    const bool timed = ctx->profile != 0;
+    const bool timed = cfg.timed;
     tm_status s = launch(ctx, w, mod, mode, &a, stream, timed);
     if (s != TM_OK) return s;
     if (timed) {
@@ -264,6 +275,131 @@ tm_status run_single(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm
         if (hipEventElapsedTime(&ms, w->ev0, w->ev1) == hipSuccess && ms_acc) *ms_acc += ms;
     }
     return TM_OK;
+}
+
+// ------------------------------------------------------------------ autotuning
+//
+// Launch settings change the speed of a launch, never its result. With
+// TM_PARAM_AUTOTUNE on, the first count (or batch) of a key runs once under
+// each candidate setting, checks that every trial gives the same counts, and
+// keeps the fastest; later calls with the key reuse it. The key is the graph,
+// the kernel module, and power-of-two buckets of the largest delta (clamped to
+// the time span), of the root count and of the query count. The candidates
+// are the knobs the paper's hyper-parameter study varies, in this design's
+// terms (Appendix, impact of hyper-parameters): how much work a wavefront
+// takes at once and whether busy lanes hand work to idle ones.
+
+int bitlen64(int64_t x) { return x > 0 ? 64 - __builtin_clzll((unsigned long long)x) : 0; }
+
+std::string module_key(const tm_ctx *ctx, const tm_graph *g, const tmo::Plan &p) {
+    return "S" + std::to_string(g->key_bytes) + "b" + std::to_string(ctx->block) + ":" + p.key();
+}
+
+std::string tune_key(const tm_graph *g, const std::string &mod, int64_t delta, int64_t roots, int q) {
+    const int64_t span = g->m ? g->t_max - g->t_min : 0;
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "g%lld,%lld,%lld|d%d|r%d|q%d|", (long long)g->n, (long long)g->m,
+                  (long long)span, bitlen64(std::min(delta, span)), bitlen64(roots), bitlen64(q));
+    return std::string(buf) + mod;
+}
+
+std::vector<tmo::LaunchCfg> tune_candidates(const tm_ctx *ctx, int64_t roots) {
+    std::vector<tmo::LaunchCfg> out;
+    int64_t last_chunks = -1;
+    for (int64_t rch : {16, 64, 256, 1024}) {
+        const int64_t chunks = (roots + rch - 1) / rch;
+        if (chunks == last_chunks) continue;  // same split of the roots as the previous size
+        last_chunks = chunks;
+        for (int split : {0, 1}) {
+            tmo::LaunchCfg c;
+            c.rch = rch;
+            c.exact = true;
+            c.split = split;
+            c.split_min = ctx->split_min;
+            c.timed = true;
+            out.push_back(c);
+        }
+    }
+    return out;
+}
+
+// The tuned setting of `key`, if any.
+bool tune_lookup(tm_ctx *ctx, const std::string &key, tmo::LaunchCfg *c) {
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    auto it = ctx->tune.find(key);
+    if (it == ctx->tune.end()) return false;
+    c->rch = it->second.rch;
+    c->exact = true;
+    c->split = it->second.split;
+    c->split_min = it->second.split_min;
+    return true;
+}
+
+void note_launch(tm_ctx *ctx, const tmo::LaunchCfg &c, bool tuned, double ms, int launches) {
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
+    ctx->last_cfg = c;
+    ctx->last_tuned = tuned ? 1 : 0;
+    if (c.timed) {
+        ctx->last_ms = ms;
+        ctx->last_launches = launches;
+    }
+}
+
+// Run `once(cfg, &ms, &results)` under the setting for `key`: the tuned one,
+// else (autotuning on) every candidate in turn, else the context's defaults.
+// Reports the setting whose results are returned, whether it was tuned, and
+// its kernel time (when timed).
+template <class F>
+tm_status run_tuned(tm_ctx *ctx, const std::string &key, int64_t roots, F &&once, std::vector<uint64_t> *res,
+                    tmo::LaunchCfg *used, bool *tuned, double *ms_out) {
+    tmo::LaunchCfg cfg = default_cfg(ctx);
+    *tuned = false;
+    if (ctx->autotune && roots > 0) {
+        if (tune_lookup(ctx, key, &cfg)) {
+            *tuned = true;
+            cfg.timed = ctx->profile != 0;
+        } else {
+            std::vector<uint64_t> first;
+            double best = 0;
+            tmo::LaunchCfg best_c;
+            bool have = false;
+            for (const tmo::LaunchCfg &c : tune_candidates(ctx, roots)) {
+                double ms = 0;
+                std::vector<uint64_t> r;
+                tm_status st = once(c, &ms, &r);
+                if (st != TM_OK) return st;
+                if (!have) {
+                    first = r;
+                } else if (r != first) {
+                    return fail(TM_E_DEVICE, "autotuning trials disagree on a count");
+                }
+                if (!have || ms < best) {
+                    best = ms;
+                    best_c = c;
+                }
+                have = true;
+            }
+            if (have) {
+                std::lock_guard<std::mutex> lk(ctx->tune_mu);
+                tmo::TuneEntry e;
+                e.rch = best_c.rch;
+                e.split = best_c.split;
+                e.split_min = best_c.split_min;
+                e.ms = best;
+                ctx->tune[key] = e;
+            }
+            if (have) {
+                *used = best_c;
+                *tuned = true;
+                *ms_out = best;
+                *res = first;
+                return TM_OK;
+            }
+        }
+    }
+    *used = cfg;
+    *ms_out = 0;
+    return once(cfg, ms_out, res);
 }
 
 }  // namespace
@@ -345,6 +481,9 @@ tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t v) {
         if (v != 0 && v != 1) return fail(TM_E_INVALID, "tier must be 0 or 1");
         ctx->tier = (int)v;
         return TM_OK;
+    case TM_PARAM_AUTOTUNE:
+        ctx->autotune = v ? 1 : 0;
+        return TM_OK;
     default:
         return fail(TM_E_INVALID, "unknown parameter");
     }
@@ -360,8 +499,85 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *v) {
     case TM_PARAM_SPLIT: *v = ctx->split; return TM_OK;
     case TM_PARAM_SPLIT_MIN: *v = ctx->split_min; return TM_OK;
     case TM_PARAM_TIER: *v = ctx->tier; return TM_OK;
+    case TM_PARAM_AUTOTUNE: *v = ctx->autotune; return TM_OK;
     default: return fail(TM_E_INVALID, "unknown parameter");
     }
+}
+
+tm_status tm_last_launch(tm_ctx *ctx, int64_t *root_chunk, int32_t *split, int32_t *tuned) {
+    if (!ctx) return fail(TM_E_INVALID, "null context");
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
+    if (root_chunk) *root_chunk = ctx->last_cfg.rch;
+    if (split) *split = ctx->last_cfg.split;
+    if (tuned) *tuned = ctx->last_tuned;
+    return TM_OK;
+}
+
+tm_status tm_tune_save(tm_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(TM_E_INVALID, "null argument");
+    std::string text = "tmotif-tune 1\n";
+    {
+        std::lock_guard<std::mutex> lk(ctx->tune_mu);
+        char buf[128];
+        for (const auto &kv : ctx->tune) {
+            std::snprintf(buf, sizeof(buf), " %lld %d %lld %.6f\n", (long long)kv.second.rch, kv.second.split,
+                          (long long)kv.second.split_min, kv.second.ms);
+            text += kv.first + buf;
+        }
+    }
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(TM_E_INVALID, std::string("cannot write ") + path);
+    const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+    if (std::fclose(f) != 0 || !ok) return fail(TM_E_INVALID, std::string("cannot write ") + path);
+    return TM_OK;
+}
+
+tm_status tm_tune_load(tm_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(TM_E_INVALID, "null argument");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(TM_E_INVALID, std::string("cannot read ") + path);
+    std::string text;
+    char buf[65536];
+    size_t got_bytes;
+    while ((got_bytes = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got_bytes);
+    std::fclose(f);
+    const std::string bad = std::string("not a tune table: ") + path;
+    const std::string head = "tmotif-tune 1\n";
+    if (text.compare(0, head.size(), head) != 0) return fail(TM_E_INVALID, bad);
+    std::map<std::string, tmo::TuneEntry> got;
+    size_t pos = head.size();
+    while (pos < text.size()) {
+        size_t eol = text.find('\n', pos);
+        if (eol == std::string::npos) return fail(TM_E_INVALID, bad);
+        const std::string line = text.substr(pos, eol - pos);
+        pos = eol + 1;
+        const size_t sp = line.find(' ');
+        if (sp == 0 || sp == std::string::npos) return fail(TM_E_INVALID, bad);
+        long long rch = 0, smin = 0;
+        int split = 0;
+        double ms = 0;
+        char tail = 0;
+        if (std::sscanf(line.c_str() + sp, " %lld %d %lld %lf %c", &rch, &split, &smin, &ms, &tail) != 4 ||
+            rch < 1 || rch > (1 << 24) || (split != 0 && split != 1) || smin < 2)
+            return fail(TM_E_INVALID, bad);
+        tmo::TuneEntry e;
+        e.rch = rch;
+        e.split = split;
+        e.split_min = smin;
+        e.ms = ms;
+        got[line.substr(0, sp)] = e;
+    }
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    for (auto &kv : got) ctx->tune[kv.first] = kv.second;
+    return TM_OK;
+}
+
+tm_status tm_tune_clear(tm_ctx *ctx, int64_t *n_removed) {
+    if (!ctx) return fail(TM_E_INVALID, "null context");
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    if (n_removed) *n_removed = (int64_t)ctx->tune.size();
+    ctx->tune.clear();
+    return TM_OK;
 }
 
 tm_status tm_last_kernel_ms(tm_ctx *ctx, double *ms, int32_t *launches) {
@@ -640,24 +856,36 @@ tm_status tm_count(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_r
     if (!count_out) return fail(TM_E_INVALID, "count_out is null");
     DeviceGuard dg(ctx->device);
     std::shared_ptr<tmo::Module> mod;
-    if ((st = get_module(ctx, g, m, &mod)) != TM_OK) return st;
+    if ((st = get_module(ctx, g, m, ctx->tier, &mod)) != TM_OK) return st;
     WsLease lease(ctx);
     tm_ctx::Workspace *w = lease.w;
-    int64_t chunks = 0, r0 = 0;
+    int64_t r0, r1, chunks = 0;
+    root_ids(g, range, &r0, &r1);
+    auto once = [&](const tmo::LaunchCfg &c, double *ms, std::vector<uint64_t> *res) -> tm_status {
+        int64_t rr0 = 0;
+        tm_status s = run_single(ctx, g, m, range, stream, tmo::MODE_COUNT, w, mod.get(), c, &chunks, &rr0, ms);
+        if (s != TM_OK) return s;
+        HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+                "read count");
+        HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+                "read control words");
+        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        if (chunks && w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
+        res->assign(1, w->h_counts[0]);
+        return TM_OK;
+    };
+    const tmo::Plan gp = tmo::generic_plan(m->plan.l);
+    const std::string key = ctx->autotune ? tune_key(g, module_key(ctx, g, ctx->tier ? gp : m->plan), m->delta,
+                                                     r1 - r0, 1)
+                                          : std::string();
+    std::vector<uint64_t> res;
+    tmo::LaunchCfg used;
+    bool tuned = false;
     double ms = 0;
-    st = run_single(ctx, g, m, range, stream, tmo::MODE_COUNT, w, mod.get(), &chunks, &r0, &ms);
+    st = run_tuned(ctx, key, r1 - r0, once, &res, &used, &tuned, &ms);
     if (st != TM_OK) return st;
-    HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "read count");
-    HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
-            "read control words");
-    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
-    if (chunks && w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
-    if (ctx->profile) {
-        std::lock_guard<std::mutex> lk(ctx->prof_mu);
-        ctx->last_ms = ms;
-        ctx->last_launches = chunks ? 1 : 0;
-    }
-    *count_out = w->h_counts[0];
+    note_launch(ctx, used, tuned, ms, chunks ? 1 : 0);
+    *count_out = res[0];
     return TM_OK;
 }
 
@@ -668,11 +896,14 @@ tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const
     if (!stats_out) return fail(TM_E_INVALID, "stats_out is null");
     DeviceGuard dg(ctx->device);
     std::shared_ptr<tmo::Module> mod;
-    if ((st = get_module(ctx, g, m, &mod)) != TM_OK) return st;
+    if ((st = get_module(ctx, g, m, ctx->tier, &mod)) != TM_OK) return st;
     WsLease lease(ctx);
     tm_ctx::Workspace *w = lease.w;
     int64_t chunks = 0, r0 = 0;
-    st = run_single(ctx, g, m, range, stream, tmo::MODE_STATS, w, mod.get(), &chunks, &r0, nullptr);
+    tmo::LaunchCfg cfg = default_cfg(ctx);
+    cfg.split = 0;  // the counters describe the unsplit search
+    cfg.timed = false;
+    st = run_single(ctx, g, m, range, stream, tmo::MODE_STATS, w, mod.get(), cfg, &chunks, &r0, nullptr);
     if (st != TM_OK) return st;
     if (chunks == 0) HIP_TRY(tmo::dev_fill_u64(w->ctl, 0, tmo::CTL_WORDS, stream), "reset counters");
     HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
@@ -684,20 +915,28 @@ tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const
     return TM_OK;
 }
 
-tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
-                       hipStream_t stream, int64_t *d_out, uint64_t capacity, uint64_t *n_out) {
-    tm_status st = check_pair(ctx, g, m);
-    if (st != TM_OK) return st;
-    if (!n_out) return fail(TM_E_INVALID, "n_out is null");
-    if (capacity > 0 && !d_out) return fail(TM_E_INVALID, "d_out is null with capacity > 0");
+}  // extern "C"
+
+namespace tmo {
+
+tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range, int tier,
+                         hipStream_t stream, tm_ctx::Workspace *w, const RowAlloc &alloc, uint64_t *n_out,
+                         int64_t **rows_out) {
     DeviceGuard dg(ctx->device);
     std::shared_ptr<tmo::Module> mod;
-    if ((st = get_module(ctx, g, m, &mod)) != TM_OK) return st;
-    WsLease lease(ctx);
-    tm_ctx::Workspace *w = lease.w;
+    tm_status st;
+    if (rows_out) *rows_out = nullptr;
+    if ((st = get_module(ctx, g, m, tier, &mod)) != TM_OK) return st;
     int64_t r0, r1;
     root_ids(g, range, &r0, &r1);
-    const int64_t rch = ctx->root_chunk;
+    // the setting a count of this key was tuned to, else the defaults
+    tmo::LaunchCfg cfg = default_cfg(ctx);
+    bool tuned = false;
+    if (ctx->autotune) {
+        const tmo::Plan gp = tmo::generic_plan(m->plan.l);
+        tuned = tune_lookup(ctx, tune_key(g, module_key(ctx, g, tier ? gp : m->plan), m->delta, r1 - r0, 1), &cfg);
+    }
+    const int64_t rch = chunk_for(ctx, cfg, r1 - r0);  // the same split as run_single's pass
     const int64_t chunks = (r1 - r0 + rch - 1) / rch;
     HIP_TRY(ws_prepare(w, chunks, 1), "workspace");
     if (chunks == 0) {
@@ -708,7 +947,7 @@ tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const 
     HIP_TRY(tmo::dev_fill_u64(w->chunk_cnt, 0, chunks, stream), "reset chunk counts");
     int64_t c0 = 0, rr0 = 0;
     double ms = 0;
-    st = run_single(ctx, g, m, range, stream, tmo::MODE_ENUM_COUNT, w, mod.get(), &c0, &rr0, &ms);
+    st = run_single(ctx, g, m, range, stream, tmo::MODE_ENUM_COUNT, w, mod.get(), cfg, &c0, &rr0, &ms);
     if (st != TM_OK) return st;
     // exclusive scan -> per-chunk output offsets (one extra entry: the total)
     HIP_TRY(tmo::dev_fill_u64(w->chunk_cnt + chunks, 0, 1, stream), "scan tail");
@@ -734,20 +973,22 @@ tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const 
     if (total != w->h_counts[0]) return fail(TM_E_DEVICE, "enumeration pass 1 disagrees with its own total");
     *n_out = total;
     if (total == 0) return TM_OK;
-    if (capacity < total) {
-        return d_out ? fail(TM_E_CAPACITY, "enumeration buffer too small") : TM_OK;
-    }
+    uint64_t capacity = 0;
+    tm_status ast = TM_OK;
+    int64_t *d_out = alloc(total, &capacity, &ast);
+    if (!d_out || capacity < total) return ast;
+    if (rows_out) *rows_out = d_out;
     // pass 2: write rows; chunk_cnt is reused as the per-chunk write cursor
     HIP_TRY(tmo::dev_fill_u64(w->chunk_cnt, 0, chunks, stream), "reset cursors");
     HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload query");
     HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 1, stream), "reset count");
-    GArgs a = base_args(g, w);
+    GArgs a = base_args(g, w, cfg);
     a.total_chunks = chunks;
     a.rch = (int32_t)rch;
     a.nq = 1;
     a.out = d_out;
     a.capacity = capacity;
-    const bool timed = ctx->profile != 0;
+    const bool timed = cfg.timed;
     st = launch(ctx, w, mod.get(), tmo::MODE_ENUM_WRITE, &a, stream, timed);
     if (st != TM_OK) return st;
     HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
@@ -758,30 +999,23 @@ tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const 
     if (timed) {
         float k = 0.f;
         if (hipEventElapsedTime(&k, w->ev0, w->ev1) == hipSuccess) ms += k;
-        std::lock_guard<std::mutex> lk(ctx->prof_mu);
-        ctx->last_ms = ms;
-        ctx->last_launches = 2;
     }
+    note_launch(ctx, cfg, tuned, ms, 2);
     if (w->h_ctl[tmo::CTL_OVERFLOW] != 0 || w->h_counts[0] != total)
         return fail(TM_E_DEVICE, "enumeration pass 2 wrote a different number of rows than pass 1 counted");
     return TM_OK;
 }
 
-tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
-                         const tm_root_range *ranges, hipStream_t stream, uint64_t *counts_out) {
-    if (!ctx || !g || q < 0 || (q > 0 && (!motifs || !counts_out))) return fail(TM_E_INVALID, "bad argument");
-    if (q == 0) return TM_OK;
-    for (int i = 0; i < q; i++) {
-        tm_status st = check_pair(ctx, g, motifs[i]);
-        if (st != TM_OK) return st;
-    }
+tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
+                           const tm_root_range *ranges, int tier, hipStream_t stream, tm_ctx::Workspace *w,
+                           uint64_t *counts_out) {
     DeviceGuard dg(ctx->device);
     // one matcher per distinct structure, or with the generic tier one
     // table-driven matcher per motif length (a module that never recompiles)
     std::vector<const tmo::Plan *> plans;
     std::vector<int> fn(q);
     std::vector<tmo::Plan> gplans;
-    if (ctx->tier) {
+    if (tier) {
         for (int l = 1; l <= TM_MAX_EDGES; l++) gplans.push_back(tmo::generic_plan(l));
         for (auto &gp : gplans) plans.push_back(&gp);
         for (int i = 0; i < q; i++) fn[i] = motifs[i]->plan.l - 1;
@@ -800,47 +1034,120 @@ tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_mot
     std::string err;
     auto mod = ctx->compiler.get_batch(plans, g->key_bytes, ctx->block, &err);
     if (!mod) return fail(TM_E_COMPILE, err);
-    WsLease lease(ctx);
-    tm_ctx::Workspace *w = lease.w;
     HIP_TRY(ws_prepare(w, 0, q), "workspace");
-    const int64_t rch = ctx->root_chunk;
-    int64_t c0 = 0;
-    QArgs *h = (QArgs *)w->h_qa;
+    std::vector<int64_t> rlo(q), rhi(q);
+    int64_t roots = 0, dmax = 0;
     for (int i = 0; i < q; i++) {
-        int64_t r0, r1;
-        root_ids(g, ranges ? &ranges[i] : nullptr, &r0, &r1);
-        fill_qargs(g, motifs[i], r0, r1, c0, rch, fn[i], &h[i]);
-        c0 += h[i].nchunks;
+        root_ids(g, ranges ? &ranges[i] : nullptr, &rlo[i], &rhi[i]);
+        roots += rhi[i] - rlo[i];
+        dmax = std::max(dmax, motifs[i]->delta);
     }
-    HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, q * sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload queries");
-    HIP_TRY(tmo::dev_fill_u64(w->counts, 0, q, stream), "reset counts");
-    double ms = 0;
-    if (c0 > 0) {
-        GArgs a = base_args(g, w);
-        a.total_chunks = c0;
-        a.rch = (int32_t)rch;
-        a.nq = q;
-        const bool timed = ctx->profile != 0;
-        tm_status st = launch(ctx, w, mod.get(), tmo::MODE_COUNT, &a, stream, timed);
-        if (st != TM_OK) return st;
-        if (timed) {
-            HIP_TRY(hipEventSynchronize(w->ev1), "hipEventSynchronize");
-            float k = 0.f;
-            if (hipEventElapsedTime(&k, w->ev0, w->ev1) == hipSuccess) ms = k;
+    int64_t c0 = 0;
+    auto once = [&](const tmo::LaunchCfg &c, double *ms, std::vector<uint64_t> *res) -> tm_status {
+        const int64_t rch = chunk_for(ctx, c, roots);
+        QArgs *h = (QArgs *)w->h_qa;
+        c0 = 0;
+        for (int i = 0; i < q; i++) {
+            fill_qargs(g, motifs[i], rlo[i], rhi[i], c0, rch, fn[i], &h[i]);
+            c0 += h[i].nchunks;
         }
+        HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, q * sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload queries");
+        HIP_TRY(tmo::dev_fill_u64(w->counts, 0, q, stream), "reset counts");
+        if (c0 > 0) {
+            GArgs a = base_args(g, w, c);
+            a.total_chunks = c0;
+            a.rch = (int32_t)rch;
+            a.nq = q;
+            tm_status st = launch(ctx, w, mod.get(), tmo::MODE_COUNT, &a, stream, c.timed);
+            if (st != TM_OK) return st;
+            if (c.timed) {
+                HIP_TRY(hipEventSynchronize(w->ev1), "hipEventSynchronize");
+                float k = 0.f;
+                if (hipEventElapsedTime(&k, w->ev0, w->ev1) == hipSuccess) *ms = k;
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, q * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+                "read counts");
+        HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+                "read control words");
+        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        if (c0 > 0 && w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
+        res->assign(w->h_counts, w->h_counts + q);
+        return TM_OK;
+    };
+    std::string mkey;
+    if (ctx->autotune) {
+        mkey = "B" + std::to_string(g->key_bytes) + "b" + std::to_string(ctx->block) + ":";
+        for (auto *p : plans) mkey += p->key() + "|";
     }
-    HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, q * sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "read counts");
-    HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
-            "read control words");
-    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
-    if (c0 > 0 && w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
-    if (ctx->profile) {
-        std::lock_guard<std::mutex> lk(ctx->prof_mu);
-        ctx->last_ms = ms;
-        ctx->last_launches = c0 > 0 ? 1 : 0;
-    }
-    for (int i = 0; i < q; i++) counts_out[i] = w->h_counts[i];
+    const std::string key = ctx->autotune ? tune_key(g, mkey, dmax, roots, q) : std::string();
+    std::vector<uint64_t> res;
+    tmo::LaunchCfg used;
+    bool tuned = false;
+    double ms = 0;
+    tm_status st = run_tuned(ctx, key, roots, once, &res, &used, &tuned, &ms);
+    if (st != TM_OK) return st;
+    note_launch(ctx, used, tuned, ms, c0 > 0 ? 1 : 0);
+    for (int i = 0; i < q; i++) counts_out[i] = res[i];
     return TM_OK;
+}
+
+tm_ctx::Workspace *ws_acquire(tm_ctx *ctx) {
+    std::lock_guard<std::mutex> lk(ctx->ws_mu);
+    for (auto &p : ctx->ws)
+        if (!p->busy) {
+            p->busy = true;
+            return p.get();
+        }
+    ctx->ws.emplace_back(new tm_ctx::Workspace());
+    ctx->ws.back()->busy = true;
+    return ctx->ws.back().get();
+}
+
+void ws_release(tm_ctx *ctx, tm_ctx::Workspace *w) {
+    std::lock_guard<std::mutex> lk(ctx->ws_mu);
+    w->busy = false;
+}
+
+tm_status set_error(tm_status st, const std::string &msg) { return fail(st, msg); }
+
+tm_status check_query(tm_ctx *ctx, const tm_graph *g, const tm_motif *m) { return check_pair(ctx, g, m); }
+
+void resolve_roots(const tm_graph *g, const tm_root_range *range, int64_t *r0, int64_t *r1) {
+    root_ids(g, range, r0, r1);
+}
+
+}  // namespace tmo
+
+extern "C" {
+
+tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
+                       hipStream_t stream, int64_t *d_out, uint64_t capacity, uint64_t *n_out) {
+    tm_status st = check_pair(ctx, g, m);
+    if (st != TM_OK) return st;
+    if (!n_out) return fail(TM_E_INVALID, "n_out is null");
+    if (capacity > 0 && !d_out) return fail(TM_E_INVALID, "d_out is null with capacity > 0");
+    // the caller's buffer, if it holds every row; a size query (no buffer) is not an error
+    tmo::RowAlloc alloc = [&](uint64_t total, uint64_t *cap, tm_status *ast) -> int64_t * {
+        *cap = capacity;
+        if (capacity >= total) return d_out;
+        *ast = d_out ? fail(TM_E_CAPACITY, "enumeration buffer too small") : TM_OK;
+        return nullptr;
+    };
+    WsLease lease(ctx);
+    return tmo::enumerate_impl(ctx, g, m, range, ctx->tier, stream, lease.w, alloc, n_out, nullptr);
+}
+
+tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
+                         const tm_root_range *ranges, hipStream_t stream, uint64_t *counts_out) {
+    if (!ctx || !g || q < 0 || (q > 0 && (!motifs || !counts_out))) return fail(TM_E_INVALID, "bad argument");
+    if (q == 0) return TM_OK;
+    for (int i = 0; i < q; i++) {
+        tm_status st = check_pair(ctx, g, motifs[i]);
+        if (st != TM_OK) return st;
+    }
+    WsLease lease(ctx);
+    return tmo::count_batch_impl(ctx, g, q, motifs, ranges, ctx->tier, stream, lease.w, counts_out);
 }
 
 }  // extern "C"

@@ -1182,38 +1182,37 @@ static bool compile_module(const std::string &src, int block, int nmodes, Module
     return true;
 }
 
-std::shared_ptr<Module> Compiler::get(const Plan &p, int key_bytes, int block, std::string *err) {
-    std::string key = "S" + std::to_string(key_bytes) + "b" + std::to_string(block) + ":" + p.key();
+std::shared_ptr<Module> Compiler::lookup_or_build(const std::string &key, int block, int nmodes,
+                                                  const std::function<std::string()> &make, std::string *err) {
     {
-        std::lock_guard<std::mutex> lk(mu);
-        auto it = cache.find(key);
-        if (it != cache.end()) return it->second;
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            auto it = cache.find(key);
+            if (it != cache.end()) return it->second;
+            if (!inflight.count(key)) break;
+            cv.wait(lk);  // another thread is compiling this key; a failed compile is retried here
+        }
+        inflight.insert(key);
     }
     auto m = std::make_shared<Module>();
-    if (!compile_module(generate_source(p, key_bytes, block), block, 4, m.get(), err)) return nullptr;
+    const bool ok = compile_module(make(), block, nmodes, m.get(), err);
     std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-    cache[key] = m;
-    return m;
+    inflight.erase(key);
+    if (ok) cache[key] = m;
+    cv.notify_all();
+    return ok ? m : nullptr;
+}
+
+std::shared_ptr<Module> Compiler::get(const Plan &p, int key_bytes, int block, std::string *err) {
+    const std::string key = "S" + std::to_string(key_bytes) + "b" + std::to_string(block) + ":" + p.key();
+    return lookup_or_build(key, block, 4, [&] { return generate_source(p, key_bytes, block); }, err);
 }
 
 std::shared_ptr<Module> Compiler::get_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
                                             std::string *err) {
     std::string key = "B" + std::to_string(key_bytes) + "b" + std::to_string(block) + ":";
     for (auto *p : plans) key += p->key() + "|";
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        auto it = cache.find(key);
-        if (it != cache.end()) return it->second;
-    }
-    auto m = std::make_shared<Module>();
-    if (!compile_module(generate_batch_source(plans, key_bytes, block), block, 1, m.get(), err)) return nullptr;
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-    cache[key] = m;
-    return m;
+    return lookup_or_build(key, block, 1, [&] { return generate_batch_source(plans, key_bytes, block); }, err);
 }
 
 }  // namespace tmo

@@ -4,9 +4,12 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
+#include <condition_variable>
 #include <string>
 #include <vector>
 
@@ -105,11 +108,17 @@ struct Graph;
 // Module cache key: plan structure + timestamp width + block size.
 struct Compiler {
     std::mutex mu;
+    std::condition_variable cv;                // signalled when a compile ends
     std::map<std::string, std::shared_ptr<Module>> cache;
+    std::set<std::string> inflight;            // keys some thread is compiling now
     int device = 0;
     std::shared_ptr<Module> get(const Plan &p, int key_bytes, int block, std::string *err);
     std::shared_ptr<Module> get_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
                                       std::string *err);
+    // the cached module for `key`, else one built by `make` (which compiles
+    // `nmodes` kernels); concurrent callers of one key share a single compile
+    std::shared_ptr<Module> lookup_or_build(const std::string &key, int block, int nmodes,
+                                            const std::function<std::string()> &make, std::string *err);
 };
 
 std::string generate_source(const Plan &p, int key_bytes, int block);
@@ -134,6 +143,27 @@ hipError_t dev_exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, 
 
 }  // namespace tmo
 
+namespace tmo {
+
+// Launch settings of one mining launch; none of them changes a result.
+struct LaunchCfg {
+    int64_t rch = 256;      // roots per chunk (an upper bound unless `exact`)
+    bool exact = false;     // use rch as is instead of shrinking it for small ranges
+    int split = 0;          // hand pending windows of busy lanes to idle lanes / wavefronts
+    int64_t split_min = 2;  // smallest pending window worth splitting
+    bool timed = false;     // record HIP events around the launch
+};
+
+// The setting the autotuner kept for one key, and its kernel time.
+struct TuneEntry {
+    int64_t rch = 0;
+    int split = 0;
+    int64_t split_min = 2;
+    double ms = 0.0;
+};
+
+}  // namespace tmo
+
 struct tm_ctx {
     int device = 0;
     int num_cus = 0;
@@ -144,6 +174,9 @@ struct tm_ctx {
     int split = 0;
     int64_t split_min = 2;
     int tier = 0;  // 0: kernels specialised per motif structure, 1: generic per motif length
+    int autotune = 0;
+    std::mutex tune_mu;
+    std::map<std::string, tmo::TuneEntry> tune;  // key: graph, module, delta and size buckets
     tmo::Compiler compiler;
     std::mutex ws_mu;
     struct Workspace {
@@ -169,6 +202,8 @@ struct tm_ctx {
     std::mutex prof_mu;
     double last_ms = 0.0;
     int last_launches = 0;
+    tmo::LaunchCfg last_cfg;  // setting of the last mining launch
+    int last_tuned = 0;       // 1: it came from the tune table
 };
 
 struct tm_graph {
@@ -199,3 +234,26 @@ struct tm_motif {
     int32_t pred_op = 0;
     float theta = 0.0f;
 };
+
+namespace tmo {
+
+// After the counting pass of an enumeration: given the total number of rows,
+// return a device buffer and its capacity in rows, or nullptr (with *st) to
+// stop after reporting the total.
+using RowAlloc = std::function<int64_t *(uint64_t rows, uint64_t *capacity, tm_status *st)>;
+
+// Blocking building blocks shared by the C entry points and the server; each
+// runs on `stream` with an explicit workspace and kernel tier.
+tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range, int tier,
+                         hipStream_t stream, tm_ctx::Workspace *w, const RowAlloc &alloc, uint64_t *n_out,
+                         int64_t **rows_out);
+tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
+                           const tm_root_range *ranges, int tier, hipStream_t stream, tm_ctx::Workspace *w,
+                           uint64_t *counts_out);
+tm_ctx::Workspace *ws_acquire(tm_ctx *ctx);
+void ws_release(tm_ctx *ctx, tm_ctx::Workspace *w);
+tm_status set_error(tm_status st, const std::string &msg);
+tm_status check_query(tm_ctx *ctx, const tm_graph *g, const tm_motif *m);
+void resolve_roots(const tm_graph *g, const tm_root_range *range, int64_t *r0, int64_t *r1);
+
+}  // namespace tmo

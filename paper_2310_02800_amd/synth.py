@@ -273,10 +273,10 @@ def batch_queries(seed: int = 3, q: int = 64) -> List[Motif]:
 
 
 def serve_queries(t_min: int, t_max: int, seed: int = 4, q: int = 10_000,
-                  enum_frac: float = 0.1) -> List[Query]:
-    """A query stream: motifs as in ``batch_queries``, a root time range
-    covering 1-100% of the span, 10% enumerate requests, unit-rate Poisson
-    arrival times."""
+                  enum_frac: float = 0.1, delta_range=(600, 86400)) -> List[Query]:
+    """A query stream: motifs as in ``batch_queries`` (delta log-uniform over
+    ``delta_range``), a root time range covering 1-100% of the span, 10%
+    enumerate requests, unit-rate Poisson arrival times."""
     rng = np.random.Generator(np.random.PCG64(seed))
     span = t_max - t_min
     arrivals = np.cumsum(rng.standard_exponential(q))
@@ -285,7 +285,7 @@ def serve_queries(t_min: int, t_max: int, seed: int = 4, q: int = 10_000,
         l = int(rng.integers(3, 7))
         k = int(rng.integers(3, min(5, l + 1) + 1))
         edges = random_motif(rng, l, k)
-        mot = Motif(edges=edges, delta=_log_uniform_int(rng, 600, 86400))
+        mot = Motif(edges=edges, delta=_log_uniform_int(rng, delta_range[0], delta_range[1]))
         if i % 2 == 1:
             mot.pred_edge = int(rng.integers(0, l))
             mot.pred_op = PRED_GE if rng.random() < 0.5 else PRED_LT
