@@ -10,10 +10,16 @@ delta = 3600 s and 86400 s. A step is one pass over all six queries.
 * plain form: one tm_count call per query, each synchronised.
 
 Graph ingest and kernel compilation happen once before timing and are
-reported separately. The roofline entry divides the method's algorithmic
+reported separately. Launch settings are autotuned per query key (the trials
+run during warmup). The roofline entry divides the method's algorithmic
 bytes per launch (from the work counters) by the measured average duration of
 the mining kernel. The CPU baseline is the oracle timed on a bounded root-time
 slice of the same workload on this host.
+
+Beside the headline, "batch64" measures the batched workload on the small
+power-law graph (n = 1,000, m = 20,000): 64 random motif queries (3-6 edges,
+half with a weight predicate) as one persistent launch against 64
+synchronised single-query launches.
 """
 from __future__ import annotations
 
@@ -23,6 +29,7 @@ import json
 import os
 import statistics
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -77,6 +84,205 @@ def cpu_baseline(graph, motifs, budget_s: float):
             "seconds": round(dt, 3)}
 
 
+def bench_batch64(ctx, args, stream):
+    """64 random queries on the small graph: one persistent launch against 64
+    synchronised single-query launches (same autotuning for both)."""
+    import torch
+    from paper_2310_02800_amd import synth
+    g = synth.tiny_graph(0)
+    dg = ctx.load_synth(g)
+    qs = synth.batch_queries()
+    handles = [ctx.compile(m) for m in qs]
+    want = ctx.count_batch(dg, handles, stream=stream)  # compiles and tunes
+    for _ in range(args.warmup):
+        plain = [ctx.count(dg, h, stream=stream) for h in handles]
+        ctx.count_batch(dg, handles, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain = [ctx.count(dg, h, stream=stream) for h in handles]
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        got = ctx.count_batch(dg, handles, stream=stream)
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - t0) / args.steps
+    setting = ctx.last_launch()
+    assert got == want == plain, "batched and plain counts differ"
+    inst = sum(want)
+    log(f"batch64: plain {plain_s * 1e3:.2f} ms, batched {batch_s * 1e3:.2f} ms")
+    return {"workload": "power-law graph n=1000 m=20000 (Chung-Lu exponent 2.1, times in [0,1e6)); 64 random "
+                        "motifs, 3-6 edges, 3-5 nodes, delta log-uniform in [600, 86400], odd ones with a weight "
+                        "predicate",
+            "instances": inst, "plain_ms": plain_s * 1e3, "batched_ms": batch_s * 1e3,
+            "plain_value": inst / plain_s, "batched_value": inst / batch_s, "unit": "instances/s",
+            "speedup": plain_s / batch_s,
+            "batched_launch": {"root_chunk": setting[0], "split": setting[1], "tuned": setting[2]}}
+
+
+def rows_checksum(rows):
+    """Order-independent checksum of enumeration rows (device int64 [n, l])."""
+    import torch
+    if rows is None or rows.shape[0] == 0:
+        return 0
+    k = torch.tensor([0x9E3779B97F4A7C15 - (1 << 64), 0x2545F4914F6CDD1D, 0x5851F42D4C957F2D,
+                      0x14057B7EF767814F, 0x27BB2EE687B0B0FD, 0x1B03738712FAD5C9, 0x62A9D9ED799705F5,
+                      0x3C6EF372FE94F82B][:rows.shape[1]], dtype=torch.int64, device=rows.device)
+    v = (rows * k).sum(dim=1)
+    v = v ^ (v >> 29)
+    return int(v.sum().item())
+
+
+def bench_serve(ctx, dg, g, args):
+    """The served workload: a stream of random motif queries over the resident
+    wiki-shaped graph (3-6 edges, delta log-uniform in [600, 86400], root time
+    range covering 1-100% of the span, 10% enumerations), first one query at a
+    time (plain), then through the continuous-batching server with Poisson
+    arrivals at 0.7x the plain capacity, and once more with every query
+    submitted at once (served capacity). Both forms use the table-driven
+    kernels and the same per-query work budget."""
+    import numpy as np
+    import torch
+    from paper_2310_02800_amd import _native as N
+    from paper_2310_02800_amd import api, synth
+    dev = torch.device(f"cuda:{ctx.device}")
+    t_min, t_max = int(g.t.min()), int(g.t.max())
+    qs = synth.serve_queries(t_min, t_max)[:args.serve_queries]
+    n = len(qs)
+    budget = args.serve_budget
+    pool_bytes = int(args.serve_pool_gib * (1 << 30))
+    old = {p: ctx.get_param(p) for p in (N.TM_PARAM_TIER, N.TM_PARAM_PROFILE, N.TM_PARAM_AUTOTUNE,
+                                         N.TM_PARAM_WORK_BUDGET)}
+    ctx.set_param(N.TM_PARAM_TIER, 1)
+    ctx.set_param(N.TM_PARAM_PROFILE, 0)
+    ctx.set_param(N.TM_PARAM_AUTOTUNE, 0)
+    ctx.set_param(N.TM_PARAM_WORK_BUDGET, budget)
+    try:
+        handles = [ctx.compile(q.motif) for q in qs]
+        pool = torch.empty(pool_bytes // 8, dtype=torch.int64, device=dev)
+        plain = []  # (status, count, checksum or None, service seconds)
+        stream = torch.cuda.current_stream(dev)
+        # warm the table-driven modules (one per motif length)
+        for l in sorted({q.motif.l for q in qs}):
+            i = next(j for j, q in enumerate(qs) if q.motif.l == l)
+            try:
+                ctx.count(dg, handles[i], t_lo=qs[i].t_lo, t_hi=qs[i].t_lo)
+            except N.NativeError:
+                pass
+        torch.cuda.synchronize()
+        log(f"serve: plain pass over {n} queries")
+        t_all = time.perf_counter()
+        for i, (q, h) in enumerate(zip(qs, handles)):
+            t0 = time.perf_counter()
+            st, c, chk = N.TM_OK, 0, None
+            try:
+                if q.enumerate:
+                    l = q.motif.l
+                    st, c = ctx.enumerate_into(dg, h, pool.data_ptr(), pool.numel() // l, t_lo=q.t_lo,
+                                               t_hi=q.t_hi, stream=stream)
+                    if st == N.TM_OK:
+                        chk = rows_checksum(pool[:c * l].view(c, l))
+                else:
+                    c = ctx.count(dg, h, t_lo=q.t_lo, t_hi=q.t_hi, stream=stream)
+            except N.NativeError as e:
+                st = e.status
+            plain.append((st, c, chk, time.perf_counter() - t0))
+            if i % 200 == 199:
+                log(f"serve: plain {i + 1}/{n} after {time.perf_counter() - t_all:.1f} s")
+        del pool
+        torch.cuda.synchronize()
+        svc = np.array([p[3] for p in plain])
+        cap_plain = n / svc.sum()
+        rate = 0.7 * cap_plain
+        arrivals = np.array([q.arrival for q in qs]) / rate  # unit-rate Poisson times scaled to the rate
+        # plain at the same arrivals: one FIFO worker, exact replay of the measured service times
+        done, lat_plain = 0.0, []
+        for a, sv in zip(arrivals, svc):
+            done = max(done, a) + sv
+            lat_plain.append(done - a)
+
+        def serve(arr_s):
+            srv = api.Server(ctx, dg, stream_slots=args.serve_slots, max_batch=args.serve_batch,
+                             enum_pool_bytes=pool_bytes, tier=1, work_budget=budget)
+            res = {}
+            sched = {}
+            try:
+                t_base = time.monotonic_ns() + 20_000_000
+
+                def producer():
+                    for i, q in enumerate(qs):
+                        due = t_base + int(arr_s[i] * 1e9)
+                        while True:
+                            now = time.monotonic_ns()
+                            if now >= due:
+                                break
+                            time.sleep(min((due - now) / 1e9, 0.002))
+                        sched[i] = due
+                        srv.submit(q.motif, q.t_lo, q.t_hi, enumerate=q.enumerate, tag=i)
+
+                th = threading.Thread(target=producer)
+                th.start()
+                t_last = time.perf_counter()
+                deadline = time.perf_counter() + 60 + 3 * (float(arr_s[-1]) + float(svc.sum()))
+                while len(res) < n:
+                    if time.perf_counter() > deadline:
+                        raise RuntimeError(f"server returned {len(res)} of {n} results before the deadline")
+                    for r in srv.poll(256, timeout_ms=100):
+                        rows = srv.rows(r) if r["rows"] else None
+                        res[r["tag"]] = (r, rows_checksum(rows) if rows is not None else None)
+                        srv.release(r["ticket"])
+                    if time.perf_counter() - t_last > 10:
+                        t_last = time.perf_counter()
+                        log(f"serve: {len(res)}/{n} results")
+                th.join()
+            finally:
+                srv.stop()
+            t0 = min(sched.values())
+            t1 = max(r["t_done_ns"] for r, _ in res.values())
+            lat = np.array([(res[i][0]["t_done_ns"] - sched[i]) / 1e9 for i in range(n)])
+            return res, lat, (t1 - t0) / 1e9
+
+        log(f"serve: served at {rate:.1f} queries/s")
+        res, lat_served, span_s = serve(arrivals)
+        log("serve: served capacity (all submitted at once)")
+        res_f, _, span_f = serve(np.zeros(n))
+        # agreement: every query that both forms finished
+        both, agree = 0, True
+        for i in range(n):
+            for rr in (res, res_f):
+                r, chk = rr[i]
+                if r["status"] == plain[i][0] and r["status"] in (N.TM_OK, N.TM_E_CAPACITY):
+                    both += 1
+                    if r["count"] != plain[i][1] or (qs[i].enumerate and r["status"] == N.TM_OK
+                                                     and chk != plain[i][2]):
+                        agree = False
+        assert agree, "served and plain results differ"
+        ok = [i for i in range(n) if res[i][0]["status"] == N.TM_OK]
+        inst = sum(res[i][0]["count"] for i in ok)
+        pct = lambda a, p: 1e3 * float(np.percentile(a, p))
+        return {
+            "workload": f"first {n} queries of the 10,000-query stream (seed 4) on the wiki-shaped graph; "
+                        "motifs with 3-6 edges and 3-5 nodes, delta log-uniform in [600, 86400], root range "
+                        "1-100% of the span, 10% enumerations",
+            "queries": n, "work_budget_steps": budget,
+            "cancelled": {"plain": sum(1 for p in plain if p[0] == N.TM_E_CANCELLED),
+                          "served": sum(1 for r, _ in res.values() if r["status"] == N.TM_E_CANCELLED)},
+            "over_pool": sum(1 for p in plain if p[0] == N.TM_E_CAPACITY),
+            "plain": {"capacity_qps": cap_plain, "service_ms": {"p50": pct(svc, 50), "p99": pct(svc, 99)},
+                      "latency_ms_at_rate": {"p50": pct(lat_plain, 50), "p99": pct(lat_plain, 99)},
+                      "instances_per_s": sum(p[1] for p in plain if p[0] == N.TM_OK) / svc.sum()},
+            "served": {"rate_qps": rate, "throughput_qps": len(ok) / span_s, "instances_per_s": inst / span_s,
+                       "latency_ms": {"p50": pct(lat_served, 50), "p99": pct(lat_served, 99)},
+                       "capacity_qps": n / span_f, "slots": args.serve_slots, "max_batch": args.serve_batch},
+            "capacity_vs_plain": (n / span_f) / cap_plain,
+            "results_compared": both, "agree": agree,
+        }
+    finally:
+        for p, v in old.items():
+            ctx.set_param(p, v)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +293,16 @@ def main():
     ap.add_argument("--plain-only", action="store_true", help="time only the plain form")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, copy 1 GiB once (a known-size kernel for scaling HBM byte counters)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default launch settings")
+    ap.add_argument("--tune-table", default=None,
+                    help="load launch settings from this file if it exists, save them there at the end")
+    ap.add_argument("--no-batch64", action="store_true", help="skip the 64-query batch on the small graph")
+    ap.add_argument("--serve-queries", type=int, default=1000,
+                    help="queries of the served stream to run (0 = skip; the full stream has 10,000)")
+    ap.add_argument("--serve-budget", type=int, default=1 << 31, help="work budget per served query (steps)")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-batch", type=int, default=64)
+    ap.add_argument("--serve-pool-gib", type=float, default=8.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the method shards by root-time "
@@ -111,6 +327,9 @@ def main():
 
     ctx = api.Context(0)
     ctx.set_param(N.TM_PARAM_PROFILE, 1)
+    ctx.set_param(N.TM_PARAM_AUTOTUNE, 0 if args.no_autotune else 1)
+    if args.tune_table and os.path.exists(args.tune_table):
+        ctx.tune_load(args.tune_table)
     t0 = time.perf_counter()
     dg = ctx.load_synth(g)
     torch.cuda.synchronize()
@@ -121,8 +340,9 @@ def main():
     handles = [ctx.compile(m) for m in motifs]
     compile_single_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    counts_b = ctx.count_batch(dg, handles, stream=stream)  # compiles the batched module
+    counts_b = ctx.count_batch(dg, handles, stream=stream)  # compiles (and tunes) the batched module
     compile_batch_s = time.perf_counter() - t0
+    batch_setting = ctx.last_launch()
     log(f"compiled: single {compile_single_s:.2f} s, batch {compile_batch_s:.2f} s")
 
     # work counters (untimed) for the byte model
@@ -175,6 +395,7 @@ def main():
         torch.cuda.synchronize()
         batch_s = (time.perf_counter() - t0) / args.steps
         assert got == counts
+        batch_setting = ctx.last_launch()
         log(f"batched: {batch_s * 1e3:.2f} ms/step")
         result_ms = batch_s * 1e3
         value = total_instances / batch_s
@@ -216,12 +437,14 @@ def main():
         "vs_plain": (plain_s * 1e3) / result_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "tm_count", "avg_launch_ms": avg_launch_ms,
+                     "kernel": "tm_count_batch" if form == "batched" else "tm_count", "avg_launch_ms": avg_launch_ms,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "setup": {"generate_s": round(gen_s, 2), "load_graph_s": round(load_s, 3),
                   "compile_single_s": round(compile_single_s, 2), "compile_batch_s": round(compile_batch_s, 2),
                   "kernel_source_hash": src_hash},
         "per_query": [{"edges": m.edges, "delta": m.delta, "count": c} for m, c in zip(motifs, counts)],
+        "launch": {"autotune": not args.no_autotune, "root_chunk": batch_setting[0], "split": batch_setting[1],
+                   "tuned": batch_setting[2]},
     }
     if args.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
@@ -231,6 +454,12 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
+    if not args.no_batch64:
+        out["batch64"] = bench_batch64(ctx, args, stream)
+    if args.serve_queries > 0:
+        out["serve"] = bench_serve(ctx, dg, g, args)
+    if args.tune_table:
+        ctx.tune_save(args.tune_table)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(g, motifs, args.cpu_budget)

@@ -51,7 +51,7 @@ enum {
     TM_E_CAPACITY = 5,    /* enumeration buffer too small; the total is still written */
     TM_E_UNSUPPORTED = 6, /* e.g. more than 8 motif edges */
     TM_E_BUSY = 7,        /* server admission queue full */
-    TM_E_CANCELLED = 8    /* query cancelled */
+    TM_E_CANCELLED = 8    /* query stopped: over its work budget, or the server is stopping */
 };
 
 /* Edge-attribute predicate operators: w(e_j) OP theta. */
@@ -73,7 +73,9 @@ int32_t tm_version(void);
 
 /* ------------------------------------------------------------------ context
  * A context binds one GPU (HIP device ordinal `device`) and owns the compiled
- * motif kernels and the internal work buffers. */
+ * motif kernels and the internal work buffers. tm_destroy frees those; graphs
+ * and motifs of the context are freed by their own calls, before or after
+ * tm_destroy (after it, freeing is the only valid use of them). */
 tm_status tm_create(int32_t device, tm_ctx **out);
 void tm_destroy(tm_ctx *ctx);
 
@@ -94,6 +96,16 @@ void tm_destroy(tm_ctx *ctx);
  *                          compilation per structure)
  *   TM_PARAM_AUTOTUNE      1 = pick root chunk and splitting per key by measurement
  *                          (see tm_tune_save); 0 (default) = use the values above
+ *   TM_PARAM_WORK_BUDGET   most wavefront loop steps (one memory step of up to 64
+ *                          lanes each) one query may use in tm_count, tm_count_batch
+ *                          and the counting pass of tm_enumerate; past it the query
+ *                          stops with TM_E_CANCELLED and no result. Checked every
+ *                          1024 steps of each wavefront, so a query may run up to
+ *                          1024 steps per wavefront past the budget, and one within
+ *                          that margin may or may not be cancelled. 0 (default) =
+ *                          no limit. This plays the role of the paper's abort signal,
+ *                          checked every fixed number of iterations (Sec. 5.2.2),
+ *                          except that the query ends instead of being resumed.
  */
 enum {
     TM_PARAM_BLOCK = 1,
@@ -103,7 +115,8 @@ enum {
     TM_PARAM_SPLIT = 6,
     TM_PARAM_SPLIT_MIN = 7,
     TM_PARAM_TIER = 8,
-    TM_PARAM_AUTOTUNE = 9
+    TM_PARAM_AUTOTUNE = 9,
+    TM_PARAM_WORK_BUDGET = 10
 };
 tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t value);
 tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
@@ -248,7 +261,8 @@ typedef struct {
  * on `stream` (0 = the null stream) and the call returns after it finished.
  * count_out: host uint64. Errors: TM_E_INVALID (a predicate on a graph
  * without weights, graph and motif from different contexts), TM_E_DEVICE,
- * TM_E_OOM, TM_E_COMPILE. */
+ * TM_E_OOM, TM_E_COMPILE, TM_E_CANCELLED (over TM_PARAM_WORK_BUDGET; count_out
+ * not written). */
 tm_status tm_count(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
                    hipStream_t stream, uint64_t *count_out);
 
@@ -263,8 +277,10 @@ tm_status tm_count(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_r
  *              TM_OK and TM_E_CAPACITY)
  * Rows are grouped by root chunk (chunk j of C holds the roots j, j+C, j+2C,
  * ... of the range, C set by the range size and TM_PARAM_ROOT_CHUNK); the
- * order of chunks is fixed, the order inside a chunk is unspecified. With capacity < total, returns TM_E_CAPACITY and leaves
- * d_out unspecified. */
+ * order of chunks is fixed, the order inside a chunk is unspecified. With
+ * capacity < total, returns TM_E_CAPACITY and leaves d_out unspecified. A
+ * counting pass over TM_PARAM_WORK_BUDGET returns TM_E_CANCELLED (n_out not
+ * written, d_out untouched). */
 tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
                        hipStream_t stream, int64_t *d_out, uint64_t capacity, uint64_t *n_out);
 
@@ -279,7 +295,9 @@ tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const
 
 /* Batched count: q queries (motifs[i] with ranges[i], ranges may be NULL) in
  * one persistent launch; work items (query, root chunk) are drawn from one
- * device queue. counts_out: host uint64[q]. Blocking. */
+ * device queue. counts_out: host uint64[q]. Blocking. TM_PARAM_WORK_BUDGET
+ * applies to each query on its own: a query over it gets count UINT64_MAX and
+ * the call returns TM_E_CANCELLED; the other counts are exact. */
 tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
                          const tm_root_range *ranges, hipStream_t stream, uint64_t *counts_out);
 
@@ -304,6 +322,7 @@ typedef struct {
     int64_t enum_pool_bytes;  /* device memory for enumeration rows (>= 0) */
     int32_t queue_capacity;   /* pending queries before TM_E_BUSY (>= 1) */
     int32_t tier;             /* kernel tier, as TM_PARAM_TIER */
+    int64_t work_budget;      /* default work budget of a query, as TM_PARAM_WORK_BUDGET (0 = none) */
     const char *tune_path;    /* NULL, or a tune table (tm_tune_save) merged at start if the
                                  file exists and written back at stop; launches are tuned
                                  when the context has TM_PARAM_AUTOTUNE = 1 */
@@ -315,6 +334,8 @@ typedef struct {
     int32_t has_range;
     int32_t enumerate;        /* 0 = count, 1 = enumerate */
     uint64_t tag;             /* returned with the result */
+    int64_t work_budget;      /* as TM_PARAM_WORK_BUDGET; 0 = the server's default; over it
+                                 the result has status TM_E_CANCELLED */
 } tm_query;
 
 typedef struct {
@@ -327,7 +348,8 @@ typedef struct {
     int64_t t_arrival_ns, t_admit_ns, t_launch_ns, t_done_ns;
 } tm_result;
 
-/* Start serving graph g of ctx. The graph must outlive the server. Errors:
+/* Start serving graph g of ctx. The graph and the context must outlive the
+ * server (stop it before destroying either). Errors:
  * TM_E_INVALID (configuration out of range), TM_E_OOM (pool). */
 tm_status tm_server_start(tm_ctx *ctx, const tm_graph *g, const tm_server_cfg *cfg, tm_server **out);
 

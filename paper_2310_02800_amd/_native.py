@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "TM_OK", 1: "TM_E_INVALID", 2: "TM_E_OOM", 3: "TM_E_COMPILE",
 
 TM_PARAM_BLOCK, TM_PARAM_ROOT_CHUNK, TM_PARAM_GRID = 1, 2, 3
 TM_PARAM_PROFILE, TM_PARAM_SPLIT, TM_PARAM_SPLIT_MIN, TM_PARAM_TIER, TM_PARAM_AUTOTUNE = 5, 6, 7, 8, 9
+TM_PARAM_WORK_BUDGET = 10
 
 # Every function the header declares, for the export check.
 EXPORTED = [
@@ -43,12 +44,13 @@ class RootRange(ctypes.Structure):
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("stream_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("enum_pool_bytes", ctypes.c_int64),
-                ("queue_capacity", ctypes.c_int32), ("tier", ctypes.c_int32), ("tune_path", ctypes.c_char_p)]
+                ("queue_capacity", ctypes.c_int32), ("tier", ctypes.c_int32), ("work_budget", ctypes.c_int64),
+                ("tune_path", ctypes.c_char_p)]
 
 
 class Query(ctypes.Structure):
     _fields_ = [("motif", MotifDesc), ("range", RootRange), ("has_range", ctypes.c_int32),
-                ("enumerate", ctypes.c_int32), ("tag", ctypes.c_uint64)]
+                ("enumerate", ctypes.c_int32), ("tag", ctypes.c_uint64), ("work_budget", ctypes.c_int64)]
 
 
 class Result(ctypes.Structure):

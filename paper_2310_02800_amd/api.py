@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -166,9 +167,12 @@ class Context:
         N.check(N.lib().tm_create(int(device), ctypes.byref(h)))
         self._h = h
         self.device = device
+        self._servers = weakref.WeakSet()  # servers use the context until they stop
 
     def close(self):
         if self._h:
+            for srv in list(self._servers):
+                srv.stop()
             N.lib().tm_destroy(self._h)
             self._h = None
 
@@ -276,7 +280,9 @@ class Context:
             raise N.NativeError(st, f"capacity {capacity} < {n}")
         return out[:n]
 
-    def count_batch(self, g: Graph, motifs: Sequence[Motif], ranges=None, stream=None):
+    def count_batch(self, g: Graph, motifs: Sequence[Motif], ranges=None, stream=None, allow_cancel=False):
+        """Counts of all queries in one launch. With allow_cancel, queries over
+        the work budget give None instead of raising TM_E_CANCELLED."""
         q = len(motifs)
         arr = (ctypes.c_void_p * max(q, 1))(*[mm.handle.value if hasattr(mm.handle, "value") else mm.handle
                                               for mm in motifs])
@@ -285,7 +291,10 @@ class Context:
             rr = (N.RootRange * q)(*[N.RootRange(I64_MIN if a is None else int(a), I64_MAX if b is None else int(b))
                                      for a, b in ranges])
         out = np.zeros(max(q, 1), np.uint64)
-        N.check(N.lib().tm_count_batch(self._h, g.handle, q, arr, rr, _stream_handle(stream), _ptr(out)))
+        st = N.lib().tm_count_batch(self._h, g.handle, q, arr, rr, _stream_handle(stream), _ptr(out))
+        if st == N.TM_E_CANCELLED and allow_cancel:
+            return [None if int(x) == 2**64 - 1 else int(x) for x in out[:q]]
+        N.check(st)
         return [int(x) for x in out[:q]]
 
 
@@ -301,17 +310,18 @@ class Server:
     """Continuous-batching query server over one resident graph (tm_server_*)."""
 
     def __init__(self, ctx: Context, g: Graph, stream_slots=2, max_batch=64, enum_pool_bytes=1 << 30,
-                 queue_capacity=1 << 16, tier=1, tune_path=None):
+                 queue_capacity=1 << 16, tier=1, tune_path=None, work_budget=0):
         self._tune_path = None if tune_path is None else os.fsencode(tune_path)  # kept alive for the call
         cfg = N.ServerCfg(int(stream_slots), int(max_batch), int(enum_pool_bytes), int(queue_capacity), int(tier),
-                          self._tune_path)
+                          int(work_budget), self._tune_path)
         h = ctypes.c_void_p()
         N.check(N.lib().tm_server_start(ctx._h, g.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
         self._ctx = ctx
         self._g = g
+        ctx._servers.add(self)
 
-    def submit(self, motif, t_lo=None, t_hi=None, enumerate=False, tag=0) -> int:
+    def submit(self, motif, t_lo=None, t_hi=None, enumerate=False, tag=0, work_budget=0) -> int:
         """Submit a synth.Motif-like query; returns its ticket."""
         d, keep = motif_desc_of(motif)
         q = N.Query()
@@ -320,6 +330,7 @@ class Server:
         q.range = N.RootRange(I64_MIN if t_lo is None else int(t_lo), I64_MAX if t_hi is None else int(t_hi))
         q.enumerate = 1 if enumerate else 0
         q.tag = int(tag)
+        q.work_budget = int(work_budget)
         t = ctypes.c_uint64()
         N.check(N.lib().tm_submit_query(self._h, ctypes.byref(q), ctypes.byref(t)))
         return t.value

@@ -99,11 +99,11 @@ hipError_t ws_prepare(tm_ctx::Workspace *w, int64_t chunks, int nq) {
         w->counts = nullptr; w->qa = nullptr; w->qctl = nullptr; w->h_qa = nullptr; w->h_counts = nullptr;
         w->q_cap = 0;
         int cap = std::max(nq, 64);
-        e = hipMalloc(&w->counts, cap * sizeof(uint64_t));
+        e = hipMalloc(&w->counts, 2 * cap * sizeof(uint64_t));  // counts, then step tallies
         if (e == hipSuccess) e = hipMalloc(&w->qctl, 2 * cap * sizeof(uint64_t));
         if (e == hipSuccess) e = hipMalloc(&w->qa, cap * sizeof(QArgs));
         if (e == hipSuccess) e = hipHostMalloc(&w->h_qa, cap * sizeof(QArgs), hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc(&w->h_counts, cap * sizeof(uint64_t), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc(&w->h_counts, 2 * cap * sizeof(uint64_t), hipHostMallocDefault);
         if (e != hipSuccess) return e;
         w->q_cap = cap;
     }
@@ -151,7 +151,7 @@ tmo::LaunchCfg default_cfg(const tm_ctx *ctx) {
 // larger window admits nothing more) and each gap to delta (consecutive gaps
 // never exceed the whole window), so the kernel's window ends never overflow.
 void fill_qargs(const tm_graph *g, const tm_motif *m, int64_t r0, int64_t r1, int64_t c0, int64_t rch, int fn,
-                QArgs *q) {
+                int64_t budget, QArgs *q) {
     std::memset(q, 0, sizeof(*q));
     const int64_t span = g->m ? g->t_max - g->t_min : 0;
     q->r0 = r0;
@@ -163,6 +163,7 @@ void fill_qargs(const tm_graph *g, const tm_motif *m, int64_t r0, int64_t r1, in
     q->theta = m->theta;
     q->pred_op = m->pred_op;
     q->fn = fn;
+    q->budget = budget;
     tmo::fill_plan_tables(m->plan, q);
 }
 
@@ -250,15 +251,15 @@ tm_status get_module(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, int tier
 // One single-query pass in the given mode; leaves results in the workspace.
 tm_status run_single(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
                      hipStream_t stream, int mode, tm_ctx::Workspace *w, tmo::Module *mod, const tmo::LaunchCfg &cfg,
-                     int64_t *chunks_out, int64_t *r0_out, double *ms_acc) {
+                     int64_t budget, int64_t *chunks_out, int64_t *r0_out, double *ms_acc) {
     int64_t r0, r1;
     root_ids(g, range, &r0, &r1);
     const int64_t rch = chunk_for(ctx, cfg, r1 - r0);
     const int64_t chunks = (r1 - r0 + rch - 1) / rch;
     HIP_TRY(ws_prepare(w, chunks, 1), "workspace");
-    fill_qargs(g, m, r0, r1, 0, rch, 0, (QArgs *)w->h_qa);
+    fill_qargs(g, m, r0, r1, 0, rch, 0, budget, (QArgs *)w->h_qa);
     HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload query");
-    HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 1, stream), "reset count");
+    HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 2, stream), "reset count and step tally");
     *chunks_out = chunks;
     *r0_out = r0;
     if (chunks == 0) return TM_OK;
@@ -288,6 +289,9 @@ tm_status run_single(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm
 // are the knobs the paper's hyper-parameter study varies, in this design's
 // terms (Appendix, impact of hyper-parameters): how much work a wavefront
 // takes at once and whether busy lanes hand work to idle ones.
+
+// Result slot of a query that ran out of its work budget.
+constexpr uint64_t kCancelled = ~0ull;
 
 int bitlen64(int64_t x) { return x > 0 ? 64 - __builtin_clzll((unsigned long long)x) : 0; }
 
@@ -370,8 +374,14 @@ tm_status run_tuned(tm_ctx *ctx, const std::string &key, int64_t roots, F &&once
                 if (st != TM_OK) return st;
                 if (!have) {
                     first = r;
-                } else if (r != first) {
-                    return fail(TM_E_DEVICE, "autotuning trials disagree on a count");
+                } else {
+                    // a query over its work budget may be cancelled in some trials
+                    // only; every count that two trials both finished must agree
+                    for (size_t i = 0; i < r.size(); i++) {
+                        if (first[i] == kCancelled) first[i] = r[i];
+                        else if (r[i] != kCancelled && r[i] != first[i])
+                            return fail(TM_E_DEVICE, "autotuning trials disagree on a count");
+                    }
                 }
                 if (!have || ms < best) {
                     best = ms;
@@ -484,6 +494,10 @@ tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t v) {
     case TM_PARAM_AUTOTUNE:
         ctx->autotune = v ? 1 : 0;
         return TM_OK;
+    case TM_PARAM_WORK_BUDGET:
+        if (v < 0) return fail(TM_E_INVALID, "work budget must be >= 0");
+        ctx->work_budget = v;
+        return TM_OK;
     default:
         return fail(TM_E_INVALID, "unknown parameter");
     }
@@ -500,6 +514,7 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *v) {
     case TM_PARAM_SPLIT_MIN: *v = ctx->split_min; return TM_OK;
     case TM_PARAM_TIER: *v = ctx->tier; return TM_OK;
     case TM_PARAM_AUTOTUNE: *v = ctx->autotune; return TM_OK;
+    case TM_PARAM_WORK_BUDGET: *v = ctx->work_budget; return TM_OK;
     default: return fail(TM_E_INVALID, "unknown parameter");
     }
 }
@@ -602,6 +617,7 @@ tm_status tm_load_graph(tm_ctx *ctx, int64_t n, int64_t m, const int32_t *src, c
     tm_graph *g = new (std::nothrow) tm_graph();
     if (!g) return fail(TM_E_OOM, "host allocation");
     g->ctx = ctx;
+    g->device = ctx->device;
     g->n = n;
     g->m = m;
     g->has_w = w != nullptr;
@@ -707,7 +723,7 @@ tm_status tm_load_graph(tm_ctx *ctx, int64_t n, int64_t m, const int32_t *src, c
 
 void tm_free_graph(tm_graph *g) {
     if (!g) return;
-    DeviceGuard dg(g->ctx->device);
+    DeviceGuard dg(g->device);
     hipDeviceSynchronize();
     free_graph_buffers(g);
     delete g;
@@ -735,7 +751,7 @@ tm_status tm_graph_edge_order(const tm_graph *g, int64_t *perm_out) {
 tm_status tm_graph_copy_csr(const tm_graph *g, int32_t dir, uint32_t *off, int32_t *nbr, int32_t *eid,
                             int64_t *t_rel) {
     if (!g || (dir != 0 && dir != 1)) return fail(TM_E_INVALID, "bad argument");
-    DeviceGuard dg(g->ctx->device);
+    DeviceGuard dg(g->device);
     const int64_t m = g->m, base = dir ? m : 0;
     if (off) HIP_TRY(hipMemcpy(off, dir ? g->d_off_in : g->d_off_out, (g->n + 1) * sizeof(uint32_t),
                                hipMemcpyDeviceToHost), "copy offsets");
@@ -861,17 +877,19 @@ tm_status tm_count(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_r
     tm_ctx::Workspace *w = lease.w;
     int64_t r0, r1, chunks = 0;
     root_ids(g, range, &r0, &r1);
+    const int64_t budget = ctx->work_budget;
     auto once = [&](const tmo::LaunchCfg &c, double *ms, std::vector<uint64_t> *res) -> tm_status {
         int64_t rr0 = 0;
-        tm_status s = run_single(ctx, g, m, range, stream, tmo::MODE_COUNT, w, mod.get(), c, &chunks, &rr0, ms);
+        tm_status s =
+            run_single(ctx, g, m, range, stream, tmo::MODE_COUNT, w, mod.get(), c, budget, &chunks, &rr0, ms);
         if (s != TM_OK) return s;
-        HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+        HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
                 "read count");
         HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
                 "read control words");
         HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
         if (chunks && w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
-        res->assign(1, w->h_counts[0]);
+        res->assign(1, budget > 0 && (int64_t)w->h_counts[1] > budget ? kCancelled : w->h_counts[0]);
         return TM_OK;
     };
     const tmo::Plan gp = tmo::generic_plan(m->plan.l);
@@ -885,6 +903,7 @@ tm_status tm_count(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_r
     st = run_tuned(ctx, key, r1 - r0, once, &res, &used, &tuned, &ms);
     if (st != TM_OK) return st;
     note_launch(ctx, used, tuned, ms, chunks ? 1 : 0);
+    if (res[0] == kCancelled) return fail(TM_E_CANCELLED, "work budget exceeded");
     *count_out = res[0];
     return TM_OK;
 }
@@ -903,7 +922,7 @@ tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const
     tmo::LaunchCfg cfg = default_cfg(ctx);
     cfg.split = 0;  // the counters describe the unsplit search
     cfg.timed = false;
-    st = run_single(ctx, g, m, range, stream, tmo::MODE_STATS, w, mod.get(), cfg, &chunks, &r0, nullptr);
+    st = run_single(ctx, g, m, range, stream, tmo::MODE_STATS, w, mod.get(), cfg, 0, &chunks, &r0, nullptr);
     if (st != TM_OK) return st;
     if (chunks == 0) HIP_TRY(tmo::dev_fill_u64(w->ctl, 0, tmo::CTL_WORDS, stream), "reset counters");
     HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
@@ -920,8 +939,8 @@ tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const
 namespace tmo {
 
 tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range, int tier,
-                         hipStream_t stream, tm_ctx::Workspace *w, const RowAlloc &alloc, uint64_t *n_out,
-                         int64_t **rows_out) {
+                         int64_t budget, hipStream_t stream, tm_ctx::Workspace *w, const RowAlloc &alloc,
+                         uint64_t *n_out, int64_t **rows_out) {
     DeviceGuard dg(ctx->device);
     std::shared_ptr<tmo::Module> mod;
     tm_status st;
@@ -947,7 +966,7 @@ tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, cons
     HIP_TRY(tmo::dev_fill_u64(w->chunk_cnt, 0, chunks, stream), "reset chunk counts");
     int64_t c0 = 0, rr0 = 0;
     double ms = 0;
-    st = run_single(ctx, g, m, range, stream, tmo::MODE_ENUM_COUNT, w, mod.get(), cfg, &c0, &rr0, &ms);
+    st = run_single(ctx, g, m, range, stream, tmo::MODE_ENUM_COUNT, w, mod.get(), cfg, budget, &c0, &rr0, &ms);
     if (st != TM_OK) return st;
     // exclusive scan -> per-chunk output offsets (one extra entry: the total)
     HIP_TRY(tmo::dev_fill_u64(w->chunk_cnt + chunks, 0, 1, stream), "scan tail");
@@ -964,11 +983,13 @@ tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, cons
     HIP_TRY(tmo::dev_exclusive_scan_u64(w->chunk_cnt, w->chunk_off, chunks + 1, w->scan_tmp, &have, stream), "scan");
     HIP_TRY(hipMemcpyAsync(w->h_ctl + 64, w->chunk_off + chunks, sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
             "read total");
-    HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "read count");
+    HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+            "read count");
     HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
             "read control words");
     HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
     if (w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
+    if (budget > 0 && (int64_t)w->h_counts[1] > budget) return fail(TM_E_CANCELLED, "work budget exceeded");
     const uint64_t total = w->h_ctl[64];
     if (total != w->h_counts[0]) return fail(TM_E_DEVICE, "enumeration pass 1 disagrees with its own total");
     *n_out = total;
@@ -978,10 +999,12 @@ tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, cons
     int64_t *d_out = alloc(total, &capacity, &ast);
     if (!d_out || capacity < total) return ast;
     if (rows_out) *rows_out = d_out;
-    // pass 2: write rows; chunk_cnt is reused as the per-chunk write cursor
+    // pass 2: write rows; chunk_cnt is reused as the per-chunk write cursor. It
+    // repeats pass 1's search, which finished within the budget, so it has none.
+    ((QArgs *)w->h_qa)->budget = 0;
     HIP_TRY(tmo::dev_fill_u64(w->chunk_cnt, 0, chunks, stream), "reset cursors");
     HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload query");
-    HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 1, stream), "reset count");
+    HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 2, stream), "reset count");
     GArgs a = base_args(g, w, cfg);
     a.total_chunks = chunks;
     a.rch = (int32_t)rch;
@@ -1007,8 +1030,8 @@ tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, cons
 }
 
 tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
-                           const tm_root_range *ranges, int tier, hipStream_t stream, tm_ctx::Workspace *w,
-                           uint64_t *counts_out) {
+                           const tm_root_range *ranges, const int64_t *budgets, int tier, hipStream_t stream,
+                           tm_ctx::Workspace *w, uint64_t *counts_out, uint8_t *cancelled) {
     DeviceGuard dg(ctx->device);
     // one matcher per distinct structure, or with the generic tier one
     // table-driven matcher per motif length (a module that never recompiles)
@@ -1048,11 +1071,11 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
         QArgs *h = (QArgs *)w->h_qa;
         c0 = 0;
         for (int i = 0; i < q; i++) {
-            fill_qargs(g, motifs[i], rlo[i], rhi[i], c0, rch, fn[i], &h[i]);
+            fill_qargs(g, motifs[i], rlo[i], rhi[i], c0, rch, fn[i], budgets ? budgets[i] : 0, &h[i]);
             c0 += h[i].nchunks;
         }
         HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, q * sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload queries");
-        HIP_TRY(tmo::dev_fill_u64(w->counts, 0, q, stream), "reset counts");
+        HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 2 * (int64_t)q, stream), "reset counts and step tallies");
         if (c0 > 0) {
             GArgs a = base_args(g, w, c);
             a.total_chunks = c0;
@@ -1066,13 +1089,15 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
                 if (hipEventElapsedTime(&k, w->ev0, w->ev1) == hipSuccess) *ms = k;
             }
         }
-        HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, q * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+        HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, 2 * q * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
                 "read counts");
         HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
                 "read control words");
         HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
         if (c0 > 0 && w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
         res->assign(w->h_counts, w->h_counts + q);
+        for (int i = 0; i < q; i++)
+            if (budgets && budgets[i] > 0 && (int64_t)w->h_counts[q + i] > budgets[i]) (*res)[i] = kCancelled;
         return TM_OK;
     };
     std::string mkey;
@@ -1088,7 +1113,10 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
     tm_status st = run_tuned(ctx, key, roots, once, &res, &used, &tuned, &ms);
     if (st != TM_OK) return st;
     note_launch(ctx, used, tuned, ms, c0 > 0 ? 1 : 0);
-    for (int i = 0; i < q; i++) counts_out[i] = res[i];
+    for (int i = 0; i < q; i++) {
+        counts_out[i] = res[i];
+        if (cancelled) cancelled[i] = res[i] == kCancelled;
+    }
     return TM_OK;
 }
 
@@ -1135,7 +1163,8 @@ tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const 
         return nullptr;
     };
     WsLease lease(ctx);
-    return tmo::enumerate_impl(ctx, g, m, range, ctx->tier, stream, lease.w, alloc, n_out, nullptr);
+    return tmo::enumerate_impl(ctx, g, m, range, ctx->tier, ctx->work_budget, stream, lease.w, alloc, n_out,
+                               nullptr);
 }
 
 tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
@@ -1147,7 +1176,15 @@ tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_mot
         if (st != TM_OK) return st;
     }
     WsLease lease(ctx);
-    return tmo::count_batch_impl(ctx, g, q, motifs, ranges, ctx->tier, stream, lease.w, counts_out);
+    std::vector<int64_t> budgets(q, ctx->work_budget);
+    std::vector<uint8_t> cancelled(q, 0);
+    tm_status st = tmo::count_batch_impl(ctx, g, q, motifs, ranges, budgets.data(), ctx->tier, stream, lease.w,
+                                         counts_out, cancelled.data());
+    if (st != TM_OK) return st;
+    const int64_t n_cancelled = std::count(cancelled.begin(), cancelled.end(), 1);
+    if (n_cancelled)
+        return fail(TM_E_CANCELLED, std::to_string(n_cancelled) + " of the queries exceeded the work budget");
+    return TM_OK;
 }
 
 }  // extern "C"

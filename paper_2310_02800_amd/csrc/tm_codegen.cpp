@@ -140,7 +140,7 @@ struct QArgs {
   int pred_op;
   int fn;
   int pad;
-  i64 reserved;
+  i64 budget;
   unsigned char pk[8], pa[8], pb[8], pm[8], pj[8];
   int pred_level;
   int glob_mask;
@@ -672,7 +672,7 @@ struct Emitter {
         o << "  const i64 q_r0 = q->r0, q_delta = q->delta, q_c0 = q->c0, q_c1 = q->c0 + q->nchunks;\n";
         o << "  // chunk j of a query holds its roots j, j + nchunks, j + 2 nchunks, ...: a burst of\n";
         o << "  // consecutive heavy roots spreads over many wavefronts\n";
-        o << "  const i64 q_nch = q->nchunks, q_n = q->r1 - q->r0;\n";
+        o << "  const i64 q_nch = q->nchunks, q_n = q->r1 - q->r0, q_budget = q->budget;\n";
         for (int i = 0; i + 1 < L; i++) o << "  const i64 gap" << i << " = q->gap[" << i << "];\n";
         if (G || p.pred_level >= 0) o << "  const float theta = q->theta; const int pop = q->pred_op;\n";
         if (G) {
@@ -697,7 +697,7 @@ struct Emitter {
         }
         o << "  tkey tmaxk = 0, sx = 0; u32 sb = 0u, sn = 0u;\n";
         o << "  u64 cnt = 0, rcnt = 0, st_win = 0, st_probe = 0, st_visit = 0, st_pv = 0, st_root = 0;\n";
-        o << "  u32 iter = 0u; i64 ghungry = 0;\n";
+        o << "  u32 iter = 0u, steps = 0u; i64 ghungry = 0;\n";
         o << "  i64 pnext = 0, pend = 0, pchunk = chunk, pending = -1;\n";
         o << "  bool drained = chunk < 0;\n";
         o << "  if (chunk >= 0) {\n";
@@ -769,6 +769,23 @@ struct Emitter {
         o << "      }\n";
         o << "    }\n";
         o << "    if (ballot(lvl >= 0) == 0ull) break;\n";
+        // work budget: every 1024 loop steps a wavefront adds them to its query's
+        // tally; once the tally passes the budget the query is abandoned (the host
+        // reports it cancelled): skip its remaining root chunks, keeping the first
+        // chunk of a later query for the caller
+        o << "    if (q_budget > 0 && (++steps & 1023u) == 0u) {\n";
+        o << "      i64 used = 0;\n";
+        o << "      if (lane == 0) used = (i64)atomicAdd(&g.counts[g.nq + qi], 1024ull) + 1024;\n";
+        o << "      used = bcast64(used);\n";
+        o << "      if (used > q_budget) {\n";
+        o << "        if (!drained) {\n";
+        o << "          i64 c = 0;\n";
+        o << "          do { if (lane == 0) c = (i64)atomicAdd(&g.ctl[0], 1ull); c = bcast64(c); } while (c < q_c1);\n";
+        o << "          drained = true; pending = c < g.total_chunks ? c : -1;\n";
+        o << "        }\n";
+        o << "        break;\n";
+        o << "      }\n";
+        o << "    }\n";
         if (L > 1) steal();
         if (L > 1 && coop_ok()) coop();
         if (L > 1) {
@@ -943,8 +960,13 @@ struct Emitter {
     }
 };
 
+// Kernel entry names: a single-query module has all four modes; a batched
+// module has one counting kernel, named apart so profiles separate the forms.
+const char *const kSingleNames[4] = {"tm_count", "tm_stats", "tm_enum_count", "tm_enum_write"};
+const char *const kBatchName = "tm_count_batch";
+
 void emit_kernels(std::ostringstream &o, int nfn, int block, bool all_modes) {
-    static const char *names[4] = {"tm_count", "tm_stats", "tm_enum_count", "tm_enum_write"};
+    const char *const *names = all_modes ? kSingleNames : &kBatchName;
     const int nmodes = all_modes ? 4 : 1;
     for (int mode = 0; mode < nmodes; mode++) {
         auto run = [&](const char *ind, const char *qv, const char *cv, const char *ih, const char *in) {
@@ -1157,6 +1179,7 @@ bool cached_code(const std::string &src, std::vector<char> *code, std::string *e
 }
 
 static bool compile_module(const std::string &src, int block, int nmodes, Module *out, std::string *err) {
+    const char *const *names = nmodes == 1 ? &kBatchName : kSingleNames;
     auto t0 = std::chrono::steady_clock::now();
     std::vector<char> code;
     if (!cached_code(src, &code, err)) return false;
@@ -1165,7 +1188,6 @@ static bool compile_module(const std::string &src, int block, int nmodes, Module
         *err = std::string("hipModuleLoadData: ") + hipGetErrorString(he);
         return false;
     }
-    static const char *names[4] = {"tm_count", "tm_stats", "tm_enum_count", "tm_enum_write"};
     for (int mode = 0; mode < nmodes; mode++) {
         he = hipModuleGetFunction(&out->fn[mode], out->mod, names[mode]);
         if (he != hipSuccess) {

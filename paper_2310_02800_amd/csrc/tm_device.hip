@@ -100,6 +100,11 @@ __global__ void k_gather_adj(int64_t m, const int32_t *eids, const int32_t *othe
     }
 }
 
+// Launch errors are read back with hipGetLastError(), which also returns an
+// error some earlier, unrelated call left on this thread; clearing it first
+// makes the check report this helper's own launches.
+void clear_stale_error() { (void)hipGetLastError(); }
+
 int bits_for(int64_t n) {
     int b = 1;
     while (b < 31 && (int64_t(1) << b) < n) b++;
@@ -109,6 +114,7 @@ int bits_for(int64_t n) {
 }  // namespace
 
 hipError_t dev_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s) {
+    clear_stale_error();
     if (n <= 0) return hipSuccess;
     k_fill_u64<<<blocks_for(n), kThreads, 0, s>>>(p, v, n);
     return hipGetLastError();
@@ -116,17 +122,20 @@ hipError_t dev_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s) {
 
 hipError_t dev_exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, void *tmp, size_t *tmp_bytes,
                                   hipStream_t s) {
+    clear_stale_error();
     return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, in, out, (int)n, s);
 }
 
 hipError_t dev_check_ids(int64_t m, int64_t n, const int32_t *d_src, const int32_t *d_dst, uint32_t *d_bad,
                          hipStream_t s) {
+    clear_stale_error();
     if (m <= 0) return hipSuccess;
     k_check_ids<<<blocks_for(m), kThreads, 0, s>>>(m, n, d_src, d_dst, d_bad);
     return hipGetLastError();
 }
 
 hipError_t dev_sort_by_time(int64_t m, int64_t *d_t, int64_t *d_perm, hipStream_t s) {
+    clear_stale_error();
     // stable sort of (t, position): returns sorted t in d_t and the input
     // position of each sorted edge in d_perm
     if (m <= 1) {
@@ -155,12 +164,14 @@ hipError_t dev_sort_by_time(int64_t m, int64_t *d_t, int64_t *d_perm, hipStream_
 
 hipError_t dev_gather_edges(int64_t m, const int64_t *d_perm, const int32_t *src_in, const int32_t *dst_in,
                             const float *w_in, int32_t *src_out, int32_t *dst_out, float *w_out, hipStream_t s) {
+    clear_stale_error();
     if (m <= 0) return hipSuccess;
     k_gather_edges<<<blocks_for(m), kThreads, 0, s>>>(m, d_perm, src_in, dst_in, w_in, src_out, dst_out, w_out);
     return hipGetLastError();
 }
 
 hipError_t dev_make_keys(int64_t m, const int64_t *d_t, int64_t t_min, int key_bytes, void *d_tk, hipStream_t s) {
+    clear_stale_error();
     if (m <= 0) return hipSuccess;
     if (key_bytes == 4)
         k_make_keys<int32_t><<<blocks_for(m), kThreads, 0, s>>>(m, d_t, t_min, (int32_t *)d_tk);
@@ -175,6 +186,7 @@ hipError_t dev_make_keys(int64_t m, const int64_t *d_t, int64_t t_min, int key_b
 hipError_t dev_build_csr(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
                          int key_bytes, const float *d_w, uint32_t add, uint32_t *d_off, void *d_adj_t,
                          int32_t *d_adj_nbr, int32_t *d_adj_eid, float *d_adj_w, uint32_t *d_pos, hipStream_t s) {
+    clear_stale_error();
     hipError_t e = hipSuccess;
     uint32_t *deg = nullptr;
     int32_t *keys_out = nullptr, *ids_in = nullptr, *ids_out = nullptr;

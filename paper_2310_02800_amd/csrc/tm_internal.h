@@ -29,7 +29,7 @@ struct QArgs {
     int32_t pred_op;
     int32_t fn;         // which specialised matcher of the module runs it
     int32_t pad;
-    int64_t reserved;
+    int64_t budget;     // wavefront loop steps this query may use (0 = no limit)
     // plan tables read by the generic (table-driven) matchers, per level:
     // list kind, source and destination motif node, mask of motif nodes bound
     // before the level, window-start rule (0 search, 1 after the root in its
@@ -54,7 +54,7 @@ struct GArgs {
     const uint32_t *off_in;   // n+1 offsets into [m,2m)
     const QArgs *qa;          // device array of nq queries
     uint64_t *ctl;            // [0] chunk cursor [1] output overflow [2..6] work counters
-    uint64_t *counts;         // per query
+    uint64_t *counts;         // per query: counts[0, nq), then steps used counts[nq, 2 nq)
     uint64_t *chunk_cnt;      // enumeration: per-chunk counts, then write cursors
     const uint64_t *chunk_off;
     int64_t *out;
@@ -175,6 +175,7 @@ struct tm_ctx {
     int64_t split_min = 2;
     int tier = 0;  // 0: kernels specialised per motif structure, 1: generic per motif length
     int autotune = 0;
+    int64_t work_budget = 0;  // wavefront loop steps per query (0 = no limit)
     std::mutex tune_mu;
     std::map<std::string, tmo::TuneEntry> tune;  // key: graph, module, delta and size buckets
     tmo::Compiler compiler;
@@ -207,7 +208,8 @@ struct tm_ctx {
 };
 
 struct tm_graph {
-    tm_ctx *ctx = nullptr;
+    tm_ctx *ctx = nullptr;  // for the same-context check only; never dereferenced
+    int device = 0;         // the device holding the buffers (freeing needs no context)
     int64_t n = 0, m = 0;
     int64_t t_min = 0, t_max = 0;
     int key_bytes = 4;
@@ -244,12 +246,15 @@ using RowAlloc = std::function<int64_t *(uint64_t rows, uint64_t *capacity, tm_s
 
 // Blocking building blocks shared by the C entry points and the server; each
 // runs on `stream` with an explicit workspace and kernel tier.
+// A positive budget caps the wavefront loop steps of the query's counting
+// pass: past it the query stops and reports TM_E_CANCELLED (batch: its flag in
+// `cancelled`, which may be null, and count ~0).
 tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range, int tier,
-                         hipStream_t stream, tm_ctx::Workspace *w, const RowAlloc &alloc, uint64_t *n_out,
-                         int64_t **rows_out);
+                         int64_t budget, hipStream_t stream, tm_ctx::Workspace *w, const RowAlloc &alloc,
+                         uint64_t *n_out, int64_t **rows_out);
 tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
-                           const tm_root_range *ranges, int tier, hipStream_t stream, tm_ctx::Workspace *w,
-                           uint64_t *counts_out);
+                           const tm_root_range *ranges, const int64_t *budgets, int tier, hipStream_t stream,
+                           tm_ctx::Workspace *w, uint64_t *counts_out, uint8_t *cancelled);
 tm_ctx::Workspace *ws_acquire(tm_ctx *ctx);
 void ws_release(tm_ctx *ctx, tm_ctx::Workspace *w);
 tm_status set_error(tm_status st, const std::string &msg);

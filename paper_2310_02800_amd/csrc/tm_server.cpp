@@ -42,6 +42,7 @@ struct Pending {
     tm_root_range range{};
     bool has_range = false;
     bool enumerate = false;
+    int64_t budget = 0;  // wavefront loop steps (0 = no limit)
     int64_t t_arrival = 0, t_admit = 0;
 };
 
@@ -148,6 +149,8 @@ void slot_main(tm_server *s) {
     std::vector<const tm_motif *> motifs;
     std::vector<tm_root_range> ranges;
     std::vector<uint64_t> counts;
+    std::vector<int64_t> budgets;
+    std::vector<uint8_t> cancelled;
     for (;;) {
         batch.clear();
         {
@@ -180,7 +183,7 @@ void slot_main(tm_server *s) {
             int64_t *rows = nullptr;
             const int64_t t_launch = now_ns();
             tm_status st = tmo::enumerate_impl(ctx, s->g, &p->motif, p->has_range ? &p->range : nullptr,
-                                               s->cfg.tier, stream, w, alloc, &n, &rows);
+                                               s->cfg.tier, p->budget, stream, w, alloc, &n, &rows);
             if (st == TM_OK && n > 0 && !rows) st = TM_E_CAPACITY;
             if (st != TM_OK) {
                 std::lock_guard<std::mutex> lk(s->mu);
@@ -192,18 +195,23 @@ void slot_main(tm_server *s) {
         } else {
             motifs.clear();
             ranges.clear();
+            budgets.clear();
             for (Pending *p : batch) {
                 motifs.push_back(&p->motif);
                 tm_root_range r = p->range;
                 if (!p->has_range) r = {INT64_MIN, INT64_MAX};
                 ranges.push_back(r);
+                budgets.push_back(p->budget);
             }
             counts.assign(batch.size(), 0);
+            cancelled.assign(batch.size(), 0);
             const int64_t t_launch = now_ns();
             tm_status st = tmo::count_batch_impl(ctx, s->g, (int)batch.size(), motifs.data(), ranges.data(),
-                                                 s->cfg.tier, stream, w, counts.data());
+                                                 budgets.data(), s->cfg.tier, stream, w, counts.data(),
+                                                 cancelled.data());
             for (size_t i = 0; i < batch.size(); i++) {
-                publish(s, *batch[i], st, st == TM_OK ? counts[i] : 0, nullptr, 0, t_launch);
+                const tm_status qs = st != TM_OK ? st : cancelled[i] ? TM_E_CANCELLED : TM_OK;
+                publish(s, *batch[i], qs, qs == TM_OK ? counts[i] : 0, nullptr, 0, t_launch);
                 delete batch[i];
             }
         }
@@ -221,7 +229,8 @@ tm_status tm_server_start(tm_ctx *ctx, const tm_graph *g, const tm_server_cfg *c
     *out = nullptr;
     if (g->ctx != ctx) return tmo::set_error(TM_E_INVALID, "graph belongs to another context");
     if (cfg->stream_slots < 1 || cfg->stream_slots > 64 || cfg->max_batch < 1 || cfg->max_batch > 4096 ||
-        cfg->queue_capacity < 1 || cfg->enum_pool_bytes < 0 || (cfg->tier != 0 && cfg->tier != 1))
+        cfg->queue_capacity < 1 || cfg->enum_pool_bytes < 0 || (cfg->tier != 0 && cfg->tier != 1) ||
+        cfg->work_budget < 0)
         return tmo::set_error(TM_E_INVALID, "server configuration out of range");
     tm_server *s = new (std::nothrow) tm_server();
     if (!s) return tmo::set_error(TM_E_OOM, "host allocation");
@@ -277,6 +286,11 @@ tm_status tm_submit_query(tm_server *s, const tm_query *q, uint64_t *ticket) {
     p->range = q->range;
     p->enumerate = q->enumerate != 0;
     p->tag = q->tag;
+    if (q->work_budget < 0) {
+        delete p;
+        return tmo::set_error(TM_E_INVALID, "work budget must be >= 0");
+    }
+    p->budget = q->work_budget ? q->work_budget : s->cfg.work_budget;
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) {
         delete p;

@@ -371,3 +371,20 @@ def test_wiki_sampled_root_ranges(ctx, wiki, wiki_g):
         say("wiki range", mot.edges, mot.delta, lo, hi)
         assert ctx.count(wiki_g, ctx.compile(mot), t_lo=lo, t_hi=hi) == oracle.count(og, mot, t_lo=lo, t_hi=hi,
                                                                                      nthreads=8)
+
+
+def test_graph_freed_after_its_context(tiny, tiny_og):
+    """Freeing a graph after its context is destroyed touches only the graph
+    (it keeps its own device id); a later context loads and counts normally."""
+    c = api.Context(0)
+    g = c.load_synth(tiny)
+    c.close()
+    g.close()
+    c2 = api.Context(0)
+    try:
+        g2 = c2.load_synth(tiny)
+        mot = synth.tiny_query()
+        assert c2.count(g2, c2.compile(mot)) == oracle.count(tiny_og, mot)
+        g2.close()
+    finally:
+        c2.close()

@@ -161,3 +161,72 @@ def test_generic_tier_with_splitting(ctx, tiny_g, tiny_og, chunk):
     finally:
         for p, v in old.items():
             ctx.set_param(p, v)
+
+
+# ---------------------------------------------------------------- work budget
+HEAVY = synth.batch_queries()[36]  # ~1e9 candidate visits on the tiny graph
+BUDGET = 1 << 22                   # wavefront loop steps (the heavy query needs >= 1.5e7)
+
+
+@pytest.fixture
+def budgeted(ctx):
+    old = ctx.get_param(N.TM_PARAM_WORK_BUDGET)
+    ctx.set_param(N.TM_PARAM_WORK_BUDGET, BUDGET)
+    yield ctx
+    ctx.set_param(N.TM_PARAM_WORK_BUDGET, old)
+
+
+def test_work_budget_cancels_only_the_heavy_query(budgeted, tiny_g, tiny_og):
+    ctx = budgeted
+    light = [synth.tiny_query(), Motif(synth.FOUR_CYCLE, 30_000)]
+    want = [oracle.count(tiny_og, m) for m in light]
+    hh = ctx.compile(HEAVY)
+    with pytest.raises(N.NativeError) as ei:
+        ctx.count(tiny_g, hh)
+    assert ei.value.status == N.TM_E_CANCELLED
+    with pytest.raises(N.NativeError) as ei:
+        ctx.enumerate(tiny_g, hh)
+    assert ei.value.status == N.TM_E_CANCELLED
+    handles = [ctx.compile(light[0]), hh, ctx.compile(light[1])]
+    assert ctx.count_batch(tiny_g, handles, allow_cancel=True) == [want[0], None, want[1]]
+    with pytest.raises(N.NativeError) as ei:
+        ctx.count_batch(tiny_g, handles)
+    assert ei.value.status == N.TM_E_CANCELLED
+    for m, w in zip(light, want):  # light queries stay exact under the budget
+        mm = ctx.compile(m)
+        assert ctx.count(tiny_g, mm) == w
+        assert same_rows(ctx.enumerate(tiny_g, mm), oracle.enumerate(tiny_og, m))
+
+
+def test_work_budget_large_enough_is_exact(ctx, tiny_g, batch_want):
+    old = ctx.get_param(N.TM_PARAM_WORK_BUDGET)
+    try:
+        ctx.set_param(N.TM_PARAM_WORK_BUDGET, 1 << 40)
+        assert ctx.count(tiny_g, ctx.compile(HEAVY)) == batch_want[36]
+    finally:
+        ctx.set_param(N.TM_PARAM_WORK_BUDGET, old)
+
+
+def test_server_cancels_over_budget_queries(ctx, tiny_g, tiny_og):
+    light = [synth.tiny_query(), Motif(synth.FOUR_CYCLE, 30_000)]
+    srv = api.Server(ctx, tiny_g, stream_slots=2, max_batch=8, enum_pool_bytes=64 << 20, tier=1)
+    try:
+        srv.submit(light[0], tag=0)
+        srv.submit(HEAVY, tag=1, work_budget=BUDGET)
+        srv.submit(HEAVY, tag=2, enumerate=True, work_budget=BUDGET)
+        srv.submit(light[1], tag=3, enumerate=True)
+        done = {}
+        import time
+        t_end = time.time() + 90
+        while len(done) < 4 and time.time() < t_end:
+            for r in srv.poll(8, timeout_ms=200):
+                done[r["tag"]] = (r, srv.rows(r) if r["rows"] else None)
+                srv.release(r["ticket"])
+    finally:
+        srv.stop()
+    assert len(done) == 4
+    assert done[0][0]["status"] == N.TM_OK and done[0][0]["count"] == oracle.count(tiny_og, light[0])
+    assert done[1][0]["status"] == N.TM_E_CANCELLED
+    assert done[2][0]["status"] == N.TM_E_CANCELLED and done[2][1] is None
+    assert done[3][0]["status"] == N.TM_OK
+    assert same_rows(done[3][1], oracle.enumerate(tiny_og, light[1]))
