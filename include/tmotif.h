@@ -88,8 +88,10 @@ void tm_destroy(tm_ctx *ctx);
  *                          and is the enumeration output segment
  *   TM_PARAM_GRID          workgroups per launch (0 = fill the GPU by occupancy)
  *   TM_PARAM_PROFILE       1 = time every mining kernel with HIP events
- *   TM_PARAM_SPLIT         1 = hand the pending candidates of busy lanes to idle lanes
- *   TM_PARAM_SPLIT_MIN     smallest pending window worth splitting (>= 2)
+ *   TM_PARAM_SPLIT         1 (default) = hand the pending candidates of busy lanes to
+ *                          idle lanes and, through per-query queues, to idle wavefronts
+ *                          once the root chunks are gone (Sec. 5.2); 0 = never
+ *   TM_PARAM_SPLIT_MIN     smallest pending window worth splitting (>= 2; default 32)
  *   TM_PARAM_TIER          0 = kernels specialised to each motif structure (compiled
  *                          once per structure); 1 = table-driven kernels, one per
  *                          motif length, that read the motif's plan at run time (no
@@ -126,7 +128,9 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
  * signal interval there; roots per chunk and splitting here). With
  * TM_PARAM_AUTOTUNE = 1 the first tm_count or tm_count_batch of a key runs
  * its launch under each candidate setting (roots per chunk in {16, 64, 256,
- * 1024}, splitting off and on), checks that every trial returns the same
+ * 1024}, each with splitting off and with splitting of windows of 32 or more;
+ * at 256 roots also splitting from 8 and from 128), checks that every trial
+ * returns the same
  * counts (else TM_E_DEVICE), returns them, and keeps the fastest setting for
  * the key. Later counts, batches and enumerations with the key use it. The
  * key is the graph (node and edge counts, time span), the kernel module, and

@@ -307,21 +307,27 @@ std::string tune_key(const tm_graph *g, const std::string &mod, int64_t delta, i
     return std::string(buf) + mod;
 }
 
-std::vector<tmo::LaunchCfg> tune_candidates(const tm_ctx *ctx, int64_t roots) {
+std::vector<tmo::LaunchCfg> tune_candidates(int64_t roots) {
     std::vector<tmo::LaunchCfg> out;
+    auto add = [&](int64_t rch, int split, int64_t smin) {
+        tmo::LaunchCfg c;
+        c.rch = rch;
+        c.exact = true;
+        c.split = split;
+        c.split_min = smin;
+        c.timed = true;
+        out.push_back(c);
+    };
     int64_t last_chunks = -1;
     for (int64_t rch : {16, 64, 256, 1024}) {
         const int64_t chunks = (roots + rch - 1) / rch;
         if (chunks == last_chunks) continue;  // same split of the roots as the previous size
         last_chunks = chunks;
-        for (int split : {0, 1}) {
-            tmo::LaunchCfg c;
-            c.rch = rch;
-            c.exact = true;
-            c.split = split;
-            c.split_min = ctx->split_min;
-            c.timed = true;
-            out.push_back(c);
+        add(rch, 0, 32);
+        add(rch, 1, 32);
+        if (rch == 256 || (rch < 256 && chunks == 1)) {
+            add(rch, 1, 8);
+            add(rch, 1, 128);
         }
     }
     return out;
@@ -367,7 +373,7 @@ tm_status run_tuned(tm_ctx *ctx, const std::string &key, int64_t roots, F &&once
             double best = 0;
             tmo::LaunchCfg best_c;
             bool have = false;
-            for (const tmo::LaunchCfg &c : tune_candidates(ctx, roots)) {
+            for (const tmo::LaunchCfg &c : tune_candidates(roots)) {
                 double ms = 0;
                 std::vector<uint64_t> r;
                 tm_status st = once(c, &ms, &r);

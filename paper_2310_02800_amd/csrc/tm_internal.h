@@ -171,8 +171,8 @@ struct tm_ctx {
     int64_t root_chunk = 256;
     int64_t grid = 0;
     int profile = 0;
-    int split = 0;
-    int64_t split_min = 2;
+    int split = 1;
+    int64_t split_min = 32;
     int tier = 0;  // 0: kernels specialised per motif structure, 1: generic per motif length
     int autotune = 0;
     int64_t work_budget = 0;  // wavefront loop steps per query (0 = no limit)

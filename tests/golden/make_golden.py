@@ -3,7 +3,7 @@
 Calls only the CPU oracle (``oracle/``) on the seeded synthetic inputs; no
 value here comes from the GPU path. Run from the repository root:
 
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py [wiki] [skew]
 """
 from __future__ import annotations
 
@@ -35,5 +35,54 @@ def wiki_counts(nthreads: int):
         json.dump(out, f, indent=1)
 
 
+def sorted_rows_sha256(rows) -> str:
+    """SHA-256 of the instance set: rows as little-endian int64, in
+    lexicographic order."""
+    import hashlib
+    import numpy as np
+    a = np.ascontiguousarray(rows, dtype="<i8")
+    if a.shape[0]:
+        a = a[np.lexsort(a.T[::-1])]
+    return hashlib.sha256(a.tobytes()).hexdigest()
+
+
+def skew_counts(nthreads: int):
+    """The heavy-skew graph: full count with work counters, the full instance
+    set (as a hash of its sorted rows plus a few rows), and counts of a few
+    root-time slices."""
+    g = synth.skew_graph()
+    og = oracle.OracleGraph.from_graph(g)
+    mot = synth.skew_query()
+    t0 = time.time()
+    c, st = oracle.count(og, mot, nthreads=nthreads, list_rule=1, with_stats=True)
+    count_s = time.time() - t0
+    print("skew count", c, st, f"{count_s:.1f} s", flush=True)
+    t0 = time.time()
+    rows = oracle.enumerate(og, mot, capacity=c)
+    assert rows.shape[0] == c
+    import numpy as np
+    # root-time slices placed by the quantiles of the instances' root times,
+    # so that each holds some of them (and one before the first holds none)
+    rt = np.sort(g.t[rows[:, 0]]) if c else np.array([int(g.t.min())])
+    q = lambda f: int(rt[min(int(f * (rt.size - 1)), rt.size - 1)])
+    slices = []
+    for lo, hi in [(q(0.1), q(0.3)), (q(0.45), q(0.55)), (q(0.9), int(g.t.max())), (int(g.t.min()), q(0.0) - 1)]:
+        slices.append({"t_lo": lo, "t_hi": hi, "count": oracle.count(og, mot, t_lo=lo, t_hi=hi, nthreads=nthreads)})
+    srt = np.ascontiguousarray(rows, dtype=np.int64)
+    srt = srt[np.lexsort(srt.T[::-1])] if srt.shape[0] else srt
+    out = {"source": "oracle/tm_oracle.c via tests/golden/make_golden.py", "generator": synth.GEN_VERSION,
+           "graph": g.name, "graph_hash": synth.content_hash(g),
+           "motif": {"edges": [list(e) for e in mot.edges], "delta": mot.delta, "gap": list(mot.gaps())},
+           "count": c, "work": st, "oracle_count_s": round(count_s, 1), "threads": nthreads,
+           "rows_sha256": sorted_rows_sha256(rows), "first_rows": srt[:8].tolist(), "slices": slices}
+    with open(os.path.join(HERE, "skew_counts.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
-    wiki_counts(int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1)))
+    which = sys.argv[1:] or ["wiki", "skew"]
+    threads = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    if "wiki" in which:
+        wiki_counts(threads)
+    if "skew" in which:
+        skew_counts(threads)
