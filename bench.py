@@ -98,11 +98,32 @@ def bench_batch64(ctx, args, stream):
         plain = [ctx.count(dg, h, stream=stream) for h in handles]
         ctx.count_batch(dg, handles, stream=stream)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plain = [ctx.count(dg, h, stream=stream) for h in handles]
-    torch.cuda.synchronize()
-    plain_s = (time.perf_counter() - t0) / args.steps
+
+    def time_plain():
+        for _ in range(args.warmup):
+            [ctx.count(dg, h, stream=stream) for h in handles]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = [ctx.count(dg, h, stream=stream) for h in handles]
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, res
+
+    # the plain baseline is the fastest of: tuned per query, the defaults, and
+    # the defaults without splitting
+    from paper_2310_02800_amd import _native as N
+    plain_forms = {}
+    plain_forms["tuned"], plain = time_plain()
+    old_at, old_split = ctx.get_param(N.TM_PARAM_AUTOTUNE), ctx.get_param(N.TM_PARAM_SPLIT)
+    try:
+        ctx.set_param(N.TM_PARAM_AUTOTUNE, 0)
+        plain_forms["default"], _ = time_plain()
+        ctx.set_param(N.TM_PARAM_SPLIT, 0)
+        plain_forms["no_split"], _ = time_plain()
+    finally:
+        ctx.set_param(N.TM_PARAM_AUTOTUNE, old_at)
+        ctx.set_param(N.TM_PARAM_SPLIT, old_split)
+    plain_s = min(plain_forms.values())
     t0 = time.perf_counter()
     for _ in range(args.steps):
         got = ctx.count_batch(dg, handles, stream=stream)
@@ -116,6 +137,7 @@ def bench_batch64(ctx, args, stream):
                         "motifs, 3-6 edges, 3-5 nodes, delta log-uniform in [600, 86400], odd ones with a weight "
                         "predicate",
             "instances": inst, "plain_ms": plain_s * 1e3, "batched_ms": batch_s * 1e3,
+            "plain_ms_by_setting": {k: v * 1e3 for k, v in plain_forms.items()},
             "plain_value": inst / plain_s, "batched_value": inst / batch_s, "unit": "instances/s",
             "speedup": plain_s / batch_s,
             "batched_launch": {"root_chunk": setting[0], "split": setting[1], "tuned": setting[2]}}
@@ -297,6 +319,11 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, copy 1 GiB once (a known-size kernel for scaling HBM byte counters)")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch settings")
+    ap.add_argument("--root-chunk", type=int, default=None, help="fixed roots per chunk (implies --no-autotune)")
+    ap.add_argument("--split", type=int, default=None, choices=(0, 1),
+                    help="fixed splitting setting (implies --no-autotune)")
+    ap.add_argument("--min-waves", type=int, default=None,
+                    help="compile the mining kernels to fit this many waves per SIMD")
     ap.add_argument("--tune-table", default=None,
                     help="load launch settings from this file if it exists, save them there at the end")
     ap.add_argument("--no-batch64", action="store_true", help="skip the 64-query batch on the small graph")
@@ -330,6 +357,14 @@ def main():
 
     ctx = api.Context(0)
     ctx.set_param(N.TM_PARAM_PROFILE, 1)
+    if args.min_waves is not None:
+        ctx.set_param(N.TM_PARAM_MIN_WAVES, args.min_waves)
+    if args.root_chunk is not None or args.split is not None:
+        args.no_autotune = True
+        if args.root_chunk is not None:
+            ctx.set_param(N.TM_PARAM_ROOT_CHUNK, args.root_chunk)
+        if args.split is not None:
+            ctx.set_param(N.TM_PARAM_SPLIT, args.split)
     ctx.set_param(N.TM_PARAM_AUTOTUNE, 0 if args.no_autotune else 1)
     if args.tune_table and os.path.exists(args.tune_table):
         ctx.tune_load(args.tune_table)
@@ -417,10 +452,11 @@ def main():
     if os.path.exists(tfile):
         with open(tfile) as f:
             tr = json.load(f)
-        lc = tr.get("launch", {})
-        if (tr.get("kernel_source_hash") == src_hash and tr.get("form") == form
-                and (lc.get("root_chunk"), lc.get("split")) == (batch_setting[0], batch_setting[1])):
-            traffic = tr.get("bytes_per_launch")
+        if tr.get("kernel_source_hash") == src_hash and tr.get("form") == form:
+            for rec in tr.get("records", []):
+                lc = rec["launch"]
+                if (lc["root_chunk"], lc["split"]) == (batch_setting[0], batch_setting[1]):
+                    traffic = rec["bytes_per_launch"]
 
     out = {
         "metric": "motif instances counted/sec per MI355X vs plain; p50/p99 query latency",

@@ -108,6 +108,11 @@ void tm_destroy(tm_ctx *ctx);
  *                          no limit. This plays the role of the paper's abort signal,
  *                          checked every fixed number of iterations (Sec. 5.2.2),
  *                          except that the query ends instead of being resumed.
+ *   TM_PARAM_MIN_WAVES     0 (default) = registers as the compiler chooses; 1..8 = compile
+ *                          the mining kernels to fit at least that many waves per SIMD
+ *                          (more resident waves hide more memory latency; fewer
+ *                          registers each). Kernels compiled with each value are
+ *                          cached apart.
  */
 enum {
     TM_PARAM_BLOCK = 1,
@@ -118,7 +123,8 @@ enum {
     TM_PARAM_SPLIT_MIN = 7,
     TM_PARAM_TIER = 8,
     TM_PARAM_AUTOTUNE = 9,
-    TM_PARAM_WORK_BUDGET = 10
+    TM_PARAM_WORK_BUDGET = 10,
+    TM_PARAM_MIN_WAVES = 11
 };
 tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t value);
 tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
@@ -129,7 +135,7 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
  * TM_PARAM_AUTOTUNE = 1 the first tm_count or tm_count_batch of a key runs
  * its launch under each candidate setting (roots per chunk in {16, 64, 256,
  * 1024}, each with splitting off and with splitting of windows of 32 or more;
- * at 256 roots also splitting from 8 and from 128), checks that every trial
+ * at 256 roots also splitting from 2, 8 and 128), checks that every trial
  * returns the same
  * counts (else TM_E_DEVICE), returns them, and keeps the fastest setting for
  * the key. Later counts, batches and enumerations with the key use it. The
@@ -299,7 +305,10 @@ tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const
 
 /* Batched count: q queries (motifs[i] with ranges[i], ranges may be NULL) in
  * one persistent launch; work items (query, root chunk) are drawn from one
- * device queue. counts_out: host uint64[q]. Blocking. TM_PARAM_WORK_BUDGET
+ * device queue, the queries' chunks in decreasing order of roots times delta
+ * (heaviest first); one launch setting (tuned per batch key with
+ * TM_PARAM_AUTOTUNE) applies to all of them. counts_out: host uint64[q], in
+ * the order of motifs. Blocking. TM_PARAM_WORK_BUDGET
  * applies to each query on its own: a query over it gets count UINT64_MAX and
  * the call returns TM_E_CANCELLED; the other counts are exact. */
 tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,

@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "TM_OK", 1: "TM_E_INVALID", 2: "TM_E_OOM", 3: "TM_E_COMPILE",
 
 TM_PARAM_BLOCK, TM_PARAM_ROOT_CHUNK, TM_PARAM_GRID = 1, 2, 3
 TM_PARAM_PROFILE, TM_PARAM_SPLIT, TM_PARAM_SPLIT_MIN, TM_PARAM_TIER, TM_PARAM_AUTOTUNE = 5, 6, 7, 8, 9
-TM_PARAM_WORK_BUDGET = 10
+TM_PARAM_WORK_BUDGET, TM_PARAM_MIN_WAVES = 10, 11
 
 # Every function the header declares, for the export check.
 EXPORTED = [

@@ -151,7 +151,7 @@ tmo::LaunchCfg default_cfg(const tm_ctx *ctx) {
 // larger window admits nothing more) and each gap to delta (consecutive gaps
 // never exceed the whole window), so the kernel's window ends never overflow.
 void fill_qargs(const tm_graph *g, const tm_motif *m, int64_t r0, int64_t r1, int64_t c0, int64_t rch, int fn,
-                int64_t budget, QArgs *q) {
+                int64_t budget, int split, int64_t split_min, QArgs *q) {
     std::memset(q, 0, sizeof(*q));
     const int64_t span = g->m ? g->t_max - g->t_min : 0;
     q->r0 = r0;
@@ -164,6 +164,8 @@ void fill_qargs(const tm_graph *g, const tm_motif *m, int64_t r0, int64_t r1, in
     q->pred_op = m->pred_op;
     q->fn = fn;
     q->budget = budget;
+    q->split = split;
+    q->split_min = (int32_t)std::min<int64_t>(split_min, INT32_MAX);
     tmo::fill_plan_tables(m->plan, q);
 }
 
@@ -242,7 +244,7 @@ tm_status get_module(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, int tier
                      std::shared_ptr<tmo::Module> *out) {
     std::string err;
     const tmo::Plan gp = tmo::generic_plan(m->plan.l);
-    auto mod = ctx->compiler.get(tier ? gp : m->plan, g->key_bytes, ctx->block, &err);
+    auto mod = ctx->compiler.get(tier ? gp : m->plan, g->key_bytes, ctx->block, &err, ctx->min_waves);
     if (!mod) return fail(TM_E_COMPILE, err);
     *out = mod;
     return TM_OK;
@@ -257,7 +259,7 @@ tm_status run_single(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm
     const int64_t rch = chunk_for(ctx, cfg, r1 - r0);
     const int64_t chunks = (r1 - r0 + rch - 1) / rch;
     HIP_TRY(ws_prepare(w, chunks, 1), "workspace");
-    fill_qargs(g, m, r0, r1, 0, rch, 0, budget, (QArgs *)w->h_qa);
+    fill_qargs(g, m, r0, r1, 0, rch, 0, budget, cfg.split, cfg.split_min, (QArgs *)w->h_qa);
     HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload query");
     HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 2, stream), "reset count and step tally");
     *chunks_out = chunks;
@@ -296,7 +298,8 @@ constexpr uint64_t kCancelled = ~0ull;
 int bitlen64(int64_t x) { return x > 0 ? 64 - __builtin_clzll((unsigned long long)x) : 0; }
 
 std::string module_key(const tm_ctx *ctx, const tm_graph *g, const tmo::Plan &p) {
-    return "S" + std::to_string(g->key_bytes) + "b" + std::to_string(ctx->block) + ":" + p.key();
+    return "S" + std::to_string(g->key_bytes) + "b" + std::to_string(ctx->block) +
+           (ctx->min_waves ? "w" + std::to_string(ctx->min_waves) : std::string()) + ":" + p.key();
 }
 
 std::string tune_key(const tm_graph *g, const std::string &mod, int64_t delta, int64_t roots, int q) {
@@ -326,6 +329,7 @@ std::vector<tmo::LaunchCfg> tune_candidates(int64_t roots) {
         add(rch, 0, 32);
         add(rch, 1, 32);
         if (rch == 256 || (rch < 256 && chunks == 1)) {
+            add(rch, 1, 2);
             add(rch, 1, 8);
             add(rch, 1, 128);
         }
@@ -504,6 +508,10 @@ tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t v) {
         if (v < 0) return fail(TM_E_INVALID, "work budget must be >= 0");
         ctx->work_budget = v;
         return TM_OK;
+    case TM_PARAM_MIN_WAVES:
+        if (v < 0 || v > 8) return fail(TM_E_INVALID, "min waves per SIMD must be in [0, 8]");
+        ctx->min_waves = (int)v;
+        return TM_OK;
     default:
         return fail(TM_E_INVALID, "unknown parameter");
     }
@@ -521,6 +529,7 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *v) {
     case TM_PARAM_TIER: *v = ctx->tier; return TM_OK;
     case TM_PARAM_AUTOTUNE: *v = ctx->autotune; return TM_OK;
     case TM_PARAM_WORK_BUDGET: *v = ctx->work_budget; return TM_OK;
+    case TM_PARAM_MIN_WAVES: *v = ctx->min_waves; return TM_OK;
     default: return fail(TM_E_INVALID, "unknown parameter");
     }
 }
@@ -800,7 +809,7 @@ tm_status tm_compile_motif(tm_ctx *ctx, const tm_motif_desc *desc, tm_motif **ou
     // compile eagerly for 32-bit time keys (the common case) so errors surface
     // here; with the generic tier this is the shared module of the motif length
     const tmo::Plan gp = tmo::generic_plan(m->plan.l);
-    if (!ctx->compiler.get(ctx->tier ? gp : m->plan, 4, ctx->block, &err)) {
+    if (!ctx->compiler.get(ctx->tier ? gp : m->plan, 4, ctx->block, &err, ctx->min_waves)) {
         delete m;
         return fail(TM_E_COMPILE, err);
     }
@@ -1061,29 +1070,49 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
         }
     }
     std::string err;
-    auto mod = ctx->compiler.get_batch(plans, g->key_bytes, ctx->block, &err);
+    auto mod = ctx->compiler.get_batch(plans, g->key_bytes, ctx->block, &err, ctx->min_waves);
     if (!mod) return fail(TM_E_COMPILE, err);
     HIP_TRY(ws_prepare(w, 0, q), "workspace");
     std::vector<int64_t> rlo(q), rhi(q);
     int64_t roots = 0, dmax = 0;
+    const int64_t span = g->m ? g->t_max - g->t_min : 0;
     for (int i = 0; i < q; i++) {
         root_ids(g, ranges ? &ranges[i] : nullptr, &rlo[i], &rhi[i]);
         roots += rhi[i] - rlo[i];
         dmax = std::max(dmax, motifs[i]->delta);
     }
+    // Queries go into the shared chunk queue heaviest first (by roots times
+    // window, a cheap estimate of their search), so the long ones start early
+    // and the short ones fill in behind them.
+    std::vector<int> order(q);
+    for (int i = 0; i < q; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const double wa = (double)(rhi[a] - rlo[a]) * (double)std::min(motifs[a]->delta, span);
+        const double wb = (double)(rhi[b] - rlo[b]) * (double)std::min(motifs[b]->delta, span);
+        return wa > wb;
+    });
+    // Every query of a batch takes the batch's splitting setting: once any
+    // query splits, idle wavefronts poll the donation queues of all of them,
+    // so settings tuned for queries alone do not carry over (measured: mixing
+    // them made a 64-query batch 5x slower).
     int64_t c0 = 0;
     auto once = [&](const tmo::LaunchCfg &c, double *ms, std::vector<uint64_t> *res) -> tm_status {
         const int64_t rch = chunk_for(ctx, c, roots);
         QArgs *h = (QArgs *)w->h_qa;
         c0 = 0;
-        for (int i = 0; i < q; i++) {
-            fill_qargs(g, motifs[i], rlo[i], rhi[i], c0, rch, fn[i], budgets ? budgets[i] : 0, &h[i]);
-            c0 += h[i].nchunks;
+        int any_split = 0;
+        for (int j = 0; j < q; j++) {
+            const int i = order[j];
+            fill_qargs(g, motifs[i], rlo[i], rhi[i], c0, rch, fn[i], budgets ? budgets[i] : 0, c.split,
+                       c.split_min, &h[j]);
+            any_split |= c.split;
+            c0 += h[j].nchunks;
         }
         HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, q * sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload queries");
         HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 2 * (int64_t)q, stream), "reset counts and step tallies");
         if (c0 > 0) {
             GArgs a = base_args(g, w, c);
+            a.split = any_split;
             a.total_chunks = c0;
             a.rch = (int32_t)rch;
             a.nq = q;
@@ -1101,14 +1130,18 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
                 "read control words");
         HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
         if (c0 > 0 && w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
-        res->assign(w->h_counts, w->h_counts + q);
-        for (int i = 0; i < q; i++)
-            if (budgets && budgets[i] > 0 && (int64_t)w->h_counts[q + i] > budgets[i]) (*res)[i] = kCancelled;
+        res->assign(q, 0);
+        for (int j = 0; j < q; j++) {
+            const int i = order[j];
+            (*res)[i] = w->h_counts[j];
+            if (budgets && budgets[i] > 0 && (int64_t)w->h_counts[q + j] > budgets[i]) (*res)[i] = kCancelled;
+        }
         return TM_OK;
     };
     std::string mkey;
     if (ctx->autotune) {
-        mkey = "B" + std::to_string(g->key_bytes) + "b" + std::to_string(ctx->block) + ":";
+        mkey = "B" + std::to_string(g->key_bytes) + "b" + std::to_string(ctx->block) +
+               (ctx->min_waves ? "w" + std::to_string(ctx->min_waves) : std::string()) + ":";
         for (auto *p : plans) mkey += p->key() + "|";
     }
     const std::string key = ctx->autotune ? tune_key(g, mkey, dmax, roots, q) : std::string();

@@ -139,11 +139,13 @@ struct QArgs {
   float theta;
   int pred_op;
   int fn;
-  int pad;
+  int split;
   i64 budget;
   unsigned char pk[8], pa[8], pb[8], pm[8], pj[8];
   int pred_level;
   int glob_mask;
+  int split_min;
+  int pad[3];
 };
 
 struct GArgs {
@@ -159,7 +161,7 @@ struct GArgs {
   u32* items; u64* qctl; u32 item_cap; u32 epoch;
   const u32* pos_out; const u32* pos_in;
 };
-static_assert(sizeof(QArgs) == 176, "QArgs layout");
+static_assert(sizeof(QArgs) == 192, "QArgs layout");
 static_assert(sizeof(GArgs) == 208, "GArgs layout");
 // generic matchers: motif node slot by run-time index, and the bound-node check
 #define mget(ix) ((ix) == 0 ? m0 : (ix) == 1 ? m1 : (ix) == 2 ? m2 : (ix) == 3 ? m3 : \
@@ -440,7 +442,7 @@ struct Emitter {
     // candidate ranges, so every instance is still found exactly once.
     void steal() {
         const int L = p.l, K = p.k;
-        o << "    if (g.split && drained && MODE != 1) {\n";
+        o << "    if (q_split && drained && MODE != 1) {\n";
         o << "      iter++;\n";
         o << "      if ((iter & 31u) == 0u && g.items != 0) {\n";
         o << "        i64 hv = 0; if (lane == 0) hv = (i64)ld_rlx64(&g.ctl[9]); ghungry = bcast64(hv);\n";
@@ -463,7 +465,7 @@ struct Emitter {
                 if (i == L - 1) extra = " && ((gglob >> " + I(i) + ") & 1u)";
             }
             o << "            if (dj == 0 && base <= " << i << " && " << i << " <= top && end" << i << " - cur" << i
-              << " >= (u32)g.split_min" << extra << ") {\n";
+              << " >= q_smin" << extra << ") {\n";
             o << "              u32 lo = cur" << i << ", n = end" << i << " - cur" << i << ";\n";
             o << "              if (exact & " << (1 << i) << "u) { lo = end" << i << "; n = 0u; }\n";
             o << "              while (n > 0u) { const u32 h2 = n >> 1; if (" << arr << "[lo + h2] <= hi" << i
@@ -673,6 +675,7 @@ struct Emitter {
         o << "  // chunk j of a query holds its roots j, j + nchunks, j + 2 nchunks, ...: a burst of\n";
         o << "  // consecutive heavy roots spreads over many wavefronts\n";
         o << "  const i64 q_nch = q->nchunks, q_n = q->r1 - q->r0, q_budget = q->budget;\n";
+        o << "  const bool q_split = g.split && q->split; const u32 q_smin = (u32)q->split_min;\n";
         for (int i = 0; i + 1 < L; i++) o << "  const i64 gap" << i << " = q->gap[" << i << "];\n";
         if (G || p.pred_level >= 0) o << "  const float theta = q->theta; const int pop = q->pred_op;\n";
         if (G) {
@@ -965,7 +968,7 @@ struct Emitter {
 const char *const kSingleNames[4] = {"tm_count", "tm_stats", "tm_enum_count", "tm_enum_write"};
 const char *const kBatchName = "tm_count_batch";
 
-void emit_kernels(std::ostringstream &o, int nfn, int block, bool all_modes) {
+void emit_kernels(std::ostringstream &o, int nfn, int block, bool all_modes, int min_waves) {
     const char *const *names = all_modes ? kSingleNames : &kBatchName;
     const int nmodes = all_modes ? 4 : 1;
     for (int mode = 0; mode < nmodes; mode++) {
@@ -978,7 +981,9 @@ void emit_kernels(std::ostringstream &o, int nfn, int block, bool all_modes) {
             o << ind << "    default: c = -1; break;\n";
             o << ind << "  } }\n";
         };
-        o << "extern \"C\" __global__ __launch_bounds__(" << block << ") void " << names[mode] << "(GArgs g) {\n";
+        o << "extern \"C\" __global__ __launch_bounds__(" << block;
+        if (min_waves > 0) o << ", " << min_waves;  // minimum waves per SIMD
+        o << ") void " << names[mode] << "(GArgs g) {\n";
         o << "  const int lane = lane_id();\n";
         o << "  i64 c = 0;\n";
         o << "  if (lane == 0) { atomicAdd(&g.ctl[8], 1ull); c = (i64)atomicAdd(&g.ctl[0], 1ull); }\n";
@@ -1047,15 +1052,16 @@ static std::string header(int key_bytes) {
     return o.str();
 }
 
-std::string generate_source(const Plan &p, int key_bytes, int block) {
+std::string generate_source(const Plan &p, int key_bytes, int block, int min_waves) {
     Emitter e(p, p.generic);
     e.o << header(key_bytes);
     e.matcher(0);
-    emit_kernels(e.o, 1, block, true);
+    emit_kernels(e.o, 1, block, true, min_waves);
     return e.o.str();
 }
 
-std::string generate_batch_source(const std::vector<const Plan *> &plans, int key_bytes, int block) {
+std::string generate_batch_source(const std::vector<const Plan *> &plans, int key_bytes, int block,
+                                  int min_waves) {
     std::ostringstream all;
     all << header(key_bytes);
     for (size_t f = 0; f < plans.size(); f++) {
@@ -1063,7 +1069,7 @@ std::string generate_batch_source(const std::vector<const Plan *> &plans, int ke
         e.matcher((int)f);
         all << e.o.str();
     }
-    emit_kernels(all, (int)plans.size(), block, false);
+    emit_kernels(all, (int)plans.size(), block, false, min_waves);
     return all.str();
 }
 
@@ -1225,16 +1231,19 @@ std::shared_ptr<Module> Compiler::lookup_or_build(const std::string &key, int bl
     return ok ? m : nullptr;
 }
 
-std::shared_ptr<Module> Compiler::get(const Plan &p, int key_bytes, int block, std::string *err) {
-    const std::string key = "S" + std::to_string(key_bytes) + "b" + std::to_string(block) + ":" + p.key();
-    return lookup_or_build(key, block, 4, [&] { return generate_source(p, key_bytes, block); }, err);
+std::shared_ptr<Module> Compiler::get(const Plan &p, int key_bytes, int block, std::string *err, int min_waves) {
+    const std::string key = "S" + std::to_string(key_bytes) + "b" + std::to_string(block) +
+                            (min_waves ? "w" + std::to_string(min_waves) : std::string()) + ":" + p.key();
+    return lookup_or_build(key, block, 4, [&] { return generate_source(p, key_bytes, block, min_waves); }, err);
 }
 
 std::shared_ptr<Module> Compiler::get_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
-                                            std::string *err) {
-    std::string key = "B" + std::to_string(key_bytes) + "b" + std::to_string(block) + ":";
+                                            std::string *err, int min_waves) {
+    std::string key = "B" + std::to_string(key_bytes) + "b" + std::to_string(block) +
+                      (min_waves ? "w" + std::to_string(min_waves) : std::string()) + ":";
     for (auto *p : plans) key += p->key() + "|";
-    return lookup_or_build(key, block, 1, [&] { return generate_batch_source(plans, key_bytes, block); }, err);
+    return lookup_or_build(key, block, 1,
+                           [&] { return generate_batch_source(plans, key_bytes, block, min_waves); }, err);
 }
 
 }  // namespace tmo

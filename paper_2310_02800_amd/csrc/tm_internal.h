@@ -28,7 +28,7 @@ struct QArgs {
     float theta;
     int32_t pred_op;
     int32_t fn;         // which specialised matcher of the module runs it
-    int32_t pad;
+    int32_t split;      // 1: busy lanes of this query hand pending windows to idle ones
     int64_t budget;     // wavefront loop steps this query may use (0 = no limit)
     // plan tables read by the generic (table-driven) matchers, per level:
     // list kind, source and destination motif node, mask of motif nodes bound
@@ -38,8 +38,10 @@ struct QArgs {
     uint8_t pk[8], pa[8], pb[8], pm[8], pj[8];
     int32_t pred_level;
     int32_t glob_mask;  // bit i: level i scans the whole edge list
+    int32_t split_min;  // smallest pending window this query splits
+    int32_t pad[3];
 };
-static_assert(sizeof(QArgs) == 176, "QArgs layout");
+static_assert(sizeof(QArgs) == 192, "QArgs layout");
 
 struct GArgs {
     const int32_t *src;
@@ -112,17 +114,19 @@ struct Compiler {
     std::map<std::string, std::shared_ptr<Module>> cache;
     std::set<std::string> inflight;            // keys some thread is compiling now
     int device = 0;
-    std::shared_ptr<Module> get(const Plan &p, int key_bytes, int block, std::string *err);
+    // min_waves > 0 asks the compiler to fit that many waves per SIMD
+    std::shared_ptr<Module> get(const Plan &p, int key_bytes, int block, std::string *err, int min_waves = 0);
     std::shared_ptr<Module> get_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
-                                      std::string *err);
+                                      std::string *err, int min_waves = 0);
     // the cached module for `key`, else one built by `make` (which compiles
     // `nmodes` kernels); concurrent callers of one key share a single compile
     std::shared_ptr<Module> lookup_or_build(const std::string &key, int block, int nmodes,
                                             const std::function<std::string()> &make, std::string *err);
 };
 
-std::string generate_source(const Plan &p, int key_bytes, int block);
-std::string generate_batch_source(const std::vector<const Plan *> &plans, int key_bytes, int block);
+std::string generate_source(const Plan &p, int key_bytes, int block, int min_waves = 0);
+std::string generate_batch_source(const std::vector<const Plan *> &plans, int key_bytes, int block,
+                                  int min_waves = 0);
 bool build_plan(const tm_motif_desc *d, Plan *p, int64_t *gaps, std::string *err);
 bool compile_to_code(const std::string &src, std::vector<char> *code, std::string *err);
 bool cached_code(const std::string &src, std::vector<char> *code, std::string *err);
@@ -174,6 +178,7 @@ struct tm_ctx {
     int split = 1;
     int64_t split_min = 32;
     int tier = 0;  // 0: kernels specialised per motif structure, 1: generic per motif length
+    int min_waves = 0;  // waves per SIMD the kernels are compiled to fit (0: compiler's choice)
     int autotune = 0;
     int64_t work_budget = 0;  // wavefront loop steps per query (0 = no limit)
     std::mutex tune_mu;

@@ -230,3 +230,17 @@ def test_server_cancels_over_budget_queries(ctx, tiny_g, tiny_og):
     assert done[2][0]["status"] == N.TM_E_CANCELLED and done[2][1] is None
     assert done[3][0]["status"] == N.TM_OK
     assert same_rows(done[3][1], oracle.enumerate(tiny_og, light[1]))
+
+
+def test_batch_after_tuned_singles(tuned, tiny_g, batch_want):
+    """Tuning some queries alone first leaves the batch exact, in the caller's
+    order whatever the dispatch order."""
+    ctx = tuned
+    ctx.set_param(N.TM_PARAM_TIER, 1)
+    qs = synth.batch_queries()
+    handles = [ctx.compile(m) for m in qs]
+    for i in (0, 5, 17, 36, 58):
+        assert ctx.count(tiny_g, handles[i]) == batch_want[i]
+    assert ctx.count_batch(tiny_g, handles) == batch_want
+    rev = handles[::-1]  # results follow the caller's order whatever the dispatch order
+    assert ctx.count_batch(tiny_g, rev) == batch_want[::-1]
