@@ -484,7 +484,13 @@ struct Emitter {
             o << "            }\n";
         }
         o << "          }\n";
-        o << "          const u64 donors = ballot(dj > 0);\n";
+        // A donor at the level just above a wavefront-cooperative last level
+        // whose last leaf window was wide gives nothing to idle lanes of its
+        // own wavefront: every candidate it hands over opens another wide leaf
+        // that the same wavefront scans one at a time anyway. Such work only
+        // moves to other wavefronts (below).
+        const int cp = coop_ok() ? L - 2 : -1;
+        o << "          const u64 donors = ballot(dj > 0 && !(dj == " << cp << " && wide));\n";
         o << "          const int ni = __builtin_popcountll(idle), nd = __builtin_popcountll(donors);\n";
         o << "          const int np = ni < nd ? ni : nd;\n";
         o << "          const int rd = rank_in(donors);\n";
@@ -513,7 +519,7 @@ struct Emitter {
         }
         o << "                default: break;\n";
         o << "              }\n";
-        o << "            } else if (dj > 0 && rd < np) {\n";
+        o << "            } else if (((donors >> lane) & 1ull) && rd < np) {\n";
         o << "              switch (dj) {\n";
         for (int i = 1; i < L; i++) o << "                case " << i << ": end" << i << " = ds; break;\n";
         o << "                default: break;\n";
@@ -523,7 +529,9 @@ struct Emitter {
         // donors not paired inside the wavefront publish their split part for
         // wavefronts that ran out of work (cross-wavefront redistribution)
         o << "          bool pushed = false;\n";
-        o << "          if (gl && dj > 0 && rd >= np && rd - np < 16) {\n";
+        o << "          const bool gave = ((donors >> lane) & 1ull) && rd < np;\n";
+        o << "          const u64 pushers = ballot(dj > 0 && !gave);\n";
+        o << "          if (gl && dj > 0 && !gave && rank_in(pushers) < 16) {\n";
         o << "            const u64 slot = atomicAdd(&g.qctl[2 * qi + 1], 1ull);\n";
         o << "            if (slot < (u64)g.item_cap) {\n";
         o << "              u32* it = item_at(g, qi, slot);\n";
@@ -989,7 +997,7 @@ void emit_kernels(std::ostringstream &o, int nfn, int block, bool all_modes, int
         o << "  if (lane == 0) { atomicAdd(&g.ctl[8], 1ull); c = (i64)atomicAdd(&g.ctl[0], 1ull); }\n";
         o << "  c = bcast64(c);\n";
         o << "  bool busy = true, hung = false;\n";
-        o << "  u32 polls = 0u;\n";
+        o << "  u32 polls = 0u, nap = 1u;\n";
         o << "  for (;;) {\n";
         o << "    if (c >= 0 && c < g.total_chunks) {\n";
         o << "      int qi = 0;\n";
@@ -1024,7 +1032,7 @@ void emit_kernels(std::ostringstream &o, int nfn, int block, bool all_modes, int
         o << "    if (fq >= 0) {\n";
         o << "      busy = true;\n";
         o << "      if (lane == 0) atomicAdd(&g.ctl[9], ~0ull);\n";
-        o << "      hung = false; polls = 0u;\n";
+        o << "      hung = false; polls = 0u; nap = 1u;\n";
         run("      ", "fq", "-1", "h", "n");
         o << "      continue;\n";
         o << "    }\n";
@@ -1032,8 +1040,13 @@ void emit_kernels(std::ostringstream &o, int nfn, int block, bool all_modes, int
         o << "    if (lane == 0) b = (i64)ld_rlx64(&g.ctl[8]);\n";
         o << "    b = bcast64(b);\n";
         o << "    if (b == 0) break;\n";
-        o << "    if (++polls > (1u << 20)) break;\n";
-        o << "    __builtin_amdgcn_s_sleep(8);\n";
+        // back off exponentially (1 to 16 long sleeps between looks), so that
+        // thousands of waiting wavefronts do not hammer the few queue words the
+        // working ones also use; give up after about 2^18 long sleeps in all
+        o << "    polls += nap;\n";
+        o << "    if (polls > (1u << 18)) break;\n";
+        o << "    for (u32 k = 0u; k < nap; ++k) __builtin_amdgcn_s_sleep(127);\n";
+        o << "    if (nap < 16u) nap <<= 1;\n";
         o << "  }\n";
         o << "  if (busy && lane == 0) atomicAdd(&g.ctl[8], ~0ull);\n";
         o << "  if (hung && lane == 0) atomicAdd(&g.ctl[9], ~0ull);\n";
