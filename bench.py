@@ -322,6 +322,7 @@ def main():
     ap.add_argument("--root-chunk", type=int, default=None, help="fixed roots per chunk (implies --no-autotune)")
     ap.add_argument("--split", type=int, default=None, choices=(0, 1),
                     help="fixed splitting setting (implies --no-autotune)")
+    ap.add_argument("--split-min", type=int, default=None, help="smallest split window (implies --no-autotune)")
     ap.add_argument("--min-waves", type=int, default=None,
                     help="compile the mining kernels to fit this many waves per SIMD")
     ap.add_argument("--tune-table", default=None,
@@ -359,8 +360,10 @@ def main():
     ctx.set_param(N.TM_PARAM_PROFILE, 1)
     if args.min_waves is not None:
         ctx.set_param(N.TM_PARAM_MIN_WAVES, args.min_waves)
-    if args.root_chunk is not None or args.split is not None:
+    if args.root_chunk is not None or args.split is not None or args.split_min is not None:
         args.no_autotune = True
+        if args.split_min is not None:
+            ctx.set_param(N.TM_PARAM_SPLIT_MIN, args.split_min)
         if args.root_chunk is not None:
             ctx.set_param(N.TM_PARAM_ROOT_CHUNK, args.root_chunk)
         if args.split is not None:
@@ -380,7 +383,7 @@ def main():
     t0 = time.perf_counter()
     counts_b = ctx.count_batch(dg, handles, stream=stream)  # compiles (and tunes) the batched module
     compile_batch_s = time.perf_counter() - t0
-    batch_setting = ctx.last_launch()
+    batch_setting = ctx.last_launch_full()
     log(f"compiled: single {compile_single_s:.2f} s, batch {compile_batch_s:.2f} s")
 
     # work counters (untimed) for the byte model
@@ -433,7 +436,7 @@ def main():
         torch.cuda.synchronize()
         batch_s = (time.perf_counter() - t0) / args.steps
         assert got == counts
-        batch_setting = ctx.last_launch()
+        batch_setting = ctx.last_launch_full()
         log(f"batched: {batch_s * 1e3:.2f} ms/step")
         result_ms = batch_s * 1e3
         value = total_instances / batch_s
@@ -455,7 +458,8 @@ def main():
         if tr.get("kernel_source_hash") == src_hash and tr.get("form") == form:
             for rec in tr.get("records", []):
                 lc = rec["launch"]
-                if (lc["root_chunk"], lc["split"]) == (batch_setting[0], batch_setting[1]):
+                if (lc["root_chunk"], lc["split"], lc.get("split_min", 32) if lc["split"] else 0) == \
+                        (batch_setting[0], batch_setting[1], batch_setting[3] if batch_setting[1] else 0):
                     traffic = rec["bytes_per_launch"]
 
     out = {
@@ -487,7 +491,7 @@ def main():
                   "kernel_source_hash": src_hash},
         "per_query": [{"edges": m.edges, "delta": m.delta, "count": c} for m, c in zip(motifs, counts)],
         "launch": {"autotune": not args.no_autotune, "root_chunk": batch_setting[0], "split": batch_setting[1],
-                   "tuned": batch_setting[2]},
+                   "split_min": batch_setting[3], "tuned": batch_setting[2]},
     }
     if args.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB

@@ -145,12 +145,12 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
  * tuning; only the first call of a key pays for the trials.
  *
  * tm_last_launch: the setting of the last count / batch / enumerate on ctx
- * (root chunk used or its upper bound, split flag, 1 if it came from the
- * tune table). tm_tune_save writes the table as text to path (host string);
+ * (root chunk used or its upper bound, split flag, smallest split window, 1
+ * if it came from the tune table); each output may be NULL. tm_tune_save writes the table as text to path (host string);
  * tm_tune_load merges a saved table into ctx (TM_E_INVALID if the file
  * cannot be read or is not a table; then nothing is merged); tm_tune_clear
  * empties it (n_removed, may be NULL, receives the number of entries). */
-tm_status tm_last_launch(tm_ctx *ctx, int64_t *root_chunk, int32_t *split, int32_t *tuned);
+tm_status tm_last_launch(tm_ctx *ctx, int64_t *root_chunk, int32_t *split, int64_t *split_min, int32_t *tuned);
 tm_status tm_tune_save(tm_ctx *ctx, const char *path);
 tm_status tm_tune_load(tm_ctx *ctx, const char *path);
 tm_status tm_tune_clear(tm_ctx *ctx, int64_t *n_removed);

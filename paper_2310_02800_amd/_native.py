@@ -99,7 +99,7 @@ def lib():
         "tm_set_param": (i32, [P, i32, i64]),
         "tm_get_param": (i32, [P, i32, P]),
         "tm_last_kernel_ms": (i32, [P, P, P]),
-        "tm_last_launch": (i32, [P, P, P, P]),
+        "tm_last_launch": (i32, [P, P, P, P, P]),
         "tm_tune_save": (i32, [P, ctypes.c_char_p]),
         "tm_tune_load": (i32, [P, ctypes.c_char_p]),
         "tm_tune_clear": (i32, [P, P]),

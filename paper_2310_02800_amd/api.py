@@ -199,9 +199,14 @@ class Context:
 
     def last_launch(self):
         """(root chunk, split flag, tuned flag) of the last mining call."""
-        r, sp, tu = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
-        N.check(N.lib().tm_last_launch(self._h, ctypes.byref(r), ctypes.byref(sp), ctypes.byref(tu)))
-        return r.value, sp.value, tu.value
+        return self.last_launch_full()[:3]
+
+    def last_launch_full(self):
+        """(root chunk, split flag, tuned flag, smallest split window) of the last mining call."""
+        r, sp, sm, tu = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        N.check(N.lib().tm_last_launch(self._h, ctypes.byref(r), ctypes.byref(sp), ctypes.byref(sm),
+                                       ctypes.byref(tu)))
+        return r.value, sp.value, tu.value, sm.value
 
     def tune_save(self, path):
         N.check(N.lib().tm_tune_save(self._h, os.fsencode(path)))

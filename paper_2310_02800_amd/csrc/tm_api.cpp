@@ -534,11 +534,12 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *v) {
     }
 }
 
-tm_status tm_last_launch(tm_ctx *ctx, int64_t *root_chunk, int32_t *split, int32_t *tuned) {
+tm_status tm_last_launch(tm_ctx *ctx, int64_t *root_chunk, int32_t *split, int64_t *split_min, int32_t *tuned) {
     if (!ctx) return fail(TM_E_INVALID, "null context");
     std::lock_guard<std::mutex> lk(ctx->prof_mu);
     if (root_chunk) *root_chunk = ctx->last_cfg.rch;
     if (split) *split = ctx->last_cfg.split;
+    if (split_min) *split_min = ctx->last_cfg.split_min;
     if (tuned) *tuned = ctx->last_tuned;
     return TM_OK;
 }
