@@ -42,14 +42,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(st: dict, l: int, n_enum: int = 0) -> int:
-    """Byte model of one query: each root reads src, dst and t (16 B); each
-    window reads two offsets (8 B) and one 8 B time per binary-search probe
-    (ceil(log2(L+1)) probes); each candidate visit reads t and the neighbour
-    (12 B) plus the weight (4 B) at the predicate level; each enumerated
-    instance writes l int64 ids."""
+def method_bytes(st: dict, l: int, n_enum: int = 0) -> int:
+    """Byte model of the method's search for one query: each root reads src,
+    dst and t (16 B); each window reads two offsets (8 B) and one 8 B time per
+    binary-search probe (ceil(log2(L+1)) probes); each candidate visit reads
+    t and the neighbour (12 B) plus the weight (4 B) at the predicate level;
+    each enumerated instance writes l int64 ids."""
     return (16 * st["roots"] + 8 * st["windows"] + 8 * st["probes"] + 12 * st["visits"]
             + 4 * st["pred_visits"] + 8 * l * n_enum)
+
+
+def algorithmic_bytes(st: dict, l: int, n_enum: int = 0) -> int:
+    """Bytes the counting kernels' algorithm reads: the method's search, except
+    that last-level windows counted in closed form read, instead of their
+    candidates (12 B each), the entries their binary searches probe (a
+    neighbour and a time, 12 B each)."""
+    return (method_bytes(st, l, n_enum) - 12 * st.get("leaf_counted_visits", 0)
+            + 12 * st.get("leaf_count_reads", 0))
 
 
 def kernel_source_hash(motifs) -> str:
@@ -323,6 +332,8 @@ def main():
     ap.add_argument("--split", type=int, default=None, choices=(0, 1),
                     help="fixed splitting setting (implies --no-autotune)")
     ap.add_argument("--split-min", type=int, default=None, help="smallest split window (implies --no-autotune)")
+    ap.add_argument("--leaf-min", type=int, default=None,
+                    help="smallest window counted in closed form, 0 = never (implies --no-autotune)")
     ap.add_argument("--min-waves", type=int, default=None,
                     help="compile the mining kernels to fit this many waves per SIMD")
     ap.add_argument("--tune-table", default=None,
@@ -360,8 +371,11 @@ def main():
     ctx.set_param(N.TM_PARAM_PROFILE, 1)
     if args.min_waves is not None:
         ctx.set_param(N.TM_PARAM_MIN_WAVES, args.min_waves)
-    if args.root_chunk is not None or args.split is not None or args.split_min is not None:
+    if (args.root_chunk is not None or args.split is not None or args.split_min is not None
+            or args.leaf_min is not None):
         args.no_autotune = True
+        if args.leaf_min is not None:
+            ctx.set_param(N.TM_PARAM_LEAF_MIN, args.leaf_min)
         if args.split_min is not None:
             ctx.set_param(N.TM_PARAM_SPLIT_MIN, args.split_min)
         if args.root_chunk is not None:
@@ -387,11 +401,12 @@ def main():
     log(f"compiled: single {compile_single_s:.2f} s, batch {compile_batch_s:.2f} s")
 
     # work counters (untimed) for the byte model
-    stats = [ctx.work_stats(dg, h, stream=stream) for h in handles]
+    stats = [ctx.work_stats(dg, h, stream=stream, leaf=True) for h in handles]
     counts = [s["matches"] for s in stats]
     assert counts == counts_b, (counts, counts_b)
     total_instances = sum(counts)
     bytes_per_step = sum(algorithmic_bytes(s, m.l) for s, m in zip(stats, motifs))
+    method_bytes_per_step = sum(method_bytes(s, m.l) for s, m in zip(stats, motifs))
 
     def plain_step(lat):
         for h in handles:
@@ -458,8 +473,10 @@ def main():
         if tr.get("kernel_source_hash") == src_hash and tr.get("form") == form:
             for rec in tr.get("records", []):
                 lc = rec["launch"]
-                if (lc["root_chunk"], lc["split"], lc.get("split_min", 32) if lc["split"] else 0) == \
-                        (batch_setting[0], batch_setting[1], batch_setting[3] if batch_setting[1] else 0):
+                if (lc["root_chunk"], lc["split"], lc.get("split_min", 32) if lc["split"] else 0,
+                        lc.get("leaf_min")) == \
+                        (batch_setting[0], batch_setting[1], batch_setting[3] if batch_setting[1] else 0,
+                         batch_setting[4]):
                     traffic = rec["bytes_per_launch"]
 
     out = {
@@ -485,13 +502,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "tm_count_batch" if form == "batched" else "tm_count", "avg_launch_ms": avg_launch_ms,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "method_bytes_per_launch": method_bytes_per_step / launches_per_step,
+                     "leaf_windows_counted": sum(s["leaf_counted"] for s in stats)},
         "setup": {"generate_s": round(gen_s, 2), "load_graph_s": round(load_s, 3),
                   "compile_single_s": round(compile_single_s, 2), "compile_batch_s": round(compile_batch_s, 2),
                   "kernel_source_hash": src_hash},
         "per_query": [{"edges": m.edges, "delta": m.delta, "count": c} for m, c in zip(motifs, counts)],
         "launch": {"autotune": not args.no_autotune, "root_chunk": batch_setting[0], "split": batch_setting[1],
-                   "split_min": batch_setting[3], "tuned": batch_setting[2]},
+                   "split_min": batch_setting[3], "leaf_min": batch_setting[4], "tuned": batch_setting[2]},
     }
     if args.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB

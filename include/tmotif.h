@@ -113,6 +113,10 @@ void tm_destroy(tm_ctx *ctx);
  *                          (more resident waves hide more memory latency; fewer
  *                          registers each). Kernels compiled with each value are
  *                          cached apart.
+ *   TM_PARAM_LEAF_MIN      counting: a last-level window of at least this many
+ *                          candidates (default 512) whose count has a closed form is
+ *                          counted with binary searches instead of a scan (see
+ *                          tm_work_stats); 0 = always scan; else 32..2^24
  */
 enum {
     TM_PARAM_BLOCK = 1,
@@ -124,7 +128,8 @@ enum {
     TM_PARAM_TIER = 8,
     TM_PARAM_AUTOTUNE = 9,
     TM_PARAM_WORK_BUDGET = 10,
-    TM_PARAM_MIN_WAVES = 11
+    TM_PARAM_MIN_WAVES = 11,
+    TM_PARAM_LEAF_MIN = 12
 };
 tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t value);
 tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
@@ -135,7 +140,8 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
  * TM_PARAM_AUTOTUNE = 1 the first tm_count or tm_count_batch of a key runs
  * its launch under each candidate setting (roots per chunk in {16, 64, 256,
  * 1024}, each with splitting off and with splitting of windows of 32 or more;
- * at 256 roots also splitting from 2, 8 and 128), checks that every trial
+ * at 256 roots also splitting from 2, 8 and 128; then, at the best of those,
+ * TM_PARAM_LEAF_MIN in {0, 128, 2048}), checks that every trial
  * returns the same
  * counts (else TM_E_DEVICE), returns them, and keeps the fastest setting for
  * the key. Later counts, batches and enumerations with the key use it. The
@@ -145,12 +151,14 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
  * tuning; only the first call of a key pays for the trials.
  *
  * tm_last_launch: the setting of the last count / batch / enumerate on ctx
- * (root chunk used or its upper bound, split flag, smallest split window, 1
- * if it came from the tune table); each output may be NULL. tm_tune_save writes the table as text to path (host string);
+ * (root chunk used or its upper bound, split flag, smallest split window,
+ * smallest window counted in closed form, 1 if it came from the tune table);
+ * each output may be NULL. tm_tune_save writes the table as text to path (host string);
  * tm_tune_load merges a saved table into ctx (TM_E_INVALID if the file
  * cannot be read or is not a table; then nothing is merged); tm_tune_clear
  * empties it (n_removed, may be NULL, receives the number of entries). */
-tm_status tm_last_launch(tm_ctx *ctx, int64_t *root_chunk, int32_t *split, int64_t *split_min, int32_t *tuned);
+tm_status tm_last_launch(tm_ctx *ctx, int64_t *root_chunk, int32_t *split, int64_t *split_min, int64_t *leaf_min,
+                         int32_t *tuned);
 tm_status tm_tune_save(tm_ctx *ctx, const char *path);
 tm_status tm_tune_load(tm_ctx *ctx, const char *path);
 tm_status tm_tune_clear(tm_ctx *ctx, int64_t *n_removed);
@@ -298,8 +306,15 @@ tm_status tm_enumerate(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const 
  * read, candidate windows opened, sum over windows of ceil(log2(L+1)) where
  * L is the searched list's length (the shorter of the two lists when both
  * endpoints are mapped), candidates read (including the read that ends a
- * window), candidate reads at the predicate level, and instances.
- * stats_out: host uint64[6]. Blocking like tm_count. */
+ * window), candidate reads at the predicate level, and instances: the
+ * search of the method as the paper describes it (Alg. 1), whatever shortcut
+ * the count kernels take. Then three counters of that shortcut: last-level
+ * windows of TM_PARAM_LEAF_MIN or more candidates whose count has a closed form (both
+ * endpoints bound, or one new endpoint, and no weight predicate on the level),
+ * which the count kernels count with binary searches in per-node lists sorted
+ * by (neighbour, time) instead of scanning; the candidate reads of those
+ * windows (included in the fourth counter); and the reads their counts take.
+ * stats_out: host uint64[9]. Blocking like tm_count. */
 tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
                         hipStream_t stream, uint64_t *stats_out);
 

@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "TM_OK", 1: "TM_E_INVALID", 2: "TM_E_OOM", 3: "TM_E_COMPILE",
 
 TM_PARAM_BLOCK, TM_PARAM_ROOT_CHUNK, TM_PARAM_GRID = 1, 2, 3
 TM_PARAM_PROFILE, TM_PARAM_SPLIT, TM_PARAM_SPLIT_MIN, TM_PARAM_TIER, TM_PARAM_AUTOTUNE = 5, 6, 7, 8, 9
-TM_PARAM_WORK_BUDGET, TM_PARAM_MIN_WAVES = 10, 11
+TM_PARAM_WORK_BUDGET, TM_PARAM_MIN_WAVES, TM_PARAM_LEAF_MIN = 10, 11, 12
 
 # Every function the header declares, for the export check.
 EXPORTED = [
@@ -99,7 +99,7 @@ def lib():
         "tm_set_param": (i32, [P, i32, i64]),
         "tm_get_param": (i32, [P, i32, P]),
         "tm_last_kernel_ms": (i32, [P, P, P]),
-        "tm_last_launch": (i32, [P, P, P, P, P]),
+        "tm_last_launch": (i32, [P, P, P, P, P, P]),
         "tm_tune_save": (i32, [P, ctypes.c_char_p]),
         "tm_tune_load": (i32, [P, ctypes.c_char_p]),
         "tm_tune_clear": (i32, [P, P]),

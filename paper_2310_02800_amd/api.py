@@ -202,11 +202,12 @@ class Context:
         return self.last_launch_full()[:3]
 
     def last_launch_full(self):
-        """(root chunk, split flag, tuned flag, smallest split window) of the last mining call."""
-        r, sp, sm, tu = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        """(root chunk, split flag, tuned flag, smallest split window, smallest
+        window counted in closed form) of the last mining call."""
+        r, sp, sm, lm, tu = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
         N.check(N.lib().tm_last_launch(self._h, ctypes.byref(r), ctypes.byref(sp), ctypes.byref(sm),
-                                       ctypes.byref(tu)))
-        return r.value, sp.value, tu.value, sm.value
+                                       ctypes.byref(lm), ctypes.byref(tu)))
+        return r.value, sp.value, tu.value, sm.value, lm.value
 
     def tune_save(self, path):
         N.check(N.lib().tm_tune_save(self._h, os.fsencode(path)))
@@ -253,12 +254,16 @@ class Context:
                                  _stream_handle(stream), ctypes.byref(out)))
         return out.value
 
-    def work_stats(self, g: Graph, m: Motif, t_lo=None, t_hi=None, stream=None) -> dict:
+    def work_stats(self, g: Graph, m: Motif, t_lo=None, t_hi=None, stream=None, leaf=False) -> dict:
+        """The method's work counters (as the oracle's); with leaf=True also
+        the counters of the closed-form last-level counts."""
         rr = _range(t_lo, t_hi)
-        st = np.zeros(6, np.uint64)
+        st = np.zeros(9, np.uint64)
         N.check(N.lib().tm_work_stats(self._h, g.handle, m.handle, None if rr is None else ctypes.byref(rr),
                                       _stream_handle(stream), _ptr(st)))
         keys = ("roots", "windows", "probes", "visits", "pred_visits", "matches")
+        if leaf:
+            keys += ("leaf_counted", "leaf_counted_visits", "leaf_count_reads")
         return {k: int(v) for k, v in zip(keys, st)}
 
     def enumerate_into(self, g: Graph, m: Motif, out_ptr: int, capacity: int, t_lo=None, t_hi=None,

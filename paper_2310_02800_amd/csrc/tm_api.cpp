@@ -44,7 +44,7 @@ struct DeviceGuard {
 
 void free_graph_buffers(tm_graph *g) {
     void *ptrs[] = {g->d_src, g->d_dst, g->d_tk, g->d_w, g->d_adj_t, g->d_adj_nbr, g->d_adj_eid, g->d_adj_w,
-                    g->d_off_out, g->d_off_in, g->d_pos_out, g->d_pos_in};
+                    g->d_off_out, g->d_off_in, g->d_pos_out, g->d_pos_in, g->d_pr_nbr, g->d_pr_t};
     for (void *p : ptrs)
         if (p) hipFree(p);
 }
@@ -143,6 +143,7 @@ tmo::LaunchCfg default_cfg(const tm_ctx *ctx) {
     c.rch = ctx->root_chunk;
     c.split = ctx->split;
     c.split_min = ctx->split_min;
+    c.leaf_min = ctx->leaf_min;
     c.timed = ctx->profile != 0;
     return c;
 }
@@ -184,6 +185,8 @@ GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w, const tmo::LaunchCfg &c
     a.off_in = g->d_off_in;
     a.pos_out = g->d_pos_out;
     a.pos_in = g->d_pos_in;
+    a.pr_nbr = g->d_pr_nbr;
+    a.pr_t = g->d_pr_t;
     a.qa = (const QArgs *)w->qa;
     a.ctl = w->ctl;
     a.counts = w->counts;
@@ -191,7 +194,7 @@ GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w, const tmo::LaunchCfg &c
     a.chunk_off = w->chunk_off;
     a.m_edges = g->m;
     a.split = c.split;
-    a.split_min = (int32_t)c.split_min;
+    a.leaf_min = (int32_t)c.leaf_min;
     return a;
 }
 
@@ -310,7 +313,7 @@ std::string tune_key(const tm_graph *g, const std::string &mod, int64_t delta, i
     return std::string(buf) + mod;
 }
 
-std::vector<tmo::LaunchCfg> tune_candidates(int64_t roots) {
+std::vector<tmo::LaunchCfg> tune_candidates(const tm_ctx *ctx, int64_t roots) {
     std::vector<tmo::LaunchCfg> out;
     auto add = [&](int64_t rch, int split, int64_t smin) {
         tmo::LaunchCfg c;
@@ -318,6 +321,7 @@ std::vector<tmo::LaunchCfg> tune_candidates(int64_t roots) {
         c.exact = true;
         c.split = split;
         c.split_min = smin;
+        c.leaf_min = ctx->leaf_min;
         c.timed = true;
         out.push_back(c);
     };
@@ -346,6 +350,7 @@ bool tune_lookup(tm_ctx *ctx, const std::string &key, tmo::LaunchCfg *c) {
     c->exact = true;
     c->split = it->second.split;
     c->split_min = it->second.split_min;
+    c->leaf_min = it->second.leaf_min;
     return true;
 }
 
@@ -377,7 +382,7 @@ tm_status run_tuned(tm_ctx *ctx, const std::string &key, int64_t roots, F &&once
             double best = 0;
             tmo::LaunchCfg best_c;
             bool have = false;
-            for (const tmo::LaunchCfg &c : tune_candidates(roots)) {
+            auto trial = [&](const tmo::LaunchCfg &c) -> tm_status {
                 double ms = 0;
                 std::vector<uint64_t> r;
                 tm_status st = once(c, &ms, &r);
@@ -398,6 +403,23 @@ tm_status run_tuned(tm_ctx *ctx, const std::string &key, int64_t roots, F &&once
                     best_c = c;
                 }
                 have = true;
+                return TM_OK;
+            };
+            // stage 1: roots per chunk and splitting; stage 2: the closed-form
+            // threshold at the best of those
+            for (const tmo::LaunchCfg &c : tune_candidates(ctx, roots)) {
+                const tm_status st = trial(c);
+                if (st != TM_OK) return st;
+            }
+            if (have) {
+                const tmo::LaunchCfg base_c = best_c;
+                for (int64_t lm : {int64_t(0), int64_t(128), int64_t(2048)}) {
+                    if (lm == base_c.leaf_min) continue;
+                    tmo::LaunchCfg c = base_c;
+                    c.leaf_min = lm;
+                    const tm_status st = trial(c);
+                    if (st != TM_OK) return st;
+                }
             }
             if (have) {
                 std::lock_guard<std::mutex> lk(ctx->tune_mu);
@@ -405,6 +427,7 @@ tm_status run_tuned(tm_ctx *ctx, const std::string &key, int64_t roots, F &&once
                 e.rch = best_c.rch;
                 e.split = best_c.split;
                 e.split_min = best_c.split_min;
+                e.leaf_min = best_c.leaf_min;
                 e.ms = best;
                 ctx->tune[key] = e;
             }
@@ -512,6 +535,10 @@ tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t v) {
         if (v < 0 || v > 8) return fail(TM_E_INVALID, "min waves per SIMD must be in [0, 8]");
         ctx->min_waves = (int)v;
         return TM_OK;
+    case TM_PARAM_LEAF_MIN:
+        if (v != 0 && (v < 32 || v > (1 << 24))) return fail(TM_E_INVALID, "leaf minimum must be 0 or in [32, 2^24]");
+        ctx->leaf_min = v;
+        return TM_OK;
     default:
         return fail(TM_E_INVALID, "unknown parameter");
     }
@@ -530,29 +557,32 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *v) {
     case TM_PARAM_AUTOTUNE: *v = ctx->autotune; return TM_OK;
     case TM_PARAM_WORK_BUDGET: *v = ctx->work_budget; return TM_OK;
     case TM_PARAM_MIN_WAVES: *v = ctx->min_waves; return TM_OK;
+    case TM_PARAM_LEAF_MIN: *v = ctx->leaf_min; return TM_OK;
     default: return fail(TM_E_INVALID, "unknown parameter");
     }
 }
 
-tm_status tm_last_launch(tm_ctx *ctx, int64_t *root_chunk, int32_t *split, int64_t *split_min, int32_t *tuned) {
+tm_status tm_last_launch(tm_ctx *ctx, int64_t *root_chunk, int32_t *split, int64_t *split_min, int64_t *leaf_min,
+                         int32_t *tuned) {
     if (!ctx) return fail(TM_E_INVALID, "null context");
     std::lock_guard<std::mutex> lk(ctx->prof_mu);
     if (root_chunk) *root_chunk = ctx->last_cfg.rch;
     if (split) *split = ctx->last_cfg.split;
     if (split_min) *split_min = ctx->last_cfg.split_min;
+    if (leaf_min) *leaf_min = ctx->last_cfg.leaf_min;
     if (tuned) *tuned = ctx->last_tuned;
     return TM_OK;
 }
 
 tm_status tm_tune_save(tm_ctx *ctx, const char *path) {
     if (!ctx || !path) return fail(TM_E_INVALID, "null argument");
-    std::string text = "tmotif-tune 1\n";
+    std::string text = "tmotif-tune 2\n";
     {
         std::lock_guard<std::mutex> lk(ctx->tune_mu);
         char buf[128];
         for (const auto &kv : ctx->tune) {
-            std::snprintf(buf, sizeof(buf), " %lld %d %lld %.6f\n", (long long)kv.second.rch, kv.second.split,
-                          (long long)kv.second.split_min, kv.second.ms);
+            std::snprintf(buf, sizeof(buf), " %lld %d %lld %lld %.6f\n", (long long)kv.second.rch, kv.second.split,
+                          (long long)kv.second.split_min, (long long)kv.second.leaf_min, kv.second.ms);
             text += kv.first + buf;
         }
     }
@@ -573,7 +603,7 @@ tm_status tm_tune_load(tm_ctx *ctx, const char *path) {
     while ((got_bytes = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got_bytes);
     std::fclose(f);
     const std::string bad = std::string("not a tune table: ") + path;
-    const std::string head = "tmotif-tune 1\n";
+    const std::string head = "tmotif-tune 2\n";
     if (text.compare(0, head.size(), head) != 0) return fail(TM_E_INVALID, bad);
     std::map<std::string, tmo::TuneEntry> got;
     size_t pos = head.size();
@@ -584,17 +614,19 @@ tm_status tm_tune_load(tm_ctx *ctx, const char *path) {
         pos = eol + 1;
         const size_t sp = line.find(' ');
         if (sp == 0 || sp == std::string::npos) return fail(TM_E_INVALID, bad);
-        long long rch = 0, smin = 0;
+        long long rch = 0, smin = 0, lmin = 0;
         int split = 0;
         double ms = 0;
         char tail = 0;
-        if (std::sscanf(line.c_str() + sp, " %lld %d %lld %lf %c", &rch, &split, &smin, &ms, &tail) != 4 ||
-            rch < 1 || rch > (1 << 24) || (split != 0 && split != 1) || smin < 2)
+        if (std::sscanf(line.c_str() + sp, " %lld %d %lld %lld %lf %c", &rch, &split, &smin, &lmin, &ms, &tail) != 5 ||
+            rch < 1 || rch > (1 << 24) || (split != 0 && split != 1) || smin < 2 ||
+            (lmin != 0 && (lmin < 32 || lmin > (1 << 24))))
             return fail(TM_E_INVALID, bad);
         tmo::TuneEntry e;
         e.rch = rch;
         e.split = split;
         e.split_min = smin;
+        e.leaf_min = lmin;
         e.ms = ms;
         got[line.substr(0, sp)] = e;
     }
@@ -731,6 +763,16 @@ tm_status tm_load_graph(tm_ctx *ctx, int64_t n, int64_t m, const int32_t *src, c
         e = tmo::dev_build_csr(n, m, g->d_dst, g->d_src, g->d_tk, g->key_bytes, g->d_w, (uint32_t)m, g->d_off_in,
                               g->d_adj_t, g->d_adj_nbr, g->d_adj_eid, g->d_adj_w, g->d_pos_in, s);
     if (e != hipSuccess) return cleanup(hip_fail(e, "adjacency build"));
+    // the same lists sorted by (neighbour, time): out at [0, m), in at [m, 2m)
+    e = dmalloc(&g->d_pr_nbr, 2 * m, &acc);
+    if (e == hipSuccess) e = hipMalloc(&g->d_pr_t, std::max<int64_t>(2 * m, 1) * g->key_bytes);
+    if (e == hipSuccess) acc += std::max<int64_t>(2 * m, 1) * g->key_bytes;
+    if (e != hipSuccess) return cleanup(hip_fail(e, "pair list allocation"));
+    e = tmo::dev_build_pairs(n, m, g->d_src, g->d_dst, g->d_tk, g->key_bytes, g->d_pr_nbr, g->d_pr_t, s);
+    if (e == hipSuccess)
+        e = tmo::dev_build_pairs(n, m, g->d_dst, g->d_src, g->d_tk, g->key_bytes, g->d_pr_nbr + m,
+                                 (char *)g->d_pr_t + m * g->key_bytes, s);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "pair list build"));
     g->device_bytes = acc;
     hipStreamDestroy(s);
     *out = g;
@@ -947,6 +989,7 @@ tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const
     HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
     for (int i = 0; i < 5; i++) stats_out[i] = w->h_ctl[tmo::CTL_STATS + i];
     stats_out[5] = w->h_counts[0];
+    for (int i = 0; i < 3; i++) stats_out[6 + i] = w->h_ctl[tmo::CTL_LEAF + i];
     return TM_OK;
 }
 

@@ -157,12 +157,13 @@ struct GArgs {
   u64* counts;
   u64* chunk_cnt; const u64* chunk_off; i64* out; u64 capacity;
   i64 m_edges; i64 total_chunks; int rch; int nq;
-  int split; int split_min;
+  int split; int leaf_min;
   u32* items; u64* qctl; u32 item_cap; u32 epoch;
   const u32* pos_out; const u32* pos_in;
+  const int* pr_nbr; const tkey* pr_t;
 };
 static_assert(sizeof(QArgs) == 192, "QArgs layout");
-static_assert(sizeof(GArgs) == 208, "GArgs layout");
+static_assert(sizeof(GArgs) == 224, "GArgs layout");
 // generic matchers: motif node slot by run-time index, and the bound-node check
 #define mget(ix) ((ix) == 0 ? m0 : (ix) == 1 ? m1 : (ix) == 2 ? m2 : (ix) == 3 ? m3 : \
                   (ix) == 4 ? m4 : (ix) == 5 ? m5 : (ix) == 6 ? m6 : m7)
@@ -203,6 +204,54 @@ __device__ __forceinline__ bool pred_ok(float w, int op, float th) {
   return op == 0 ? (w >= th) : op == 1 ? (w > th) : op == 2 ? (w <= th) : (w < th);
 }
 __device__ __forceinline__ u32 bitlen(u32 x) { return x ? 32u - (u32)__builtin_clz(x) : 0u; }
+// Counting a last-level window without scanning it. `pr` counts the reads.
+// Entries of [c, e) (sorted by time) with time <= t, galloping from c.
+__device__ __forceinline__ u32 win_len(const tkey* at, u32 c, u32 e, tkey t, u32& pr) {
+  u32 lo = c, bound = e;
+  for (u64 step = 1u;; step <<= 1) {
+    const u64 q = (u64)lo + step - 1u;
+    if (q >= (u64)e) { bound = e; break; }
+    ++pr;
+    if (at[q] > t) { bound = (u32)q; break; }
+    lo = (u32)q + 1u;
+  }
+  u32 n = bound - lo;
+  while (n > 0u) { const u32 h = n >> 1, m = lo + h; ++pr; if (at[m] <= t) { lo = m + 1u; n -= h + 1u; } else n = h; }
+  return lo - c;
+}
+// In one node's list [lo, hi) sorted by (neighbour, time): the first entry
+// with neighbour >= x.
+__device__ __forceinline__ u32 nbr_lb(const int* pn, u32 lo, u32 hi, int x, u32& pr) {
+  u32 n = hi - lo;
+  while (n > 0u) { const u32 h = n >> 1, m = lo + h; ++pr; if (pn[m] < x) { lo = m + 1u; n -= h + 1u; } else n = h; }
+  return lo;
+}
+// From s (the first entry with neighbour x), the first entry past those with
+// neighbour x and time <= t: galloping, then binary search.
+__device__ __forceinline__ u32 run_ub(const int* pn, const tkey* pt, u32 s, u32 hi, int x, tkey t, u32& pr) {
+  u32 lo = s, bound = hi;
+  for (u64 step = 1u;; step <<= 1) {
+    const u64 q = (u64)lo + step - 1u;
+    if (q >= (u64)hi) { bound = hi; break; }
+    ++pr;
+    if (pn[q] != x || pt[q] > t) { bound = (u32)q; break; }
+    lo = (u32)q + 1u;
+  }
+  u32 n = bound - lo;
+  while (n > 0u) {
+    const u32 h = n >> 1, m = lo + h; ++pr;
+    if (pn[m] == x && pt[m] <= t) { lo = m + 1u; n -= h + 1u; } else n = h;
+  }
+  return lo;
+}
+// Entries of [lo, hi) with neighbour x and time in (t0, t1], t0 < t1.
+__device__ __forceinline__ u32 pair_cnt(const int* pn, const tkey* pt, u32 lo, u32 hi, int x, tkey t0, tkey t1,
+                                        u32& pr) {
+  const u32 s = nbr_lb(pn, lo, hi, x, pr);
+  ++pr;
+  if (s >= hi || pn[s] != x) return 0u;
+  return run_ub(pn, pt, s, hi, x, t1, pr) - run_ub(pn, pt, s, hi, x, t0, pr);
+}
 // read lane `src`'s value (all 64 lanes must be active)
 __device__ __forceinline__ int shf(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
 __device__ __forceinline__ u32 shf(u32 v, int src) { return (u32)__builtin_amdgcn_ds_bpermute(src << 2, (int)v); }
@@ -595,6 +644,102 @@ struct Emitter {
 
     bool coop_ok() const { return p.l > 1 && (G || p.kind[p.l - 1] != LIST_GLOBAL); }
 
+    // Whether the last level's count has a closed form: both endpoints bound
+    // (the edges between two given nodes in the time window), or one new
+    // endpoint (the window's size minus the edges to each already bound node,
+    // the node itself included, since the new node must differ from all of
+    // them). Not with a weight predicate on that level. Generic matchers decide
+    // at run time.
+    bool leaf_countable() const {
+        const int i = p.l - 1;
+        return G || (p.l > 1 && p.kind[i] != LIST_GLOBAL && p.pred_level != i);
+    }
+
+    // Closed-form count of the last level's window (registers cur, end, hi of
+    // that level and sx = the previous edge's time) into lc_; w_ = the
+    // window's length when computed; pr_ = entries read.
+    void leaf_body(int i, const char *in, bool need_w) {
+        const std::string s = I(i);
+        o << in << "u32 pr_ = 0u; u64 lc_ = 0; u32 w_ = 0u;\n";
+        if (G) {
+            o << in << "if (gk" << s << " == 2) {\n";
+            o << in << "  const int u_ = mget(ga" << s << ");\n";
+            o << in << "  lc_ = pair_cnt(g.pr_nbr, g.pr_t, g.off_out[u_], g.off_out[u_ + 1], mget(gb" << s
+              << "), sx, hi" << s << ", pr_);\n";
+            if (need_w)
+                o << in << "  w_ = win_len(g.adj_t, cur" << s << ", end" << s << ", hi" << s << ", pr_);\n";
+            o << in << "} else {\n";
+            o << in << "  const bool o_ = gk" << s << " == 0; const int u_ = o_ ? mget(ga" << s << ") : mget(gb" << s
+              << ");\n";
+            o << in << "  const u32 plo = o_ ? g.off_out[u_] : g.off_in[u_], phi = o_ ? g.off_out[u_ + 1] : "
+              << "g.off_in[u_ + 1];\n";
+            o << in << "  w_ = win_len(g.adj_t, cur" << s << ", end" << s << ", hi" << s << ", pr_); lc_ = w_;\n";
+            o << in << "  for (int v_ = 0; v_ < 8; ++v_)\n";
+            o << in << "    if ((gm" << s << " >> v_) & 1u) lc_ -= pair_cnt(g.pr_nbr, g.pr_t, plo, phi, mget(v_), sx, hi"
+              << s << ", pr_);\n";
+            o << in << "}\n";
+        } else if (p.kind[i] == LIST_BOTH) {
+            o << in << "lc_ = pair_cnt(g.pr_nbr, g.pr_t, g.off_out[m" << p.a[i] << "], g.off_out[m" << p.a[i]
+              << " + 1], m" << p.b[i] << ", sx, hi" << s << ", pr_);\n";
+            if (need_w) o << in << "w_ = win_len(g.adj_t, cur" << s << ", end" << s << ", hi" << s << ", pr_);\n";
+        } else {
+            const bool out = p.kind[i] == LIST_OUT;
+            const int u = out ? p.a[i] : p.b[i];
+            const char *off = out ? "g.off_out" : "g.off_in";
+            o << in << "const u32 plo = " << off << "[m" << u << "], phi = " << off << "[m" << u << " + 1];\n";
+            o << in << "w_ = win_len(g.adj_t, cur" << s << ", end" << s << ", hi" << s << ", pr_); lc_ = w_;\n";
+            for (int v : p.mapped[i])
+                o << in << "lc_ -= pair_cnt(g.pr_nbr, g.pr_t, plo, phi, m" << v << ", sx, hi" << s << ", pr_);\n";
+        }
+    }
+
+    // At the end of the last level's window search. Count modes: a window of
+    // g.leaf_min or more candidates whose count has a closed form parks its
+    // lane (phase 3) until the wavefront counts the parked windows together
+    // (park_flush). The work-counter mode, which still scans (the byte model
+    // of the method), computes the same count on the side to record what the
+    // count modes read instead.
+    void leaf_count(int i) {
+        if (!leaf_countable()) return;
+        const std::string s = I(i);
+        const char *ind = "            ";
+        const std::string gc = G ? " && gpl != " + s : std::string();
+        o << ind << "if ((MODE == 0 || MODE == 2) && wide && g.leaf_min > 0 && sb + (u32)g.leaf_min - 1u < end" << s
+          << " && g.adj_t[sb + (u32)g.leaf_min - 1u] <= hi" << s << gc << ") park = true;\n";
+        const std::string gcond = G ? " && !((gglob >> " + s + ") & 1u) && gpl != " + s : std::string();
+        o << ind << "if (MODE == 1 && g.leaf_min > 0" << gcond << ") {\n";
+        o << ind << "  const u32 pk = sb + (u32)g.leaf_min - 1u;\n";
+        o << ind << "  if (pk < end" << s << " && g.adj_t[pk] <= hi" << s << ") {\n";
+        leaf_body(i, "                ", true);
+        o << ind << "    st_lc++; st_lcp += pr_;\n";
+        o << ind << "    st_lcw += (u64)w_ + (cur" << s << " + w_ < end" << s << " ? 1u : 0u);\n";
+        o << ind << "  }\n";
+        o << ind << "}\n";
+    }
+
+    // Count the parked windows: once half the wavefront is parked, or no
+    // other lane can move, every parked lane runs its closed form at the same
+    // time (their searches overlap instead of running one lane at a time),
+    // then backtracks as if it had scanned the window.
+    void park_flush() {
+        if (!leaf_countable()) return;
+        const int i = p.l - 1;
+        o << "    if (MODE == 0 || MODE == 2) {\n";
+        o << "      const u64 parked = ballot(ph == 3);\n";
+        o << "      if (parked != 0ull && (__builtin_popcountll(parked) >= 32 || ballot(lvl >= 0 && ph != 3) == 0ull)) {\n";
+        o << "        if (ph == 3) {\n";
+        leaf_body(i, "          ", false);
+        o << "          if (MODE == 2) rcnt += lc_; else cnt += lc_;\n";
+        o << "          ph = 0; wide = false; lvl = " << i - 1 << ";\n";
+        o << "          if (lvl < base) {\n";
+        o << "            lvl = 0;\n";
+        o << "            if (MODE == 2 && rcnt) { atomicAdd(&g.chunk_cnt[mych], rcnt); cnt += rcnt; rcnt = 0; }\n";
+        o << "          }\n";
+        o << "        }\n";
+        o << "      }\n";
+        o << "    }\n";
+    }
+
     // Wavefront-cooperative last level. A lane whose last-level window is
     // wide hands it to the whole wavefront: the 64 lanes read 64 consecutive
     // candidates per step (coalesced), apply the owner's checks, and one
@@ -708,6 +853,7 @@ struct Emitter {
         }
         o << "  tkey tmaxk = 0, sx = 0; u32 sb = 0u, sn = 0u;\n";
         o << "  u64 cnt = 0, rcnt = 0, st_win = 0, st_probe = 0, st_visit = 0, st_pv = 0, st_root = 0;\n";
+        o << "  u64 st_lc = 0, st_lcw = 0, st_lcp = 0;  // windows counted without a scan: number, visits, reads\n";
         o << "  u32 iter = 0u, steps = 0u; i64 ghungry = 0;\n";
         o << "  i64 pnext = 0, pend = 0, pchunk = chunk, pending = -1;\n";
         o << "  bool drained = chunk < 0;\n";
@@ -799,9 +945,10 @@ struct Emitter {
         o << "    }\n";
         if (L > 1) steal();
         if (L > 1 && coop_ok()) coop();
+        if (L > 1 && coop_ok()) park_flush();
         if (L > 1) {
             // ---------------- search probe
-            o << "    if (lvl > 0 && ph >= 1) {\n";
+            o << "    if (lvl > 0 && (ph == 1 || ph == 2)) {\n";
             if (G) {
                 o << "      const tkey* sarr = ((gglob >> lvl) & 1u) ? g.tk : g.adj_t;\n";
             } else if (glob) {
@@ -818,14 +965,17 @@ struct Emitter {
             o << "      if (v <= sx) { sb = mid + 1u; sn = sn - half - 1u; } else { sn = half; }\n";
             o << "      ph = 1;\n";
             o << "      if (sn == 0u) {\n";
+            o << "        bool park = false;\n";
             o << "        switch (lvl) {\n";
             for (int i = 1; i < L; i++) {
                 if (i == L - 1 && coop_ok()) {
                     // peek 32 candidates ahead: a window that reaches that far is
-                    // scanned by the whole wavefront
+                    // scanned by the whole wavefront, or, when counting and the
+                    // window's count has a closed form, counted without a scan
                     o << "          case " << i << ": cur" << i << " = sb;\n";
                     o << "            if (MODE != 1" << (G ? " && !((gglob >> " + I(i) + ") & 1u)" : std::string())
                       << ") { const u32 pk = sb + 31u; wide = pk < end" << i << " && g.adj_t[pk] <= hi" << i << "; }\n";
+                    leaf_count(i);
                     o << "            break;\n";
                 } else {
                     o << "          case " << i << ": cur" << i << " = sb; break;\n";
@@ -833,9 +983,9 @@ struct Emitter {
             }
             o << "          default: break;\n";
             o << "        }\n";
-            o << "        ph = 0;\n";
+            o << "        ph = park ? 3 : 0;\n";
             o << "      }\n";
-            o << "    } else if (lvl > 0) {\n";
+            o << "    } else if (lvl > 0 && ph == 0) {\n";
             // ---------------- candidate scan
             o << "      u32 c = 0u, e = 0u; tkey h = 0;\n";
             o << "      switch (lvl) {\n";
@@ -965,6 +1115,8 @@ struct Emitter {
         o << "    u64 v3 = wave_sum(st_visit, lane), v4 = wave_sum(st_pv, lane);\n";
         o << "    if (lane == 0) { atomicAdd(&g.ctl[2], v0); atomicAdd(&g.ctl[3], v1); atomicAdd(&g.ctl[4], v2);\n";
         o << "                     atomicAdd(&g.ctl[5], v3); atomicAdd(&g.ctl[6], v4); }\n";
+        o << "    u64 v5 = wave_sum(st_lc, lane), v6 = wave_sum(st_lcw, lane), v7 = wave_sum(st_lcp, lane);\n";
+        o << "    if (lane == 0) { atomicAdd(&g.ctl[10], v5); atomicAdd(&g.ctl[11], v6); atomicAdd(&g.ctl[12], v7); }\n";
         o << "  }\n";
         o << "  return pending;\n";
         o << "}\n\n";

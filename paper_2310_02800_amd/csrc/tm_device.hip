@@ -105,6 +105,21 @@ __global__ void k_gather_adj(int64_t m, const int32_t *eids, const int32_t *othe
 // makes the check report this helper's own launches.
 void clear_stale_error() { (void)hipGetLastError(); }
 
+__global__ void k_pair_keys(int64_t m, const int32_t *key, const int32_t *other, uint64_t *k64) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        k64[i] = ((uint64_t)(uint32_t)key[i] << 32) | (uint64_t)(uint32_t)other[i];
+}
+
+template <typename K>
+__global__ void k_gather_pairs(int64_t m, const int32_t *ids, const int32_t *other, const K *tk, int32_t *pr_nbr,
+                               K *pr_t) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e = ids[i];
+        pr_nbr[i] = other[e];
+        pr_t[i] = tk[e];
+    }
+}
+
 int bits_for(int64_t n) {
     int b = 1;
     while (b < 31 && (int64_t(1) << b) < n) b++;
@@ -178,6 +193,52 @@ hipError_t dev_make_keys(int64_t m, const int64_t *d_t, int64_t t_min, int key_b
     else
         k_make_keys<int64_t><<<blocks_for(m), kThreads, 0, s>>>(m, d_t, t_min, (int64_t *)d_tk);
     return hipGetLastError();
+}
+
+// Per-node lists sorted by (neighbour, time), for counting the edges between
+// two given nodes inside a time window with binary searches. Same grouping by
+// node (and so the same offsets) as the time-sorted lists below.
+hipError_t dev_build_pairs(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
+                           int key_bytes, int32_t *d_pr_nbr, void *d_pr_t, hipStream_t s) {
+    clear_stale_error();
+    if (m <= 0) return hipSuccess;
+    hipError_t e = hipSuccess;
+    uint64_t *k_in = nullptr, *k_out = nullptr;
+    int32_t *ids_in = nullptr, *ids_out = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    const int end_bit = 32 + bits_for(n);
+    e = hipMalloc(&k_in, m * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&k_out, m * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&ids_in, m * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&ids_out, m * sizeof(int32_t));
+    if (e != hipSuccess) goto done;
+    k_pair_keys<<<blocks_for(m), kThreads, 0, s>>>(m, d_key, d_other, k_in);
+    k_iota_i32<<<blocks_for(m), kThreads, 0, s>>>(ids_in, m);
+    // radix sort is stable: equal (node, neighbour) keys keep edge-id order,
+    // which is time order
+    e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k_in, k_out, ids_in, ids_out, (int)m, 0, end_bit, s);
+    if (e != hipSuccess) goto done;
+    e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1);
+    if (e != hipSuccess) goto done;
+    e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, k_in, k_out, ids_in, ids_out, (int)m, 0, end_bit, s);
+    if (e != hipSuccess) goto done;
+    if (key_bytes == 4)
+        k_gather_pairs<int32_t><<<blocks_for(m), kThreads, 0, s>>>(m, ids_out, d_other, (const int32_t *)d_tk,
+                                                                    d_pr_nbr, (int32_t *)d_pr_t);
+    else
+        k_gather_pairs<int64_t><<<blocks_for(m), kThreads, 0, s>>>(m, ids_out, d_other, (const int64_t *)d_tk,
+                                                                    d_pr_nbr, (int64_t *)d_pr_t);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+done:
+    hipStreamSynchronize(s);
+    hipFree(tmp);
+    hipFree(ids_out);
+    hipFree(ids_in);
+    hipFree(k_out);
+    hipFree(k_in);
+    return e;
 }
 
 // Build one direction of the adjacency. d_key = the node that owns the list

@@ -66,17 +66,21 @@ struct GArgs {
     int32_t rch;              // roots per chunk
     int32_t nq;
     int32_t split;            // 1 = idle lanes take pending candidates from busy lanes
-    int32_t split_min;        // smallest pending index range worth a split search
+    int32_t leaf_min;         // smallest last-level window counted in closed form (0 = never)
     uint32_t *items;          // donated work items, item_cap per query, 32 words each
     uint64_t *qctl;           // per query: (head, tail) of its item queue
     uint32_t item_cap;
     uint32_t epoch;           // launch number; an item is ready when its word 0 equals it
     const uint32_t *pos_out;  // per edge: its position in its source's out-list
     const uint32_t *pos_in;   // per edge: its position in its destination's in-list
+    const int32_t *pr_nbr;    // adjacency sorted by (neighbour, time), same offsets
+    const void *pr_t;
 };
-static_assert(sizeof(GArgs) == 208, "GArgs layout");
+static_assert(sizeof(GArgs) == 224, "GArgs layout");
 
-enum { CTL_CURSOR = 0, CTL_OVERFLOW = 1, CTL_STATS = 2, CTL_ERROR = 7, CTL_BUSY = 8, CTL_HUNGRY = 9, CTL_WORDS = 16 };
+// ctl words: [10..12] work counters of the windows counted without a scan
+enum { CTL_CURSOR = 0, CTL_OVERFLOW = 1, CTL_STATS = 2, CTL_ERROR = 7, CTL_BUSY = 8, CTL_HUNGRY = 9,
+       CTL_LEAF = 10, CTL_WORDS = 16 };
 constexpr uint32_t kItemWords = 32;
 constexpr uint64_t kItemsTotal = uint64_t(1) << 20;  // donated work items per launch (128 MiB)
 enum Mode { MODE_COUNT = 0, MODE_STATS = 1, MODE_ENUM_COUNT = 2, MODE_ENUM_WRITE = 3, MODE_COUNT_ = 4 };
@@ -132,6 +136,8 @@ bool compile_to_code(const std::string &src, std::vector<char> *code, std::strin
 bool cached_code(const std::string &src, std::vector<char> *code, std::string *err);
 
 // device helpers (tm_device.hip)
+hipError_t dev_build_pairs(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
+                           int key_bytes, int32_t *d_pr_nbr, void *d_pr_t, hipStream_t s);
 hipError_t dev_build_csr(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
                          int key_bytes, const float *d_w, uint32_t add, uint32_t *d_off, void *d_adj_t,
                          int32_t *d_adj_nbr, int32_t *d_adj_eid, float *d_adj_w, uint32_t *d_pos, hipStream_t s);
@@ -155,6 +161,7 @@ struct LaunchCfg {
     bool exact = false;     // use rch as is instead of shrinking it for small ranges
     int split = 0;          // hand pending windows of busy lanes to idle lanes / wavefronts
     int64_t split_min = 2;  // smallest pending window worth splitting
+    int64_t leaf_min = 512; // smallest last-level window counted in closed form (0 = never)
     bool timed = false;     // record HIP events around the launch
 };
 
@@ -163,6 +170,7 @@ struct TuneEntry {
     int64_t rch = 0;
     int split = 0;
     int64_t split_min = 2;
+    int64_t leaf_min = 512;
     double ms = 0.0;
 };
 
@@ -179,6 +187,7 @@ struct tm_ctx {
     int64_t split_min = 32;
     int tier = 0;  // 0: kernels specialised per motif structure, 1: generic per motif length
     int min_waves = 0;  // waves per SIMD the kernels are compiled to fit (0: compiler's choice)
+    int64_t leaf_min = 512;  // smallest last-level window counted in closed form (0 = never)
     int autotune = 0;
     int64_t work_budget = 0;  // wavefront loop steps per query (0 = no limit)
     std::mutex tune_mu;
@@ -228,6 +237,8 @@ struct tm_graph {
     float *d_adj_w = nullptr;
     uint32_t *d_off_out = nullptr, *d_off_in = nullptr;
     uint32_t *d_pos_out = nullptr, *d_pos_in = nullptr;
+    int32_t *d_pr_nbr = nullptr;  // adjacency sorted by (neighbour, time): out [0,m), in [m,2m)
+    void *d_pr_t = nullptr;
     std::vector<int64_t> h_t;     // sorted absolute times (root-range lookup)
     std::vector<int64_t> perm;    // empty when the input was sorted
     int64_t device_bytes = 0;

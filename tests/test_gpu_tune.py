@@ -129,7 +129,7 @@ def test_tune_table_round_trip(tuned, tiny_g, tiny_og, tmp_path):
     setting = ctx.last_launch()
     path = tmp_path / "tune.txt"
     ctx.tune_save(path)
-    assert path.read_text().startswith("tmotif-tune 1\n")
+    assert path.read_text().startswith("tmotif-tune 2\n")
     assert ctx.tune_clear() >= 1
     ctx.tune_load(path)
     assert ctx.count(tiny_g, mm) == want
