@@ -80,7 +80,7 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"native library not built: {LIB_PATH} (run __graft_entry__.build())")
+        raise ImportError(f"native library not built: {LIB_PATH} (build it: python -m paper_2310_02800_amd.build)")
     # PyTorch ships its own HIP runtime. Importing it first makes the library
     # bind to that already-loaded runtime, so the process holds one runtime and
     # torch's device buffers and streams are valid handles for the library.

@@ -318,7 +318,10 @@ __device__ __forceinline__ i64 try_pop(const GArgs& g, int qi, int want, int* n)
     if (hh < tt) {
       u64 kk = tt - hh;
       if (kk > (u64)want) kk = (u64)want;
-      if (atomicCAS(&qc[0], hh, hh + kk) == hh) { h = (i64)hh; k = (int)kk; }
+      if (atomicCAS(&qc[0], hh, hh + kk) == hh) {
+        h = (i64)hh; k = (int)kk;
+        atomicAdd(&g.ctl[13], (u64)(-(i64)kk));  // items waiting in all queues
+      }
     }
   }
   *n = __builtin_amdgcn_readfirstlane(k);
@@ -583,6 +586,7 @@ struct Emitter {
         o << "          if (gl && dj > 0 && !gave && rank_in(pushers) < 16) {\n";
         o << "            const u64 slot = atomicAdd(&g.qctl[2 * qi + 1], 1ull);\n";
         o << "            if (slot < (u64)g.item_cap) {\n";
+        o << "              atomicAdd(&g.ctl[13], 1ull);  // items waiting in all queues\n";
         o << "              u32* it = item_at(g, qi, slot);\n";
         o << "              st_ag(it + 1, (u32)dj); st_ag(it + 2, ds); st_ag(it + 3, de); st_ag64(it + 4, (i64)dh);\n";
         o << "              st_ag(it + 6, (u32)dw); st_ag(it + 7, (u32)root); st_ag64(it + 8, mych);\n";
@@ -1164,8 +1168,18 @@ void emit_kernels(std::ostringstream &o, int nfn, int block, bool all_modes, int
         o << "    if (busy) { if (lane == 0) atomicAdd(&g.ctl[8], ~0ull); busy = false; }\n";
         o << "    if (" << mode << " == 1 || !g.split || g.items == 0) break;\n";
         o << "    if (!hung) { if (lane == 0) atomicAdd(&g.ctl[9], 1ull); hung = true; }\n";
+        // look at the queues only when some item waits (one word), and once
+        // more, whatever that word says, before leaving: every wavefront that
+        // donated was busy at the time and looks at the queues itself when it
+        // stops being busy, so no item is left behind
+        o << "    i64 b = 0, av = 0, hq = 0;\n";
+        o << "    if (lane == 0) { b = (i64)ld_rlx64(&g.ctl[8]); av = (i64)ld_rlx64(&g.ctl[13]); hq = (i64)ld_rlx64(&g.ctl[9]); }\n";
+        o << "    b = bcast64(b); av = bcast64(av); hq = bcast64(hq);\n";
+        // surplus waiters leave, freeing their compute units for other
+        // launches (a few per busy wavefront take all it can donate)
+        o << "    if (av <= 0 && b > 0 && hq > 2 * b + 32) break;\n";
         o << "    int fq = -1, n = 0; i64 h = 0;\n";
-        o << "    for (int qq = 0; qq < g.nq; ++qq) {\n";
+        o << "    for (int qq = 0; (av > 0 || b == 0) && qq < g.nq; ++qq) {\n";
         o << "      int ne = 0;\n";
         o << "      if (lane == 0) {\n";
         o << "        const u64 hh = ld_rlx64(&g.qctl[2 * qq]);\n";
@@ -1188,9 +1202,6 @@ void emit_kernels(std::ostringstream &o, int nfn, int block, bool all_modes, int
         run("      ", "fq", "-1", "h", "n");
         o << "      continue;\n";
         o << "    }\n";
-        o << "    i64 b = 0;\n";
-        o << "    if (lane == 0) b = (i64)ld_rlx64(&g.ctl[8]);\n";
-        o << "    b = bcast64(b);\n";
         o << "    if (b == 0) break;\n";
         // back off exponentially (1 to 16 long sleeps between looks), so that
         // thousands of waiting wavefronts do not hammer the few queue words the

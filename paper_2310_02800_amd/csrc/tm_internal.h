@@ -78,9 +78,10 @@ struct GArgs {
 };
 static_assert(sizeof(GArgs) == 224, "GArgs layout");
 
-// ctl words: [10..12] work counters of the windows counted without a scan
+// ctl words: [10..12] work counters of the windows counted without a scan,
+// [13] donated items waiting in all queues
 enum { CTL_CURSOR = 0, CTL_OVERFLOW = 1, CTL_STATS = 2, CTL_ERROR = 7, CTL_BUSY = 8, CTL_HUNGRY = 9,
-       CTL_LEAF = 10, CTL_WORDS = 16 };
+       CTL_LEAF = 10, CTL_AVAIL = 13, CTL_WORDS = 16 };
 constexpr uint32_t kItemWords = 32;
 constexpr uint64_t kItemsTotal = uint64_t(1) << 20;  // donated work items per launch (128 MiB)
 enum Mode { MODE_COUNT = 0, MODE_STATS = 1, MODE_ENUM_COUNT = 2, MODE_ENUM_WRITE = 3, MODE_COUNT_ = 4 };
