@@ -247,7 +247,9 @@ def test_root_ranges_are_additive(ctx, tiny_g, tiny_og):
                                           (N.TM_PARAM_BLOCK, [64, 1024, 256]),
                                           (N.TM_PARAM_GRID, [1, 3, 0]),
                                           (N.TM_PARAM_SPLIT, [0, 1]),
-                                          (N.TM_PARAM_SPLIT_MIN, [3, 1000, 2])])
+                                          (N.TM_PARAM_SPLIT_MIN, [3, 1000, 2]),
+                                          (N.TM_PARAM_LEAF_MIN, [0, 32, 2048, 512]),
+                                          (N.TM_PARAM_MIN_WAVES, [6, 0])])
 def test_launch_parameters_do_not_change_results(ctx, tiny_g, tiny_og, param, values):
     mot = Motif(synth.FOUR_CYCLE, 30_000, pred_edge=1, pred_op=0, pred_theta=0.5)
     want = oracle.count(tiny_og, mot)
@@ -388,3 +390,15 @@ def test_graph_freed_after_its_context(tiny, tiny_og):
         g2.close()
     finally:
         c2.close()
+
+
+@pytest.mark.parametrize("param,bad", [(N.TM_PARAM_LEAF_MIN, 31), (N.TM_PARAM_LEAF_MIN, -1), (N.TM_PARAM_MIN_WAVES, 9),
+                                       (N.TM_PARAM_WORK_BUDGET, -5), (N.TM_PARAM_SPLIT_MIN, 1), (N.TM_PARAM_TIER, 2),
+                                       (N.TM_PARAM_BLOCK, 100), (99, 0)])
+def test_bad_parameters_are_rejected(ctx, param, bad):
+    old = ctx.get_param(param) if param != 99 else None
+    with pytest.raises(N.NativeError) as ei:
+        ctx.set_param(param, bad)
+    assert ei.value.status == N.TM_E_INVALID
+    if old is not None:
+        assert ctx.get_param(param) == old
