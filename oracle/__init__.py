@@ -6,8 +6,8 @@ package. The product path never imports it and shares no code with it.
 Two independent implementations of the problem definition (Sec. 2.1):
 
 * ``count`` / ``enumerate`` call the plain C depth-first search in
-  ``tm_oracle.c`` (Algorithm 1 with the fine-grained gap, attribute and
-  root-range constraints of Sec. 2.1 and Sec. 5.4);
+  ``tm_oracle.c`` (Algorithm 1 with the fine-grained gap, attribute,
+  temporal anti-edge and root-range constraints of Sec. 2.1 and Sec. 5.4);
 * ``brute.py`` checks every ordered l-tuple of distinct edges against the
   definition literally, for tiny graphs.
 """
@@ -51,10 +51,14 @@ def _load():
         lib.oracle_graph_new.argtypes = [i64, i64, P, P, P, P]
         lib.oracle_graph_free.argtypes = [P]
         lib.oracle_count.restype = i32
-        lib.oracle_count.argtypes = [P, i32, i32, P, i64, P, i32, i32, ctypes.c_float, i64, i64, i32, i32, P, P]
+        lib.oracle_count.argtypes = [P, i32, i32, P, i64, P, i32, i32, ctypes.c_float, i64, i64, i32,
+                                     i32, P, P, i32, P, P]
         lib.oracle_enumerate.restype = i32
-        lib.oracle_enumerate.argtypes = [P, i32, i32, P, i64, P, i32, i32, ctypes.c_float, i64, i64, P,
-                                         ctypes.c_uint64, P]
+        lib.oracle_enumerate.argtypes = [P, i32, i32, P, i64, P, i32, i32, ctypes.c_float, i64, i64,
+                                         i32, P, P, P, ctypes.c_uint64, P]
+        lib.oracle_version.restype = i32
+        if lib.oracle_version() != 2:
+            raise RuntimeError("stale oracle library: rebuild it with oracle.build()")
         _lib = lib
     return _lib
 
@@ -95,17 +99,29 @@ def _motif_args(motif):
     return edges, gaps
 
 
+def _anti_args(motif):
+    """Temporal anti-edges as (a, b, attach edge) triples and their windows."""
+    anti = getattr(motif, "anti", None) or []
+    if not anti:
+        return 0, None, None
+    trip = np.ascontiguousarray(np.array([x[:3] for x in anti], dtype=np.int32).reshape(-1))
+    win = np.ascontiguousarray(np.array([x[3] for x in anti], dtype=np.int64))
+    return len(anti), trip, win
+
+
 def count(og: OracleGraph, motif, t_lo: int = I64_MIN, t_hi: int = I64_MAX, nthreads: int = 1,
           list_rule: int = 0, with_stats: bool = False):
     """Number of instances. With ``with_stats`` also returns a dict of the
     work counters (roots, windows, probes, visits, pred_visits, matches)."""
     lib = _load()
     edges, gaps = _motif_args(motif)
+    na, trip, win = _anti_args(motif)
     out = np.zeros(1, np.uint64)
     st = np.zeros(6, np.uint64)
     rc = lib.oracle_count(og._h, motif.l, motif.k, _ptr(edges), int(motif.delta), _ptr(gaps),
                           int(motif.pred_edge), int(motif.pred_op), float(motif.pred_theta),
-                          int(t_lo), int(t_hi), int(list_rule), int(nthreads), _ptr(out), _ptr(st))
+                          int(t_lo), int(t_hi), int(list_rule), na, _ptr(trip), _ptr(win), int(nthreads),
+                          _ptr(out), _ptr(st))
     if rc != 0:
         raise ValueError("oracle rejected the query")
     if with_stats:
@@ -119,13 +135,15 @@ def enumerate(og: OracleGraph, motif, t_lo: int = I64_MIN, t_hi: int = I64_MAX,
     """All instances as an int64[count, l] array (root order, then DFS order)."""
     lib = _load()
     edges, gaps = _motif_args(motif)
+    na, trip, win = _anti_args(motif)
     n_out = np.zeros(1, np.uint64)
     if capacity is None:
         capacity = count(og, motif, t_lo, t_hi)
     buf = np.zeros((max(capacity, 1), motif.l), np.int64)
     rc = lib.oracle_enumerate(og._h, motif.l, motif.k, _ptr(edges), int(motif.delta), _ptr(gaps),
                               int(motif.pred_edge), int(motif.pred_op), float(motif.pred_theta),
-                              int(t_lo), int(t_hi), _ptr(buf), int(capacity), _ptr(n_out))
+                              int(t_lo), int(t_hi), na, _ptr(trip), _ptr(win), _ptr(buf), int(capacity),
+                              _ptr(n_out))
     if rc != 0:
         raise ValueError("oracle rejected the query")
     n = int(n_out[0])

@@ -5,7 +5,9 @@ each condition of the problem definition (Sec. 2.1) directly: strictly
 increasing times, the delta window (inclusive), the fine-grained gaps delta_i,
 the existence of an injective node map phi with phi(a_i)=src(e_i) and
 phi(b_i)=dst(e_i) (isomorphism: a bijection onto the matched nodes), an
-edge-weight predicate, and the root-range filter. It shares nothing with the
+edge-weight predicate, temporal anti-edges (absence of an edge between two
+mapped nodes in a closed time range after the attached edge), and the
+root-range filter. It shares nothing with the
 C oracle or the GPU path.
 """
 from __future__ import annotations
@@ -57,6 +59,13 @@ def is_instance(g, motif, tup, t_lo=I64_MIN, t_hi=I64_MAX) -> bool:
         e = tup[motif.pred_edge]
         if not _pred(motif.pred_op, np.float32(g.w[e]), np.float32(motif.pred_theta)):
             return False
+    # temporal anti-edges: no graph edge at all (the tuple's own included) from
+    # phi(a) to phi(b) with a time in [t(e_i), t(e_i) + window]
+    for a, b, i, win in getattr(motif, "anti", None) or []:
+        t0 = ts[i]
+        for f in range(g.m):
+            if int(g.src[f]) == phi[a] and int(g.dst[f]) == phi[b] and t0 <= int(g.t[f]) <= t0 + win:
+                return False
     return True
 
 

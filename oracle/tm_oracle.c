@@ -16,7 +16,11 @@
  *   - an optional edge-attribute constraint w(e_j) OP theta holds (float32
  *     comparison; label/attribute constraints, Sec. 5.4.1);
  *   - the root edge's time lies in [t_lo, t_hi] (a root-range filter; later
- *     edges may exceed t_hi by up to delta, so counts add over root ranges).
+ *     edges may exceed t_hi by up to delta, so counts add over root ranges);
+ *   - for every temporal anti-edge (a, b, attached to motif edge i, delta_ab)
+ *     the graph has no edge phi(a) -> phi(b) with time in the closed range
+ *     [t(e_i), t(e_i) + delta_ab] (absence of an edge, Sec. 2.1), whether or
+ *     not that edge belongs to the match.
  *
  * How (Sec. 2.2, Algorithm 1): chronological depth-first search in the style of
  * Mackey et al. The first motif edge is mapped onto every graph edge in time
@@ -28,6 +32,12 @@
  * eCount with the update and rollback steps of the algorithm. The window end
  * is inclusive, following the definition (the printed loop tests time < t',
  * which would exclude t_last - t_first == delta).
+ *
+ * Anti-edges (Sec. 5.4.3): an anti-edge is checked as soon as its attach edge
+ * is matched and both its nodes are bound, i.e. when the candidate of level
+ * max(i, first level binding a, first level binding b) is accepted; a
+ * matching graph edge ends that branch. The check scans phi(a)'s out-list
+ * over the closed range. It reads no candidate the work counters count.
  *
  * Readings where the paper is silent: equal timestamps are allowed in the
  * graph and never both used in one match (strict order); a candidate whose two
@@ -50,6 +60,7 @@
 
 #define OR_MAXL 8
 #define OR_MAXK 8
+#define OR_MAXA 4
 
 enum { OR_GE = 0, OR_GT = 1, OR_LE = 2, OR_LT = 3 };
 
@@ -71,6 +82,9 @@ typedef struct {
     float theta;
     int64_t t_lo, t_hi;
     int list_rule;
+    int n_anti;
+    int anti_a[OR_MAXA], anti_b[OR_MAXA], anti_at[OR_MAXA], anti_lvl[OR_MAXA];
+    int64_t anti_delta[OR_MAXA];
 } or_query;
 
 typedef struct {
@@ -170,6 +184,34 @@ static int struct_ok(const or_ctx *c, int64_t e, int64_t ug, int64_t vg) {
     return u_cons && v_cons;
 }
 
+/* Absence check of anti-edge j once its nodes are bound and its attach edge
+ * matched: no edge phi(a) -> phi(b) with time in [t_at, t_at + delta]. */
+static int anti_free(const or_ctx *c, int j) {
+    const or_graph *g = c->g;
+    const or_query *q = c->q;
+    const int64_t u = c->map_mg[q->anti_a[j]], v = c->map_mg[q->anti_b[j]];
+    const int64_t t0 = g->t[c->estack[q->anti_at[j]]];
+    const int64_t t1 = sat_add(t0, q->anti_delta[j]);
+    int64_t lo = g->out_off[u], hi = g->out_off[u + 1];
+    while (lo < hi) { /* first out-edge of u with time >= t0 */
+        int64_t mid = lo + (hi - lo) / 2;
+        if (g->t[g->out_ids[mid]] < t0) lo = mid + 1; else hi = mid;
+    }
+    for (int64_t p = lo; p < g->out_off[u + 1]; p++) {
+        const int64_t e = g->out_ids[p];
+        if (g->t[e] > t1) break;
+        if (g->dst[e] == v) return 0;
+    }
+    return 1;
+}
+
+/* All anti-edges checked at level i hold. */
+static int anti_ok(const or_ctx *c, int i) {
+    for (int j = 0; j < c->q->n_anti; j++)
+        if (c->q->anti_lvl[j] == i && !anti_free(c, j)) return 0;
+    return 1;
+}
+
 static void emit(or_ctx *c) {
     c->count++;
     c->st.matches++;
@@ -225,7 +267,7 @@ static void dfs(or_ctx *c, int i, int64_t t_prev) {
         /* NextLevel: bookkeeping and push, then descend; Backtrack on return */
         update_ds(c, i, e);
         c->estack[i] = e;
-        dfs(c, i + 1, g->t[e]);
+        if (anti_ok(c, i)) dfs(c, i + 1, g->t[e]);
         rollback_ds(c, e);
     }
 }
@@ -240,7 +282,7 @@ static void run_root(or_ctx *c, int64_t r) {
     update_ds(c, 0, r);
     c->estack[0] = r;
     c->tprime = sat_add(g->t[r], q->delta);
-    dfs(c, 1, g->t[r]);
+    if (anti_ok(c, 0)) dfs(c, 1, g->t[r]);
     rollback_ds(c, r);
 }
 
@@ -276,7 +318,8 @@ void oracle_graph_free(void *h) {
 }
 
 static int make_query(or_query *q, int l, int k, const int32_t *edges, int64_t delta, const int64_t *gaps,
-                      int pred_edge, int pred_op, float theta, int64_t t_lo, int64_t t_hi, int list_rule) {
+                      int pred_edge, int pred_op, float theta, int64_t t_lo, int64_t t_hi, int list_rule,
+                      int n_anti, const int32_t *anti, const int64_t *anti_delta) {
     if (l < 1 || l > OR_MAXL || k < 2 || k > OR_MAXK || delta < 0) return 1;
     memset(q, 0, sizeof(*q));
     q->l = l; q->k = k; q->delta = delta;
@@ -290,6 +333,23 @@ static int make_query(or_query *q, int l, int k, const int32_t *edges, int64_t d
     }
     q->pred_edge = pred_edge; q->pred_op = pred_op; q->theta = theta;
     q->t_lo = t_lo; q->t_hi = t_hi; q->list_rule = list_rule;
+    /* anti-edges: (a, b, attach edge) triples; checked at the level where the
+     * attach edge is matched and both nodes are bound */
+    if (n_anti < 0 || n_anti > OR_MAXA || (n_anti > 0 && (!anti || !anti_delta))) return 1;
+    int first[OR_MAXK];
+    for (int v = 0; v < k; v++) first[v] = -1;
+    for (int i = l - 1; i >= 0; i--) { first[q->a[i]] = i; first[q->b[i]] = i; }
+    q->n_anti = n_anti;
+    for (int j = 0; j < n_anti; j++) {
+        const int a = anti[3 * j], b = anti[3 * j + 1], at = anti[3 * j + 2];
+        if (a < 0 || a >= k || b < 0 || b >= k || a == b || at < 0 || at >= l || anti_delta[j] < 0) return 1;
+        if (first[a] < 0 || first[b] < 0) return 1;
+        int lvl = at;
+        if (first[a] > lvl) lvl = first[a];
+        if (first[b] > lvl) lvl = first[b];
+        q->anti_a[j] = a; q->anti_b[j] = b; q->anti_at[j] = at; q->anti_lvl[j] = lvl;
+        q->anti_delta[j] = anti_delta[j];
+    }
     return 0;
 }
 
@@ -344,10 +404,13 @@ static void *worker_main(void *arg) {
  * pred_visits, matches. Returns 0 on success, 1 on an invalid query. */
 int oracle_count(void *gh, int l, int k, const int32_t *edges, int64_t delta, const int64_t *gaps,
                  int pred_edge, int pred_op, float theta, int64_t t_lo, int64_t t_hi, int list_rule,
+                 int n_anti, const int32_t *anti, const int64_t *anti_delta,
                  int nthreads, uint64_t *count_out, uint64_t *stats_out) {
     const or_graph *g = (const or_graph *)gh;
     or_query q;
-    if (make_query(&q, l, k, edges, delta, gaps, pred_edge, pred_op, theta, t_lo, t_hi, list_rule)) return 1;
+    if (make_query(&q, l, k, edges, delta, gaps, pred_edge, pred_op, theta, t_lo, t_hi, list_rule, n_anti, anti,
+                   anti_delta))
+        return 1;
     if (pred_edge >= l || (pred_edge >= 0 && !g->w)) return 1;
     int64_t r0 = first_root(g, t_lo), r1 = end_root(g, t_hi);
     if (r1 < r0) r1 = r0;
@@ -385,10 +448,13 @@ int oracle_count(void *gh, int l, int k, const int32_t *edges, int64_t delta, co
  * at most `capacity` rows of l int64 edge ids; *n_out gets the total. */
 int oracle_enumerate(void *gh, int l, int k, const int32_t *edges, int64_t delta, const int64_t *gaps,
                      int pred_edge, int pred_op, float theta, int64_t t_lo, int64_t t_hi,
+                     int n_anti, const int32_t *anti, const int64_t *anti_delta,
                      int64_t *out, uint64_t capacity, uint64_t *n_out) {
     const or_graph *g = (const or_graph *)gh;
     or_query q;
-    if (make_query(&q, l, k, edges, delta, gaps, pred_edge, pred_op, theta, t_lo, t_hi, 0)) return 1;
+    if (make_query(&q, l, k, edges, delta, gaps, pred_edge, pred_op, theta, t_lo, t_hi, 0, n_anti, anti,
+                   anti_delta))
+        return 1;
     if (pred_edge >= l || (pred_edge >= 0 && !g->w)) return 1;
     int64_t r0 = first_root(g, t_lo), r1 = end_root(g, t_hi);
     or_ctx c;
@@ -400,4 +466,4 @@ int oracle_enumerate(void *gh, int l, int k, const int32_t *edges, int64_t delta
     return 0;
 }
 
-int oracle_version(void) { return 1; }
+int oracle_version(void) { return 2; }

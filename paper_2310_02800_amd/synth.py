@@ -63,6 +63,8 @@ class Motif:
 
     ``gap`` has l-1 entries (``NO_GAP`` = unconstrained); the predicate, when
     ``pred_edge >= 0``, requires ``w[e_pred_edge] OP theta`` in float32.
+    ``anti`` lists temporal anti-edges as (a, b, i, window): no graph edge
+    phi(a) -> phi(b) may have a time in [t(e_i), t(e_i) + window].
     """
 
     edges: List[Tuple[int, int]]
@@ -71,6 +73,7 @@ class Motif:
     pred_edge: int = -1
     pred_op: int = PRED_GE
     pred_theta: float = 0.0
+    anti: Optional[List[Tuple[int, int, int, int]]] = None
 
     @property
     def l(self) -> int:
