@@ -6,8 +6,9 @@ package. The product path never imports it and shares no code with it.
 Two independent implementations of the problem definition (Sec. 2.1):
 
 * ``count`` / ``enumerate`` call the plain C depth-first search in
-  ``tm_oracle.c`` (Algorithm 1 with the fine-grained gap, attribute,
-  temporal anti-edge and root-range constraints of Sec. 2.1 and Sec. 5.4);
+  ``tm_oracle.c`` (Algorithm 1 with the fine-grained gap, attribute, vertex
+  label, temporal anti-edge and root-range constraints of Sec. 2.1 and
+  Sec. 5.4);
 * ``brute.py`` checks every ordered l-tuple of distinct edges against the
   definition literally, for tiny graphs.
 """
@@ -52,12 +53,13 @@ def _load():
         lib.oracle_graph_free.argtypes = [P]
         lib.oracle_count.restype = i32
         lib.oracle_count.argtypes = [P, i32, i32, P, i64, P, i32, i32, ctypes.c_float, i64, i64, i32,
-                                     i32, P, P, i32, P, P]
+                                     i32, P, P, P, i32, P, P]
         lib.oracle_enumerate.restype = i32
         lib.oracle_enumerate.argtypes = [P, i32, i32, P, i64, P, i32, i32, ctypes.c_float, i64, i64,
-                                         i32, P, P, P, ctypes.c_uint64, P]
+                                         i32, P, P, P, P, ctypes.c_uint64, P]
+        lib.oracle_graph_set_labels.argtypes = [P, P]
         lib.oracle_version.restype = i32
-        if lib.oracle_version() != 2:
+        if lib.oracle_version() != 3:
             raise RuntimeError("stale oracle library: rebuild it with oracle.build()")
         _lib = lib
     return _lib
@@ -70,7 +72,7 @@ def _ptr(a: Optional[np.ndarray]):
 class OracleGraph:
     """Holds the time-sorted edge arrays and the per-node in/out id lists."""
 
-    def __init__(self, n: int, src, dst, t, w=None):
+    def __init__(self, n: int, src, dst, t, w=None, labels=None):
         lib = _load()
         self.src = np.ascontiguousarray(src, dtype=np.int32)
         self.dst = np.ascontiguousarray(dst, dtype=np.int32)
@@ -82,10 +84,16 @@ class OracleGraph:
         self.m = int(self.src.size)
         self._h = lib.oracle_graph_new(self.n, self.m, _ptr(self.src), _ptr(self.dst), _ptr(self.t),
                                        _ptr(self.w))
+        self.labels = None
+        if labels is not None:
+            self.labels = np.ascontiguousarray(labels, dtype=np.int32)
+            if self.labels.shape != (self.n,) or (self.n and self.labels.min() < 0):
+                raise ValueError("labels: one non-negative int32 per node")
+            lib.oracle_graph_set_labels(self._h, _ptr(self.labels))
 
     @classmethod
     def from_graph(cls, g) -> "OracleGraph":
-        return cls(g.n, g.src, g.dst, g.t, g.w)
+        return cls(g.n, g.src, g.dst, g.t, g.w, getattr(g, "labels", None))
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -109,6 +117,12 @@ def _anti_args(motif):
     return len(anti), trip, win
 
 
+def _label_args(motif):
+    """Required label per motif node (-1 = any), or None."""
+    lab = getattr(motif, "node_labels", None)
+    return None if lab is None else np.ascontiguousarray(np.array(lab, dtype=np.int32))
+
+
 def count(og: OracleGraph, motif, t_lo: int = I64_MIN, t_hi: int = I64_MAX, nthreads: int = 1,
           list_rule: int = 0, with_stats: bool = False):
     """Number of instances. With ``with_stats`` also returns a dict of the
@@ -116,11 +130,12 @@ def count(og: OracleGraph, motif, t_lo: int = I64_MIN, t_hi: int = I64_MAX, nthr
     lib = _load()
     edges, gaps = _motif_args(motif)
     na, trip, win = _anti_args(motif)
+    lab = _label_args(motif)
     out = np.zeros(1, np.uint64)
     st = np.zeros(6, np.uint64)
     rc = lib.oracle_count(og._h, motif.l, motif.k, _ptr(edges), int(motif.delta), _ptr(gaps),
                           int(motif.pred_edge), int(motif.pred_op), float(motif.pred_theta),
-                          int(t_lo), int(t_hi), int(list_rule), na, _ptr(trip), _ptr(win), int(nthreads),
+                          int(t_lo), int(t_hi), int(list_rule), na, _ptr(trip), _ptr(win), _ptr(lab), int(nthreads),
                           _ptr(out), _ptr(st))
     if rc != 0:
         raise ValueError("oracle rejected the query")
@@ -136,13 +151,14 @@ def enumerate(og: OracleGraph, motif, t_lo: int = I64_MIN, t_hi: int = I64_MAX,
     lib = _load()
     edges, gaps = _motif_args(motif)
     na, trip, win = _anti_args(motif)
+    lab = _label_args(motif)
     n_out = np.zeros(1, np.uint64)
     if capacity is None:
         capacity = count(og, motif, t_lo, t_hi)
     buf = np.zeros((max(capacity, 1), motif.l), np.int64)
     rc = lib.oracle_enumerate(og._h, motif.l, motif.k, _ptr(edges), int(motif.delta), _ptr(gaps),
                               int(motif.pred_edge), int(motif.pred_op), float(motif.pred_theta),
-                              int(t_lo), int(t_hi), na, _ptr(trip), _ptr(win), _ptr(buf), int(capacity),
+                              int(t_lo), int(t_hi), na, _ptr(trip), _ptr(win), _ptr(lab), _ptr(buf), int(capacity),
                               _ptr(n_out))
     if rc != 0:
         raise ValueError("oracle rejected the query")

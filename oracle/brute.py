@@ -5,7 +5,7 @@ each condition of the problem definition (Sec. 2.1) directly: strictly
 increasing times, the delta window (inclusive), the fine-grained gaps delta_i,
 the existence of an injective node map phi with phi(a_i)=src(e_i) and
 phi(b_i)=dst(e_i) (isomorphism: a bijection onto the matched nodes), an
-edge-weight predicate, temporal anti-edges (absence of an edge between two
+edge-weight predicate, vertex labels, temporal anti-edges (absence of an edge between two
 mapped nodes in a closed time range after the attached edge), and the
 root-range filter. It shares nothing with the
 C oracle or the GPU path.
@@ -55,6 +55,10 @@ def is_instance(g, motif, tup, t_lo=I64_MIN, t_hi=I64_MAX) -> bool:
             phi[mnode] = gnode
     if len(set(phi.values())) != len(phi):  # injective
         return False
+    # vertex labels: a motif node with a required label maps to a node carrying it
+    for v, want in enumerate(getattr(motif, "node_labels", None) or []):
+        if want >= 0 and int(g.labels[phi[v]]) != want:
+            return False
     if motif.pred_edge >= 0:
         e = tup[motif.pred_edge]
         if not _pred(motif.pred_op, np.float32(g.w[e]), np.float32(motif.pred_theta)):

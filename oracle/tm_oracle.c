@@ -17,6 +17,9 @@
  *     comparison; label/attribute constraints, Sec. 5.4.1);
  *   - the root edge's time lies in [t_lo, t_hi] (a root-range filter; later
  *     edges may exceed t_hi by up to delta, so counts add over root ranges);
+ *   - every motif node v with a required label L(v) >= 0 maps to a graph node
+ *     carrying that label (vertex labels, Sec. 5.4.1: checked when the node
+ *     is newly matched);
  *   - for every temporal anti-edge (a, b, attached to motif edge i, delta_ab)
  *     the graph has no edge phi(a) -> phi(b) with time in the closed range
  *     [t(e_i), t(e_i) + delta_ab] (absence of an edge, Sec. 2.1), whether or
@@ -69,6 +72,7 @@ typedef struct {
     const int32_t *src, *dst;
     const int64_t *t;
     const float *w;
+    const int32_t *lab;        /* node labels (n entries, >= 0) or NULL */
     int64_t *out_off, *in_off; /* n+1 each */
     int64_t *out_ids, *in_ids; /* edge ids per node, ascending id order */
 } or_graph;
@@ -85,6 +89,7 @@ typedef struct {
     int n_anti;
     int anti_a[OR_MAXA], anti_b[OR_MAXA], anti_at[OR_MAXA], anti_lvl[OR_MAXA];
     int64_t anti_delta[OR_MAXA];
+    int32_t nlab[OR_MAXK]; /* required label per motif node, -1 = any */
 } or_query;
 
 typedef struct {
@@ -184,6 +189,19 @@ static int struct_ok(const or_ctx *c, int64_t e, int64_t ug, int64_t vg) {
     return u_cons && v_cons;
 }
 
+static int needs_labels(const or_query *q) {
+    for (int v = 0; v < q->k; v++)
+        if (q->nlab[v] >= 0) return 1;
+    return 0;
+}
+
+/* Vertex labels (Sec. 5.4.1): a newly matched graph node carries the label
+ * its motif node requires. Nodes bound earlier were checked then. */
+static int label_ok(const or_ctx *c, int v, int64_t gnode) {
+    const int32_t want = c->q->nlab[v];
+    return want < 0 || c->g->lab[gnode] == want;
+}
+
 /* Absence check of anti-edge j once its nodes are bound and its attach edge
  * matched: no edge phi(a) -> phi(b) with time in [t_at, t_at + delta]. */
 static int anti_free(const or_ctx *c, int j) {
@@ -263,6 +281,8 @@ static void dfs(or_ctx *c, int i, int64_t t_prev) {
         if (i == q->pred_edge) c->st.pred_visits++;
         if (g->t[e] > hi) break;
         if (!struct_ok(c, e, ug, vg)) continue;
+        if (ug < 0 && !label_ok(c, q->a[i], g->src[e])) continue;
+        if (vg < 0 && !label_ok(c, q->b[i], g->dst[e])) continue;
         if (i == q->pred_edge && !pred_ok(q, g->w[e])) continue;
         /* NextLevel: bookkeeping and push, then descend; Backtrack on return */
         update_ds(c, i, e);
@@ -278,6 +298,7 @@ static void run_root(or_ctx *c, int64_t r) {
     c->st.roots++;
     if (q->pred_edge == 0) c->st.pred_visits++;
     if (g->src[r] == g->dst[r]) return; /* both motif nodes new: must differ */
+    if (!label_ok(c, q->a[0], g->src[r]) || !label_ok(c, q->b[0], g->dst[r])) return;
     if (q->pred_edge == 0 && !pred_ok(q, g->w[r])) return;
     update_ds(c, 0, r);
     c->estack[0] = r;
@@ -319,7 +340,7 @@ void oracle_graph_free(void *h) {
 
 static int make_query(or_query *q, int l, int k, const int32_t *edges, int64_t delta, const int64_t *gaps,
                       int pred_edge, int pred_op, float theta, int64_t t_lo, int64_t t_hi, int list_rule,
-                      int n_anti, const int32_t *anti, const int64_t *anti_delta) {
+                      int n_anti, const int32_t *anti, const int64_t *anti_delta, const int32_t *node_label) {
     if (l < 1 || l > OR_MAXL || k < 2 || k > OR_MAXK || delta < 0) return 1;
     memset(q, 0, sizeof(*q));
     q->l = l; q->k = k; q->delta = delta;
@@ -333,6 +354,12 @@ static int make_query(or_query *q, int l, int k, const int32_t *edges, int64_t d
     }
     q->pred_edge = pred_edge; q->pred_op = pred_op; q->theta = theta;
     q->t_lo = t_lo; q->t_hi = t_hi; q->list_rule = list_rule;
+    for (int v = 0; v < OR_MAXK; v++) q->nlab[v] = -1;
+    if (node_label)
+        for (int v = 0; v < k; v++) {
+            if (node_label[v] < -1) return 1;
+            q->nlab[v] = node_label[v];
+        }
     /* anti-edges: (a, b, attach edge) triples; checked at the level where the
      * attach edge is matched and both nodes are bound */
     if (n_anti < 0 || n_anti > OR_MAXA || (n_anti > 0 && (!anti || !anti_delta))) return 1;
@@ -404,13 +431,14 @@ static void *worker_main(void *arg) {
  * pred_visits, matches. Returns 0 on success, 1 on an invalid query. */
 int oracle_count(void *gh, int l, int k, const int32_t *edges, int64_t delta, const int64_t *gaps,
                  int pred_edge, int pred_op, float theta, int64_t t_lo, int64_t t_hi, int list_rule,
-                 int n_anti, const int32_t *anti, const int64_t *anti_delta,
+                 int n_anti, const int32_t *anti, const int64_t *anti_delta, const int32_t *node_label,
                  int nthreads, uint64_t *count_out, uint64_t *stats_out) {
     const or_graph *g = (const or_graph *)gh;
     or_query q;
     if (make_query(&q, l, k, edges, delta, gaps, pred_edge, pred_op, theta, t_lo, t_hi, list_rule, n_anti, anti,
-                   anti_delta))
+                   anti_delta, node_label))
         return 1;
+    if (needs_labels(&q) && !g->lab) return 1; /* labels required, graph has none */
     if (pred_edge >= l || (pred_edge >= 0 && !g->w)) return 1;
     int64_t r0 = first_root(g, t_lo), r1 = end_root(g, t_hi);
     if (r1 < r0) r1 = r0;
@@ -448,13 +476,14 @@ int oracle_count(void *gh, int l, int k, const int32_t *edges, int64_t delta, co
  * at most `capacity` rows of l int64 edge ids; *n_out gets the total. */
 int oracle_enumerate(void *gh, int l, int k, const int32_t *edges, int64_t delta, const int64_t *gaps,
                      int pred_edge, int pred_op, float theta, int64_t t_lo, int64_t t_hi,
-                     int n_anti, const int32_t *anti, const int64_t *anti_delta,
+                     int n_anti, const int32_t *anti, const int64_t *anti_delta, const int32_t *node_label,
                      int64_t *out, uint64_t capacity, uint64_t *n_out) {
     const or_graph *g = (const or_graph *)gh;
     or_query q;
     if (make_query(&q, l, k, edges, delta, gaps, pred_edge, pred_op, theta, t_lo, t_hi, 0, n_anti, anti,
-                   anti_delta))
+                   anti_delta, node_label))
         return 1;
+    if (needs_labels(&q) && !g->lab) return 1; /* labels required, graph has none */
     if (pred_edge >= l || (pred_edge >= 0 && !g->w)) return 1;
     int64_t r0 = first_root(g, t_lo), r1 = end_root(g, t_hi);
     or_ctx c;
@@ -466,4 +495,7 @@ int oracle_enumerate(void *gh, int l, int k, const int32_t *edges, int64_t delta
     return 0;
 }
 
-int oracle_version(void) { return 2; }
+/* Attach node labels (n entries, >= 0; the caller keeps them alive). */
+void oracle_graph_set_labels(void *gh, const int32_t *lab) { ((or_graph *)gh)->lab = lab; }
+
+int oracle_version(void) { return 3; }

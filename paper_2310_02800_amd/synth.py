@@ -51,6 +51,7 @@ class TemporalGraph:
     t: np.ndarray    # int64[m], non-decreasing
     w: Optional[np.ndarray] = None  # float32[m]
     name: str = ""
+    labels: Optional[np.ndarray] = None  # int32[n], node labels >= 0
 
     @property
     def m(self) -> int:
@@ -65,6 +66,7 @@ class Motif:
     ``pred_edge >= 0``, requires ``w[e_pred_edge] OP theta`` in float32.
     ``anti`` lists temporal anti-edges as (a, b, i, window): no graph edge
     phi(a) -> phi(b) may have a time in [t(e_i), t(e_i) + window].
+    ``node_labels`` gives each motif node's required vertex label (-1 = any).
     """
 
     edges: List[Tuple[int, int]]
@@ -74,6 +76,7 @@ class Motif:
     pred_op: int = PRED_GE
     pred_theta: float = 0.0
     anti: Optional[List[Tuple[int, int, int, int]]] = None
+    node_labels: Optional[List[int]] = None
 
     @property
     def l(self) -> int:
@@ -359,4 +362,18 @@ def content_hash(g: TemporalGraph) -> str:
     h = hashlib.sha256()
     for a in (g.src, g.dst, g.t) + ((g.w,) if g.w is not None else ()):
         h.update(np.ascontiguousarray(a).tobytes())
+    if g.labels is not None:
+        h.update(b"labels")
+        h.update(np.ascontiguousarray(g.labels).tobytes())
     return h.hexdigest()[:16]
+
+
+def node_labels(seed: int, n: int, n_labels: int) -> np.ndarray:
+    """Uniform random vertex labels 0..n_labels-1 (the paper's labels are
+    randomly generated, Sec. 6)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, n_labels, n).astype(np.int32)
+
+
+def with_labels(g: TemporalGraph, labels) -> TemporalGraph:
+    return dataclasses.replace(g, labels=np.ascontiguousarray(labels, dtype=np.int32))
