@@ -19,7 +19,10 @@ slice of the same workload on this host.
 Beside the headline, "batch64" measures the batched workload on the small
 power-law graph (n = 1,000, m = 20,000): 64 random motif queries (3-6 edges,
 half with a weight predicate) as one persistent launch against 64
-synchronised single-query launches.
+synchronised single-query launches. "constraints" times the 4-cycle at
+delta = 86400 s on the same wiki-shaped graph with the constraints added one
+after another, as the paper's table of additional constraints does (Sec. 6):
+none, fine-grained gaps, then also a temporal anti-edge.
 """
 from __future__ import annotations
 
@@ -150,6 +153,34 @@ def bench_batch64(ctx, args, stream):
             "plain_value": inst / plain_s, "batched_value": inst / batch_s, "unit": "instances/s",
             "speedup": plain_s / batch_s,
             "batched_launch": {"root_chunk": setting[0], "split": setting[1], "tuned": setting[2]}}
+
+
+def bench_constraints(ctx, dg, args, stream):
+    """The 4-cycle (delta = 86400 s) with no constraint (N), with every
+    consecutive gap <= 21600 s (T), and with those gaps plus an anti-edge from
+    motif node 2 to node 0 within 3600 s after edge 2 (T+A): count and the
+    time of one autotuned, synchronised tm_count each."""
+    import torch
+    from paper_2310_02800_amd import synth
+    four = list(synth.FOUR_CYCLE)
+    forms = {"N": synth.Motif(four, 86_400),
+             "T": synth.Motif(four, 86_400, gap=[21_600] * 3),
+             "T+A": synth.Motif(four, 86_400, gap=[21_600] * 3, anti=[(2, 0, 2, 3600)])}
+    out = {}
+    for name, mot in forms.items():
+        h = ctx.compile(mot)
+        for _ in range(max(args.warmup, 1)):
+            c = ctx.count(dg, h, stream=stream)  # the first call tunes
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            c = ctx.count(dg, h, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        out[name] = {"count": c, "ms": ms}
+        log(f"constraints {name}: {c} instances, {ms:.2f} ms")
+    return {"workload": "wiki-shaped graph, 4-cycle, delta 86400 s; T: gaps <= 21600 s; A: anti-edge 2->0 "
+                        "within 3600 s after edge 2", "forms": out}
 
 
 def rows_checksum(rows):
@@ -342,6 +373,8 @@ def main():
     ap.add_argument("--tune-table", default=None,
                     help="load launch settings from this file if it exists, save them there at the end")
     ap.add_argument("--no-batch64", action="store_true", help="skip the 64-query batch on the small graph")
+    ap.add_argument("--no-constraints", action="store_true",
+                    help="skip the 4-cycle with added constraints (gaps, anti-edge)")
     ap.add_argument("--serve-queries", type=int, default=500,
                     help="queries of the served stream to run (0 = skip; the full stream has 10,000)")
     ap.add_argument("--serve-budget", type=int, default=1 << 31, help="work budget per served query (steps)")
@@ -523,6 +556,8 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
+    if not args.no_constraints:
+        out["constraints"] = bench_constraints(ctx, dg, args, stream)
     if not args.no_batch64:
         out["batch64"] = bench_batch64(ctx, args, stream)
     if args.serve_queries > 0:

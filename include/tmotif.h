@@ -59,6 +59,7 @@ enum { TM_PRED_GE = 0, TM_PRED_GT = 1, TM_PRED_LE = 2, TM_PRED_LT = 3 };
 
 #define TM_MAX_EDGES 8
 #define TM_MAX_NODES 8
+#define TM_MAX_ANTI 4
 
 typedef struct tm_ctx tm_ctx;
 typedef struct tm_graph tm_graph;
@@ -197,8 +198,17 @@ typedef struct {
     int32_t has_weights;
     int64_t device_bytes;    /* HBM held by the graph */
     int32_t was_sorted;      /* 1 if the input was already in non-decreasing time order */
+    int32_t has_labels;      /* 1 once vertex labels are attached */
 } tm_graph_info;
 tm_status tm_graph_get_info(const tm_graph *g, tm_graph_info *info);
+
+/* Attach vertex labels (Sec. 5.4.1; the paper's example labels nodes by
+ * role, Sec. 4.3): labels is a host int32[n_nodes] array of values >= 0,
+ * copied to device memory (4 bytes per node; a second call replaces them).
+ * Motifs that require labels run only on a graph that has them. Not while
+ * queries on this graph are running. Blocking. Errors: TM_E_INVALID (null
+ * argument, a negative label), TM_E_OOM, TM_E_DEVICE. */
+tm_status tm_graph_set_node_labels(tm_graph *g, const int32_t *labels);
 
 /* perm_out: host int64[n_edges]; perm_out[id] = input position of edge id. */
 tm_status tm_graph_edge_order(const tm_graph *g, int64_t *perm_out);
@@ -226,6 +236,25 @@ tm_status tm_graph_copy_csr(const tm_graph *g, int32_t dir, uint32_t *off, int32
  *               INT64_MAX means none; entries must be >= 0
  *   pred_edge   -1 for none, else the motif edge j whose weight is tested
  *   pred_op     TM_PRED_*; pred_theta the float32 threshold
+ *   n_anti      number of temporal anti-edges (Sec. 2.1), 0..TM_MAX_ANTI, with
+ *               n_edges + n_anti <= 9
+ *   anti        host int32[3*n_anti] or NULL when n_anti is 0: a, b, i per
+ *               anti-edge; a != b are motif nodes that appear on edges, i is the
+ *               motif edge it is attached to
+ *   node_label  host int32[n_nodes] or NULL: the vertex label each motif node
+ *               requires (Sec. 5.4.1), -1 = any; checked when the node is
+ *               first matched. Label values are launch arguments; which nodes
+ *               carry one is part of the structure.
+ *   anti_delta  host int64[n_anti], entries >= 0: a match is rejected when the
+ *               graph has any edge phi(a) -> phi(b) (one of the match's own
+ *               edges included) whose time lies in the closed range
+ *               [t(e_i), t(e_i) + anti_delta]
+ *
+ * An anti-edge is checked when the candidate of level max(i, first level
+ * binding a, first level binding b) is accepted, and a hit ends that branch of
+ * the search (Sec. 5.4.3). Anti-edge windows are launch arguments like delta.
+ * A motif with anti-edges always runs a matcher specialised to it, also under
+ * TM_PARAM_TIER = 1.
  *
  * Compiling specialises a GPU kernel to the motif's structure (Sec. 5.1.2:
  * per-level candidate list, mapped-node checks and bookkeeping fixed ahead of
@@ -244,6 +273,10 @@ typedef struct {
     int32_t pred_edge;
     int32_t pred_op;
     float pred_theta;
+    int32_t n_anti;
+    const int32_t *anti;
+    const int64_t *anti_delta;
+    const int32_t *node_label;
 } tm_motif_desc;
 
 tm_status tm_compile_motif(tm_ctx *ctx, const tm_motif_desc *desc, tm_motif **out);
@@ -261,6 +294,16 @@ tm_status tm_motif_source(const tm_motif_desc *desc, int32_t key_bytes, char *bu
  * may be NULL) receives the code object's size. Errors: TM_E_INVALID,
  * TM_E_COMPILE (log in tm_last_error()). */
 tm_status tm_motif_compile_check(const tm_motif_desc *descs, int32_t q, int32_t key_bytes, int64_t *code_bytes);
+
+/* Compile, without loading it, the batched module that tm_count_batch (and the
+ * server's count batches) would launch for descs[0..q-1] (host array) under
+ * `tier` (as TM_PARAM_TIER: 0 one matcher per distinct structure, 1 the
+ * table-driven matchers plus specialised ones for motifs with anti-edges), so
+ * that a later launch finds it in the code-object cache. Needs no device.
+ * *code_bytes (host, may be NULL) receives the code object's size. Errors:
+ * TM_E_INVALID, TM_E_COMPILE. */
+tm_status tm_batch_compile_check(const tm_motif_desc *descs, int32_t q, int32_t tier, int32_t key_bytes,
+                                 int64_t *code_bytes);
 
 /* Compile a table-driven module (TM_PARAM_TIER = 1) without loading it: l in
  * 1..8 the single-query module for motifs of l edges, l = 0 the batched module
@@ -340,7 +383,9 @@ tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_mot
  * known after its counting pass) against a device pool of enum_pool_bytes,
  * waiting while other results hold the pool; rows that would not fit in the
  * whole pool complete with TM_E_CAPACITY and the count. There is no per-query
- * compilation when tier = 1 (see TM_PARAM_TIER).
+ * compilation when tier = 1 (see TM_PARAM_TIER), except once per structure of
+ * a motif with anti-edges: under tier 1 such a count query is launched on its
+ * own, with its specialised matcher.
  * Timestamps are host monotonic-clock nanoseconds (CLOCK_MONOTONIC). */
 typedef struct tm_server tm_server;
 

@@ -25,7 +25,9 @@ EXPORTED = [
     "tm_last_error", "tm_version", "tm_create", "tm_destroy", "tm_set_param", "tm_get_param", "tm_last_kernel_ms",
     "tm_last_launch", "tm_tune_save", "tm_tune_load", "tm_tune_clear",
     "tm_load_graph", "tm_free_graph", "tm_graph_get_info", "tm_graph_edge_order", "tm_graph_copy_csr",
-    "tm_compile_motif", "tm_free_motif", "tm_motif_source", "tm_motif_compile_check", "tm_generic_compile_check",
+    "tm_graph_set_node_labels",
+    "tm_compile_motif", "tm_free_motif", "tm_motif_source", "tm_motif_compile_check", "tm_batch_compile_check",
+    "tm_generic_compile_check",
     "tm_count", "tm_enumerate",
     "tm_work_stats", "tm_count_batch", "tm_server_start", "tm_submit_query", "tm_poll", "tm_release",
     "tm_server_stats", "tm_server_stop",
@@ -35,7 +37,8 @@ EXPORTED = [
 class MotifDesc(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int32), ("n_edges", ctypes.c_int32), ("edges", ctypes.c_void_p),
                 ("delta", ctypes.c_int64), ("gap_max", ctypes.c_void_p), ("pred_edge", ctypes.c_int32),
-                ("pred_op", ctypes.c_int32), ("pred_theta", ctypes.c_float)]
+                ("pred_op", ctypes.c_int32), ("pred_theta", ctypes.c_float), ("n_anti", ctypes.c_int32),
+                ("anti", ctypes.c_void_p), ("anti_delta", ctypes.c_void_p), ("node_label", ctypes.c_void_p)]
 
 
 class RootRange(ctypes.Structure):
@@ -63,7 +66,7 @@ class Result(ctypes.Structure):
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64), ("n_edges", ctypes.c_int64), ("t_min", ctypes.c_int64),
                 ("t_max", ctypes.c_int64), ("key_bytes", ctypes.c_int32), ("has_weights", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64), ("was_sorted", ctypes.c_int32)]
+                ("device_bytes", ctypes.c_int64), ("was_sorted", ctypes.c_int32), ("has_labels", ctypes.c_int32)]
 
 
 _lib = None
@@ -108,10 +111,12 @@ def lib():
         "tm_graph_get_info": (i32, [P, P]),
         "tm_graph_edge_order": (i32, [P, P]),
         "tm_graph_copy_csr": (i32, [P, i32, P, P, P, P]),
+        "tm_graph_set_node_labels": (i32, [P, P]),
         "tm_compile_motif": (i32, [P, P, pp]),
         "tm_free_motif": (None, [P]),
         "tm_motif_source": (i32, [P, i32, P, i64, P]),
         "tm_motif_compile_check": (i32, [P, i32, i32, P]),
+        "tm_batch_compile_check": (i32, [P, i32, i32, i32, P]),
         "tm_generic_compile_check": (i32, [i32, i32, P]),
         "tm_count": (i32, [P, P, P, P, P, P]),
         "tm_enumerate": (i32, [P, P, P, P, P, P, ctypes.c_uint64, P]),

@@ -65,6 +65,13 @@ class Graph:
         N.check(N.lib().tm_graph_get_info(self._h, ctypes.byref(inf)))
         return {f: getattr(inf, f) for f, _ in N.GraphInfo._fields_}
 
+    def set_node_labels(self, labels) -> None:
+        """Attach vertex labels (int32 >= 0, one per node)."""
+        lab = _np(labels, np.int32)
+        if lab.shape != (self.info()["n_nodes"],):
+            raise ValueError("one label per node")
+        N.check(N.lib().tm_graph_set_node_labels(self._h, _ptr(lab)))
+
     def edge_order(self) -> np.ndarray:
         m = self.info()["n_edges"]
         out = np.zeros(m, np.int64)
@@ -116,20 +123,37 @@ class Motif:
             pass
 
 
-def make_desc(edges, delta, gap=None, pred_edge=-1, pred_op=0, pred_theta=0.0, n_nodes=None):
+def make_desc(edges, delta, gap=None, pred_edge=-1, pred_op=0, pred_theta=0.0, n_nodes=None, anti=None,
+              node_labels=None):
+    """Motif descriptor. ``anti``: temporal anti-edges as (a, b, attach edge,
+    window) tuples; ``node_labels``: required vertex label per motif node
+    (-1 = any)."""
     e = np.ascontiguousarray(np.array(edges, dtype=np.int32).reshape(-1))
     l = e.size // 2
     k = int(n_nodes) if n_nodes is not None else (int(e.max()) + 1 if e.size else 0)
     g = None if gap is None else np.ascontiguousarray(np.array(gap, dtype=np.int64))
+    na = 0 if not anti else len(anti)
+    an = ad = None
+    if na:
+        an = np.ascontiguousarray(np.array([x[:3] for x in anti], dtype=np.int32).reshape(-1))
+        ad = np.ascontiguousarray(np.array([x[3] for x in anti], dtype=np.int64))
+    nl = None
+    if node_labels is not None:
+        nl = np.ascontiguousarray(np.array(node_labels, dtype=np.int32))
+        if nl.shape != (k,):
+            raise ValueError("one label (or -1) per motif node")
     d = N.MotifDesc(k, l, ctypes.c_void_p(e.ctypes.data), int(delta),
                     None if g is None else ctypes.c_void_p(g.ctypes.data), int(pred_edge), int(pred_op),
-                    float(pred_theta))
-    return d, (e, g)  # keep arrays alive with the descriptor
+                    float(pred_theta), na, None if an is None else ctypes.c_void_p(an.ctypes.data),
+                    None if ad is None else ctypes.c_void_p(ad.ctypes.data),
+                    None if nl is None else ctypes.c_void_p(nl.ctypes.data))
+    return d, (e, g, an, ad, nl)  # keep arrays alive with the descriptor
 
 
 def motif_desc_of(m):
     """Descriptor of a synth.Motif-like object."""
-    return make_desc(m.edges, m.delta, None if m.gap is None else m.gaps(), m.pred_edge, m.pred_op, m.pred_theta)
+    return make_desc(m.edges, m.delta, None if m.gap is None else m.gaps(), m.pred_edge, m.pred_op, m.pred_theta,
+                     anti=getattr(m, "anti", None), node_labels=getattr(m, "node_labels", None))
 
 
 def motif_source(edges, delta=0, key_bytes=4, **kw) -> str:
@@ -148,8 +172,9 @@ def motif_compile_check(edges, delta=0, key_bytes=4, **kw) -> int:
     return n.value
 
 
-def batch_compile_check(motifs, key_bytes=4) -> int:
-    """Compile the batched module of synth.Motif-like objects (no device)."""
+def batch_compile_check(motifs, key_bytes=4, tier=0) -> int:
+    """Compile the batched module a count batch of synth.Motif-like objects
+    launches under ``tier`` (no device)."""
     descs = (N.MotifDesc * len(motifs))()
     keep = []
     for i, m in enumerate(motifs):
@@ -157,7 +182,7 @@ def batch_compile_check(motifs, key_bytes=4) -> int:
         descs[i] = d
         keep.append(k)
     n = ctypes.c_int64(0)
-    N.check(N.lib().tm_motif_compile_check(descs, len(motifs), key_bytes, ctypes.byref(n)))
+    N.check(N.lib().tm_batch_compile_check(descs, len(motifs), int(tier), key_bytes, ctypes.byref(n)))
     return n.value
 
 
@@ -232,11 +257,14 @@ class Context:
         return Graph(self, h)
 
     def load_synth(self, g) -> Graph:
-        return self.load_graph(g.n, g.src, g.dst, g.t, g.w)
+        dg = self.load_graph(g.n, g.src, g.dst, g.t, g.w)
+        if getattr(g, "labels", None) is not None:
+            dg.set_node_labels(g.labels)
+        return dg
 
     def compile_motif(self, edges, delta, gap=None, pred_edge=-1, pred_op=0, pred_theta=0.0,
-                      n_nodes=None) -> Motif:
-        d, keep = make_desc(edges, delta, gap, pred_edge, pred_op, pred_theta, n_nodes)
+                      n_nodes=None, anti=None, node_labels=None) -> Motif:
+        d, keep = make_desc(edges, delta, gap, pred_edge, pred_op, pred_theta, n_nodes, anti, node_labels)
         h = ctypes.c_void_p()
         N.check(N.lib().tm_compile_motif(self._h, ctypes.byref(d), ctypes.byref(h)))
         return Motif(self, h, d.n_edges)
@@ -244,7 +272,8 @@ class Context:
     def compile(self, m) -> Motif:
         """Compile a synth.Motif-like object."""
         return self.compile_motif(m.edges, m.delta, None if m.gap is None else m.gaps(), m.pred_edge, m.pred_op,
-                                  m.pred_theta)
+                                  m.pred_theta, anti=getattr(m, "anti", None),
+                                  node_labels=getattr(m, "node_labels", None))
 
     # ---- mining
     def count(self, g: Graph, m: Motif, t_lo=None, t_hi=None, stream=None) -> int:

@@ -44,7 +44,7 @@ struct DeviceGuard {
 
 void free_graph_buffers(tm_graph *g) {
     void *ptrs[] = {g->d_src, g->d_dst, g->d_tk, g->d_w, g->d_adj_t, g->d_adj_nbr, g->d_adj_eid, g->d_adj_w,
-                    g->d_off_out, g->d_off_in, g->d_pos_out, g->d_pos_in, g->d_pr_nbr, g->d_pr_t};
+                    g->d_off_out, g->d_off_in, g->d_pos_out, g->d_pos_in, g->d_pr_nbr, g->d_pr_t, g->d_nlab};
     for (void *p : ptrs)
         if (p) hipFree(p);
 }
@@ -159,6 +159,9 @@ void fill_qargs(const tm_graph *g, const tm_motif *m, int64_t r0, int64_t r1, in
     q->r1 = r1;
     q->delta = std::min<int64_t>(m->delta, span);
     for (int i = 0; i < 8; i++) q->gap[i] = std::min<int64_t>(m->gaps[i], q->delta);
+    // anti-edge windows (in slots the motif's gaps leave free), clamped to the
+    // time span like delta
+    for (int j = 0; j < m->plan.n_anti; j++) q->gap[tmo::anti_slot(j)] = std::min<int64_t>(m->plan.anti_delta[j], span);
     q->c0 = c0;
     q->nchunks = (r1 - r0 + rch - 1) / rch;
     q->theta = m->theta;
@@ -167,6 +170,8 @@ void fill_qargs(const tm_graph *g, const tm_motif *m, int64_t r0, int64_t r1, in
     q->budget = budget;
     q->split = split;
     q->split_min = (int32_t)std::min<int64_t>(split_min, INT32_MAX);
+    q->lab_mask = m->plan.lab_mask;
+    for (int v = 0; v < 8; v++) q->nlab[v] = m->plan.lab_val[v];
     tmo::fill_plan_tables(m->plan, q);
 }
 
@@ -187,6 +192,7 @@ GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w, const tmo::LaunchCfg &c
     a.pos_in = g->d_pos_in;
     a.pr_nbr = g->d_pr_nbr;
     a.pr_t = g->d_pr_t;
+    a.nlab = g->d_nlab;
     a.qa = (const QArgs *)w->qa;
     a.ctl = w->ctl;
     a.counts = w->counts;
@@ -240,14 +246,52 @@ tm_status check_pair(tm_ctx *ctx, const tm_graph *g, const tm_motif *m) {
     if (!ctx || !g || !m) return fail(TM_E_INVALID, "null context, graph or motif");
     if (g->ctx != ctx || m->ctx != ctx) return fail(TM_E_INVALID, "graph or motif belongs to another context");
     if (m->plan.pred_level >= 0 && !g->has_w) return fail(TM_E_INVALID, "motif has a weight predicate but the graph has no weights");
+    if (m->plan.lab_mask && !g->has_labels)
+        return fail(TM_E_INVALID, "motif requires vertex labels but the graph has none");
     return TM_OK;
+}
+
+// The generic (table-driven) matchers have no anti-edge checks: a motif with
+// anti-edges runs its specialised matcher under either tier.
+bool use_generic(int tier, const tmo::Plan &p) { return tier != 0 && p.n_anti == 0; }
+bool use_generic(int tier, const tm_motif *m) { return use_generic(tier, m->plan); }
+
+// The matchers of a batched launch: one per distinct structure, or under the
+// generic tier one table-driven matcher per motif length (a module that never
+// recompiles) plus the specialised matchers of motifs with anti-edges.
+// fn[i] receives query i's matcher; `gplans` holds the generic plans that
+// `plans` points to.
+void batch_plans(const std::vector<const tmo::Plan *> &qp, int tier, std::vector<tmo::Plan> *gplans,
+                 std::vector<const tmo::Plan *> *plans, std::vector<int> *fn) {
+    gplans->clear();
+    plans->clear();
+    fn->assign(qp.size(), 0);
+    if (tier) {
+        gplans->reserve(TM_MAX_EDGES);
+        for (int l = 1; l <= TM_MAX_EDGES; l++) gplans->push_back(tmo::generic_plan(l));
+        for (auto &gp : *gplans) plans->push_back(&gp);
+    }
+    std::map<std::string, int> seen;
+    for (size_t i = 0; i < qp.size(); i++) {
+        if (use_generic(tier, *qp[i])) {
+            (*fn)[i] = qp[i]->l - 1;
+            continue;
+        }
+        auto it = seen.find(qp[i]->key());
+        if (it == seen.end()) {
+            it = seen.emplace(qp[i]->key(), (int)plans->size()).first;
+            plans->push_back(qp[i]);
+        }
+        (*fn)[i] = it->second;
+    }
 }
 
 tm_status get_module(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, int tier,
                      std::shared_ptr<tmo::Module> *out) {
     std::string err;
     const tmo::Plan gp = tmo::generic_plan(m->plan.l);
-    auto mod = ctx->compiler.get(tier ? gp : m->plan, g->key_bytes, ctx->block, &err, ctx->min_waves);
+    auto mod = ctx->compiler.get(use_generic(tier, m) ? gp : m->plan, g->key_bytes, ctx->block, &err,
+                                 ctx->min_waves);
     if (!mod) return fail(TM_E_COMPILE, err);
     *out = mod;
     return TM_OK;
@@ -797,6 +841,19 @@ tm_status tm_graph_get_info(const tm_graph *g, tm_graph_info *info) {
     info->has_weights = g->has_w ? 1 : 0;
     info->device_bytes = g->device_bytes;
     info->was_sorted = g->was_sorted ? 1 : 0;
+    info->has_labels = g->has_labels ? 1 : 0;
+    return TM_OK;
+}
+
+tm_status tm_graph_set_node_labels(tm_graph *g, const int32_t *labels) {
+    if (!g || (!labels && g->n > 0)) return fail(TM_E_INVALID, "null argument");
+    for (int64_t v = 0; v < g->n; v++)
+        if (labels[v] < 0) return fail(TM_E_INVALID, "vertex labels must be >= 0");
+    DeviceGuard dg(g->device);
+    if (!g->d_nlab) HIP_TRY(dmalloc(&g->d_nlab, g->n, &g->device_bytes), "hipMalloc labels");
+    if (g->n > 0)
+        HIP_TRY(hipMemcpy(g->d_nlab, labels, (size_t)g->n * sizeof(int32_t), hipMemcpyHostToDevice), "upload labels");
+    g->has_labels = true;
     return TM_OK;
 }
 
@@ -852,7 +909,7 @@ tm_status tm_compile_motif(tm_ctx *ctx, const tm_motif_desc *desc, tm_motif **ou
     // compile eagerly for 32-bit time keys (the common case) so errors surface
     // here; with the generic tier this is the shared module of the motif length
     const tmo::Plan gp = tmo::generic_plan(m->plan.l);
-    if (!ctx->compiler.get(ctx->tier ? gp : m->plan, 4, ctx->block, &err, ctx->min_waves)) {
+    if (!ctx->compiler.get(use_generic(ctx->tier, m) ? gp : m->plan, 4, ctx->block, &err, ctx->min_waves)) {
         delete m;
         return fail(TM_E_COMPILE, err);
     }
@@ -880,20 +937,41 @@ tm_status tm_motif_source(const tm_motif_desc *desc, int32_t key_bytes, char *bu
     return TM_OK;
 }
 
-tm_status tm_motif_compile_check(const tm_motif_desc *descs, int32_t q, int32_t key_bytes, int64_t *code_bytes) {
+tm_status tm_batch_compile_check(const tm_motif_desc *descs, int32_t q, int32_t tier, int32_t key_bytes,
+                                 int64_t *code_bytes) {
     if (!descs || q < 1) return fail(TM_E_INVALID, "need at least one motif");
     if (key_bytes != 4 && key_bytes != 8) return fail(TM_E_INVALID, "key_bytes must be 4 or 8");
+    if (tier != 0 && tier != 1) return fail(TM_E_INVALID, "tier must be 0 or 1");
     std::vector<tmo::Plan> plans(q);
-    std::vector<const tmo::Plan *> uniq;
-    std::map<std::string, int> seen;
+    std::vector<const tmo::Plan *> qp(q), mods;
     for (int i = 0; i < q; i++) {
         int64_t gaps[TM_MAX_EDGES];
         std::string err;
         if (!tmo::build_plan(&descs[i], &plans[i], gaps, &err)) return fail(TM_E_INVALID, err);
-        if (seen.emplace(plans[i].key(), 1).second) uniq.push_back(&plans[i]);
+        qp[i] = &plans[i];
     }
-    std::string src = q == 1 ? tmo::generate_source(plans[0], key_bytes, 256)
-                             : tmo::generate_batch_source(uniq, key_bytes, 256);
+    std::vector<int> fn;
+    std::vector<tmo::Plan> gplans;
+    batch_plans(qp, tier, &gplans, &mods, &fn);
+    const std::string src = tmo::generate_batch_source(mods, key_bytes, 256);
+    std::vector<char> code;
+    std::string err;
+    if (!tmo::cached_code(src, &code, &err)) return fail(TM_E_COMPILE, err);
+    if (code_bytes) *code_bytes = (int64_t)code.size();
+    return TM_OK;
+}
+
+tm_status tm_motif_compile_check(const tm_motif_desc *descs, int32_t q, int32_t key_bytes, int64_t *code_bytes) {
+    if (!descs || q < 1) return fail(TM_E_INVALID, "need at least one motif");
+    if (key_bytes != 4 && key_bytes != 8) return fail(TM_E_INVALID, "key_bytes must be 4 or 8");
+    if (q > 1) return tm_batch_compile_check(descs, q, 0, key_bytes, code_bytes);
+    tmo::Plan plan;
+    {
+        int64_t gaps[TM_MAX_EDGES];
+        std::string err;
+        if (!tmo::build_plan(&descs[0], &plan, gaps, &err)) return fail(TM_E_INVALID, err);
+    }
+    std::string src = tmo::generate_source(plan, key_bytes, 256);
     std::vector<char> code;
     std::string err;
     if (!tmo::cached_code(src, &code, &err)) return fail(TM_E_COMPILE, err);
@@ -951,7 +1029,8 @@ tm_status tm_count(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_r
         return TM_OK;
     };
     const tmo::Plan gp = tmo::generic_plan(m->plan.l);
-    const std::string key = ctx->autotune ? tune_key(g, module_key(ctx, g, ctx->tier ? gp : m->plan), m->delta,
+    const std::string key = ctx->autotune ? tune_key(g, module_key(ctx, g, use_generic(ctx->tier, m) ? gp : m->plan),
+                                                     m->delta,
                                                      r1 - r0, 1)
                                           : std::string();
     std::vector<uint64_t> res;
@@ -1012,7 +1091,8 @@ tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, cons
     bool tuned = false;
     if (ctx->autotune) {
         const tmo::Plan gp = tmo::generic_plan(m->plan.l);
-        tuned = tune_lookup(ctx, tune_key(g, module_key(ctx, g, tier ? gp : m->plan), m->delta, r1 - r0, 1), &cfg);
+        tuned = tune_lookup(
+            ctx, tune_key(g, module_key(ctx, g, use_generic(tier, m) ? gp : m->plan), m->delta, r1 - r0, 1), &cfg);
     }
     const int64_t rch = chunk_for(ctx, cfg, r1 - r0);  // the same split as run_single's pass
     const int64_t chunks = (r1 - r0 + rch - 1) / rch;
@@ -1092,27 +1172,11 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
                            const tm_root_range *ranges, const int64_t *budgets, int tier, hipStream_t stream,
                            tm_ctx::Workspace *w, uint64_t *counts_out, uint8_t *cancelled) {
     DeviceGuard dg(ctx->device);
-    // one matcher per distinct structure, or with the generic tier one
-    // table-driven matcher per motif length (a module that never recompiles)
-    std::vector<const tmo::Plan *> plans;
-    std::vector<int> fn(q);
+    std::vector<const tmo::Plan *> qp(q), plans;
+    for (int i = 0; i < q; i++) qp[i] = &motifs[i]->plan;
+    std::vector<int> fn;
     std::vector<tmo::Plan> gplans;
-    if (tier) {
-        for (int l = 1; l <= TM_MAX_EDGES; l++) gplans.push_back(tmo::generic_plan(l));
-        for (auto &gp : gplans) plans.push_back(&gp);
-        for (int i = 0; i < q; i++) fn[i] = motifs[i]->plan.l - 1;
-    } else {
-        std::map<std::string, int> seen;
-        for (int i = 0; i < q; i++) {
-            std::string k = motifs[i]->plan.key();
-            auto it = seen.find(k);
-            if (it == seen.end()) {
-                it = seen.emplace(k, (int)plans.size()).first;
-                plans.push_back(&motifs[i]->plan);
-            }
-            fn[i] = it->second;
-        }
-    }
+    batch_plans(qp, tier, &gplans, &plans, &fn);
     std::string err;
     auto mod = ctx->compiler.get_batch(plans, g->key_bytes, ctx->block, &err, ctx->min_waves);
     if (!mod) return fail(TM_E_COMPILE, err);

@@ -26,6 +26,7 @@
 #include <sys/stat.h>
 #include <unistd.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -72,6 +73,11 @@ std::string Plan::key() const {
     std::ostringstream o;
     o << "l" << l << "k" << k << "p" << pred_level << ":";
     for (int i = 0; i < l; i++) o << a[i] << b[i] << ",";
+    if (lab_mask) o << "L" << lab_mask;
+    if (n_anti > 0) {
+        o << "n";
+        for (int j = 0; j < n_anti; j++) o << anti_a[j] << anti_b[j] << anti_at[j] << ",";
+    }
     return o.str();
 }
 
@@ -122,6 +128,41 @@ bool build_plan(const tm_motif_desc *d, Plan *p, int64_t *gaps, std::string *err
         p->kind[i] = am && bm ? LIST_BOTH : am ? LIST_OUT : bm ? LIST_IN : LIST_GLOBAL;
         bound[p->a[i]] = bound[p->b[i]] = true;
     }
+    // vertex labels (Sec. 5.4.1), in the relabelled node order
+    p->lab_mask = 0;
+    for (int v = 0; v < TM_MAX_NODES; v++) p->lab_val[v] = 0;
+    if (d->node_label)
+        for (int v = 0; v < k; v++) {
+            const int32_t want = d->node_label[v];
+            if (want < -1) { *err = "node labels must be -1 (any) or >= 0"; return false; }
+            if (want >= 0) {
+                p->lab_mask |= 1 << relabel[v];
+                p->lab_val[relabel[v]] = want;
+            }
+        }
+    // temporal anti-edges (Sec. 2.1): each is checked at the first level where
+    // its attach edge is matched and both its nodes are bound (Sec. 5.4.3)
+    const int na = d->n_anti;
+    if (na < 0 || na > TM_MAX_ANTI) { *err = "at most 4 anti-edges"; return false; }
+    if (na > 0 && (!d->anti || !d->anti_delta)) { *err = "anti-edge arrays are null"; return false; }
+    if (l + na > TM_MAX_EDGES + 1) { *err = "edges plus anti-edges must not exceed 9"; return false; }
+    int first[TM_MAX_NODES];
+    for (int v = 0; v < TM_MAX_NODES; v++) first[v] = -1;
+    for (int i = l - 1; i >= 0; i--) first[p->a[i]] = first[p->b[i]] = i;
+    p->n_anti = na;
+    for (int j = 0; j < na; j++) {
+        const int a = d->anti[3 * j], b = d->anti[3 * j + 1], at = d->anti[3 * j + 2];
+        if (a < 0 || a >= k || b < 0 || b >= k) { *err = "anti-edge node id out of range"; return false; }
+        if (a == b) { *err = "anti-edge with a == b"; return false; }
+        if (at < 0 || at >= l) { *err = "anti-edge attach edge out of range"; return false; }
+        if (d->anti_delta[j] < 0) { *err = "anti-edge windows must be >= 0"; return false; }
+        const int ra = relabel[a], rb = relabel[b];
+        p->anti_a[j] = ra;
+        p->anti_b[j] = rb;
+        p->anti_at[j] = at;
+        p->anti_lvl[j] = std::max(at, std::max(first[ra], first[rb]));
+        p->anti_delta[j] = d->anti_delta[j];
+    }
     return true;
 }
 
@@ -145,7 +186,9 @@ struct QArgs {
   int pred_level;
   int glob_mask;
   int split_min;
-  int pad[3];
+  int lab_mask;
+  int nlab[8];
+  int pad[2];
 };
 
 struct GArgs {
@@ -161,12 +204,15 @@ struct GArgs {
   u32* items; u64* qctl; u32 item_cap; u32 epoch;
   const u32* pos_out; const u32* pos_in;
   const int* pr_nbr; const tkey* pr_t;
+  const int* nlab;
 };
-static_assert(sizeof(QArgs) == 192, "QArgs layout");
-static_assert(sizeof(GArgs) == 224, "GArgs layout");
+static_assert(sizeof(QArgs) == 224, "QArgs layout");
+static_assert(sizeof(GArgs) == 232, "GArgs layout");
 // generic matchers: motif node slot by run-time index, and the bound-node check
 #define mget(ix) ((ix) == 0 ? m0 : (ix) == 1 ? m1 : (ix) == 2 ? m2 : (ix) == 3 ? m3 : \
                   (ix) == 4 ? m4 : (ix) == 5 ? m5 : (ix) == 6 ? m6 : m7)
+#define lget(ix) ((ix) == 0 ? l0 : (ix) == 1 ? l1 : (ix) == 2 ? l2 : (ix) == 3 ? l3 : \
+                  (ix) == 4 ? l4 : (ix) == 5 ? l5 : (ix) == 6 ? l6 : l7)
 #define mset(ix, val) do { const int v_ = (val); const int i_ = (ix); \
     m0 = i_ == 0 ? v_ : m0; m1 = i_ == 1 ? v_ : m1; m2 = i_ == 2 ? v_ : m2; m3 = i_ == 3 ? v_ : m3; \
     m4 = i_ == 4 ? v_ : m4; m5 = i_ == 5 ? v_ : m5; m6 = i_ == 6 ? v_ : m6; m7 = i_ == 7 ? v_ : m7; } while (0)
@@ -354,6 +400,55 @@ struct Emitter {
     explicit Emitter(const Plan &pl, bool generic = false) : p(pl), G(generic) {}
 
     std::string I(int i) const { return std::to_string(i); }
+
+    // Vertex labels (Sec. 5.4.1): a node newly bound by a candidate must carry
+    // the label its motif node requires (register nl<v>, a launch argument).
+    bool labelled(int v) const { return !G && ((p.lab_mask >> v) & 1); }
+    // The motif node a level's candidate binds, for list kinds OUT and IN.
+    int new_node(int i) const { return p.kind[i] == LIST_OUT ? p.b[i] : p.a[i]; }
+
+    // Temporal anti-edges (Sec. 2.1, Sec. 5.4.3). Each is checked when the
+    // candidate of its check level is accepted: the candidate is rejected when
+    // the graph holds an edge between the two mapped nodes inside the
+    // anti-edge's window.
+    bool anti_on(int i) const {
+        for (int j = 0; j < p.n_anti; j++)
+            if (p.anti_lvl[j] == i) return true;
+        return false;
+    }
+    // Level j's edge id is kept in every mode (not only when writing rows)
+    // when an anti-edge attached to it is checked at a deeper level.
+    bool keep_e(int j) const {
+        for (int x = 0; x < p.n_anti; x++)
+            if (j >= 1 && p.anti_at[x] == j && p.anti_lvl[x] > j) return true;
+        return false;
+    }
+    std::string e_cond(int j) const { return keep_e(j) ? "true" : "MODE == 3"; }
+    // Graph node of motif node v while level i's candidate is checked.
+    std::string node_at(int i, int v) const {
+        if (i == 0) return v == p.a[0] ? "s" : "d";
+        for (int u : p.mapped[i])
+            if (u == v) return "m" + I(v);
+        if (p.kind[i] == LIST_GLOBAL) return v == p.a[i] ? "cs" : "cd";
+        return "nb";  // the node the candidate binds
+    }
+    // Time of the edge matched at level `at` while level i's candidate is checked.
+    std::string time_at(int i, int at) const {
+        if (at == i) return i == 0 ? "tr" : "tt";
+        if (at == 0) return "g.tk[root]";
+        return "g.tk[e" + I(at) + "]";
+    }
+    std::string anti_cond(int i) const {
+        std::ostringstream c;
+        bool first = true;
+        for (int j = 0; j < p.n_anti; j++) {
+            if (p.anti_lvl[j] != i) continue;
+            c << (first ? "" : " && ") << "anti_free(g, " << node_at(i, p.anti_a[j]) << ", "
+              << node_at(i, p.anti_b[j]) << ", " << time_at(i, p.anti_at[j]) << ", adl" << j << ")";
+            first = false;
+        }
+        return c.str();
+    }
 
     bool has_global() const {
         if (G) return true;
@@ -556,12 +651,12 @@ struct Emitter {
         o << "            const tkey t_tmax = shf(tmaxk, srcl);\n";
         for (int v = 0; v < K; v++) o << "            const int t_m" << v << " = shf(m" << v << ", srcl);\n";
         for (int j = 1; j + 1 < L; j++)
-            o << "            const int t_e" << j << " = MODE == 3 ? shf(e" << j << ", srcl) : 0;\n";
+            o << "            const int t_e" << j << " = " << e_cond(j) << " ? shf(e" << j << ", srcl) : 0;\n";
         o << "            if (thief) {\n";
         o << "              lvl = t_dj; base = t_dj; ph = 0; root = t_root; mych = t_mych; tmaxk = t_tmax;\n";
         o << "              exact = 1u << t_dj;\n";
         for (int v = 0; v < K; v++) o << "              m" << v << " = t_m" << v << ";\n";
-        for (int j = 1; j + 1 < L; j++) o << "              if (MODE == 3) e" << j << " = t_e" << j << ";\n";
+        for (int j = 1; j + 1 < L; j++) o << "              if (" << e_cond(j) << ") e" << j << " = t_e" << j << ";\n";
         o << "              switch (t_dj) {\n";
         for (int i = 1; i < L; i++) {
             o << "                case " << i << ": cur" << i << " = t_ds; end" << i << " = t_de; hi" << i
@@ -593,7 +688,7 @@ struct Emitter {
         o << "              st_ag64(it + 10, (i64)tmaxk);\n";
         for (int v = 0; v < K; v++) o << "              st_ag(it + " << 12 + v << ", (u32)m" << v << ");\n";
         for (int j = 1; j + 1 < L; j++)
-            o << "              if (MODE == 3) st_ag(it + " << 19 + j << ", (u32)e" << j << ");\n";
+            o << "              if (" << e_cond(j) << ") st_ag(it + " << 19 + j << ", (u32)e" << j << ");\n";
         o << "              mem_order();\n";
         o << "              st_ag(it, g.epoch);\n";
         o << "              pushed = true;\n";
@@ -632,7 +727,8 @@ struct Emitter {
         o << ind << "  lvl = j; base = j; ph = 0; exact = 1u << j;\n";
         o << ind << "  root = (int)ld_ag(it + 7); mych = ld_ag64(it + 8); tmaxk = (tkey)ld_ag64(it + 10);\n";
         for (int v = 0; v < K; v++) o << ind << "  m" << v << " = (int)ld_ag(it + " << 12 + v << ");\n";
-        for (int j = 1; j + 1 < L; j++) o << ind << "  if (MODE == 3) e" << j << " = (int)ld_ag(it + " << 19 + j << ");\n";
+        for (int j = 1; j + 1 < L; j++)
+            o << ind << "  if (" << e_cond(j) << ") e" << j << " = (int)ld_ag(it + " << 19 + j << ");\n";
         o << ind << "  const u32 i_s = ld_ag(it + 2), i_e = ld_ag(it + 3); const tkey i_h = (tkey)ld_ag64(it + 4);\n";
         o << ind << "  const int i_w = (int)ld_ag(it + 6);\n";
         o << ind << "  switch (j) {\n";
@@ -646,17 +742,20 @@ struct Emitter {
         o << ind << "}\n";
     }
 
-    bool coop_ok() const { return p.l > 1 && (G || p.kind[p.l - 1] != LIST_GLOBAL); }
+    // (not when an anti-edge is checked on the last level: each candidate
+    // then needs its own search)
+    bool coop_ok() const { return p.l > 1 && (G || p.kind[p.l - 1] != LIST_GLOBAL) && !anti_on(p.l - 1); }
 
     // Whether the last level's count has a closed form: both endpoints bound
     // (the edges between two given nodes in the time window), or one new
     // endpoint (the window's size minus the edges to each already bound node,
     // the node itself included, since the new node must differ from all of
-    // them). Not with a weight predicate on that level. Generic matchers decide
+    // them). Not with a weight predicate, an anti-edge or a label on the new node of that level. Generic matchers decide
     // at run time.
     bool leaf_countable() const {
         const int i = p.l - 1;
-        return G || (p.l > 1 && p.kind[i] != LIST_GLOBAL && p.pred_level != i);
+        return G || (p.l > 1 && p.kind[i] != LIST_GLOBAL && p.pred_level != i && !anti_on(i) &&
+                     !(p.kind[i] != LIST_BOTH && labelled(new_node(i))));
     }
 
     // Closed-form count of the last level's window (registers cur, end, hi of
@@ -707,10 +806,10 @@ struct Emitter {
         if (!leaf_countable()) return;
         const std::string s = I(i);
         const char *ind = "            ";
-        const std::string gc = G ? " && gpl != " + s : std::string();
+        const std::string gc = G ? " && gpl != " + s + " && !glabl" : std::string();
         o << ind << "if ((MODE == 0 || MODE == 2) && wide && g.leaf_min > 0 && sb + (u32)g.leaf_min - 1u < end" << s
           << " && g.adj_t[sb + (u32)g.leaf_min - 1u] <= hi" << s << gc << ") park = true;\n";
-        const std::string gcond = G ? " && !((gglob >> " + s + ") & 1u) && gpl != " + s : std::string();
+        const std::string gcond = G ? " && !((gglob >> " + s + ") & 1u) && gpl != " + s + " && !glabl" : std::string();
         o << ind << "if (MODE == 1 && g.leaf_min > 0" << gcond << ") {\n";
         o << ind << "  const u32 pk = sb + (u32)g.leaf_min - 1u;\n";
         o << ind << "  if (pk < end" << s << " && g.adj_t[pk] <= hi" << s << ") {\n";
@@ -762,6 +861,8 @@ struct Emitter {
             o << "        const int w_ = rl(want" << i << ", j);\n";
             for (int v = 0; v < 8; v++) o << "        const int x" << v << " = rl(m" << v << ", j);\n";
             ok << "(gk" << i << " == 2 ? nb == w_ : notin(gm" << i << ", nb, x0, x1, x2, x3, x4, x5, x6, x7))";
+            ok << " && (gk" << i << " == 2 || ((glm >> gn" << i << ") & 1u) == 0u || g.nlab[nb] == lget(gn" << i
+               << "))";
         } else if (p.kind[i] == LIST_BOTH) {
             o << "        const int w_ = rl(want" << i << ", j);\n";
             ok << "nb == w_";
@@ -771,6 +872,7 @@ struct Emitter {
                 o << "        const int x" << v << " = rl(m" << v << ", j);\n";
                 ok << " && nb != x" << v;
             }
+            if (labelled(new_node(i))) ok << " && g.nlab[nb] == nl" << new_node(i);
         }
         o << "        int o_root = 0; i64 o_ch = 0;\n";
         o << "        if (MODE == 3) { o_root = rl(root, j); o_ch = rl(mych, j); }\n";
@@ -824,6 +926,20 @@ struct Emitter {
         const int L = p.l, K = p.k;
         const bool glob = has_global();
         o << "// motif " << p.key() << "\n";
+        if (p.n_anti > 0) {
+            o << "#ifndef TM_ANTI_FREE\n#define TM_ANTI_FREE\n";
+            o << "// No edge u -> v with time in [t0, t0 + d]: find v's run in u's out-list\n";
+            o << "// sorted by (neighbour, time), then the run's first entry with time >= t0.\n";
+            o << "__device__ __forceinline__ bool anti_free(const GArgs& g, int u, int v, tkey t0, i64 d) {\n";
+            o << "  const u32 lo = g.off_out[u], hi = g.off_out[u + 1];\n";
+            o << "  u32 pr = 0u;\n";
+            o << "  const u32 s = nbr_lb(g.pr_nbr, lo, hi, v, pr);\n";
+            o << "  if (s >= hi || g.pr_nbr[s] != v) return true;\n";
+            o << "  const u32 f = run_ub(g.pr_nbr, g.pr_t, s, hi, v, (tkey)(t0 - 1), pr);\n";
+            o << "  if (f >= hi || g.pr_nbr[f] != v) return true;\n";
+            o << "  return (i64)g.pr_t[f] > (i64)t0 + d;\n";
+            o << "}\n#endif\n";
+        }
         o << "template <int MODE>\n__device__ __forceinline__ i64 match" << fi
           << "(const GArgs& g, int qi, i64 chunk, i64 ih, int in) {\n";
         o << "  const int lane = lane_id();\n";
@@ -834,13 +950,23 @@ struct Emitter {
         o << "  const i64 q_nch = q->nchunks, q_n = q->r1 - q->r0, q_budget = q->budget;\n";
         o << "  const bool q_split = g.split && q->split; const u32 q_smin = (u32)q->split_min;\n";
         for (int i = 0; i + 1 < L; i++) o << "  const i64 gap" << i << " = q->gap[" << i << "];\n";
+        for (int j = 0; j < p.n_anti; j++) o << "  const i64 adl" << j << " = q->gap[" << anti_slot(j) << "];\n";
         if (G || p.pred_level >= 0) o << "  const float theta = q->theta; const int pop = q->pred_op;\n";
+        for (int v = 0; v < K; v++)
+            if (labelled(v)) o << "  const int nl" << v << " = q->nlab[" << v << "];\n";
         if (G) {
             o << "  const int gpl = q->pred_level; const u32 gglob = (u32)q->glob_mask;\n";
             for (int i = 1; i < L; i++)
                 o << "  const int gk" << i << " = q->pk[" << i << "], ga" << i << " = q->pa[" << i << "], gb" << i
                   << " = q->pb[" << i << "], gj" << i << " = q->pj[" << i << "]; const u32 gm" << i << " = q->pm["
                   << i << "];\n";
+            o << "  const u32 glm = (u32)q->lab_mask;\n";
+            o << "  const int l0 = q->nlab[0], l1 = q->nlab[1], l2 = q->nlab[2], l3 = q->nlab[3], l4 = q->nlab[4], "
+                 "l5 = q->nlab[5], l6 = q->nlab[6], l7 = q->nlab[7];\n";
+            for (int i = 1; i < L; i++)
+                o << "  const int gn" << i << " = gk" << i << " == 0 ? gb" << i << " : ga" << i << ";\n";
+            if (L > 1)
+                o << "  const bool glabl = gk" << L - 1 << " != 2 && ((glm >> gn" << L - 1 << ") & 1u) != 0u;\n";
         }
         o << "  int lvl = 0, ph = 0, root = 0, base = 1, cool = 0;\n";
         o << "  u32 exact = 0u;  // bit i: end of level i's window is its exact extent\n";
@@ -908,10 +1034,15 @@ struct Emitter {
             o << "          if (MODE == 1) { st_root++; if (gpl == 0) st_pv++; }\n";
             o << "          bool ok = s != d;\n";
             o << "          if (gpl == 0) ok = ok && pred_ok(g.w[r], pop, theta);\n";
+            o << "          if (glm & 1u) ok = ok && g.nlab[s] == l0;\n";
+            o << "          if (glm & 2u) ok = ok && g.nlab[d] == l1;\n";
         } else {
             o << "          if (MODE == 1) { st_root++;" << (p.pred_level == 0 ? " st_pv++;" : "") << " }\n";
             o << "          bool ok = s != d;\n";
             if (p.pred_level == 0) o << "          ok = ok && pred_ok(g.w[r], pop, theta);\n";
+            if (labelled(p.a[0])) o << "          ok = ok && g.nlab[s] == nl" << p.a[0] << ";\n";
+            if (labelled(p.b[0])) o << "          ok = ok && g.nlab[d] == nl" << p.b[0] << ";\n";
+            if (anti_on(0)) o << "          ok = ok && " << anti_cond(0) << ";\n";
         }
         o << "          if (ok) {\n";
         o << "            root = r; mych = myc; base = 1;\n";
@@ -1052,6 +1183,14 @@ struct Emitter {
                     o << "            ok = cs != cd && notin(gm" << s << ", cs, " << ms << ") && notin(gm" << s
                       << ", cd, " << ms << "); }\n";
                     o << "          else ok = notin(gm" << s << ", nb, " << ms << ");\n";
+                    o << "          if (glm != 0u) {\n";
+                    o << "            if (gk" << s << " == 3) {\n";
+                    o << "              if ((glm >> ga" << s << ") & 1u) ok = ok && g.nlab[cs] == lget(ga" << s << ");\n";
+                    o << "              if ((glm >> gb" << s << ") & 1u) ok = ok && g.nlab[cd] == lget(gb" << s << ");\n";
+                    o << "            } else if (gk" << s << " != 2 && ((glm >> gn" << s << ") & 1u)) {\n";
+                    o << "              ok = ok && g.nlab[nb] == lget(gn" << s << ");\n";
+                    o << "            }\n";
+                    o << "          }\n";
                     o << "          if (gpl == " << i << ") ok = ok && pred_ok(wv, pop, theta);\n";
                     o << "          if (ok) {\n";
                     if (i == L - 1) {
@@ -1076,6 +1215,7 @@ struct Emitter {
                 case LIST_IN: {
                     ok << "true";
                     for (int v : p.mapped[i]) ok << " && nb != m" << v;
+                    if (labelled(new_node(i))) ok << " && g.nlab[nb] == nl" << new_node(i);
                     bind = "m" + std::to_string(p.kind[i] == LIST_OUT ? B : A) + " = nb;";
                     eid = "g.adj_eid[c]";
                     break;
@@ -1088,18 +1228,21 @@ struct Emitter {
                     o << "          const int cs = g.src[c], cd = g.dst[c];\n";
                     ok << "cs != cd";
                     for (int v : p.mapped[i]) ok << " && cs != m" << v << " && cd != m" << v;
+                    if (labelled(A)) ok << " && g.nlab[cs] == nl" << A;
+                    if (labelled(B)) ok << " && g.nlab[cd] == nl" << B;
                     bind = "m" + std::to_string(A) + " = cs; m" + std::to_string(B) + " = cd;";
                     eid = "(int)c";
                 }
                 }
                 o << "          bool ok = " << ok.str() << ";\n";
                 if (p.pred_level == i) o << "          ok = ok && pred_ok(wv, pop, theta);\n";
+                if (anti_on(i)) o << "          ok = ok && " << anti_cond(i) << ";\n";
                 o << "          if (ok) {\n";
                 if (i == L - 1) {
                     leaf("            ", eid.c_str());
                 } else {
                     if (!bind.empty()) o << "            " << bind << "\n";
-                    o << "            if (MODE == 3) e" << i << " = " << eid << ";\n";
+                    o << "            if (" << e_cond(i) << ") e" << i << " = " << eid << ";\n";
                     open(i + 1, "tt", "            ");
                 }
                 o << "          }\n";

@@ -39,9 +39,11 @@ struct QArgs {
     int32_t pred_level;
     int32_t glob_mask;  // bit i: level i scans the whole edge list
     int32_t split_min;  // smallest pending window this query splits
-    int32_t pad[3];
+    int32_t lab_mask;   // bit v: motif node v requires the vertex label nlab[v]
+    int32_t nlab[8];
+    int32_t pad[2];
 };
-static_assert(sizeof(QArgs) == 192, "QArgs layout");
+static_assert(sizeof(QArgs) == 224, "QArgs layout");
 
 struct GArgs {
     const int32_t *src;
@@ -75,8 +77,9 @@ struct GArgs {
     const uint32_t *pos_in;   // per edge: its position in its destination's in-list
     const int32_t *pr_nbr;    // adjacency sorted by (neighbour, time), same offsets
     const void *pr_t;
+    const int32_t *nlab;      // vertex labels (n entries) or null
 };
-static_assert(sizeof(GArgs) == 224, "GArgs layout");
+static_assert(sizeof(GArgs) == 232, "GArgs layout");
 
 // ctl words: [10..12] work counters of the windows counted without a scan,
 // [13] donated items waiting in all queues
@@ -96,8 +99,23 @@ struct Plan {
     std::vector<int> mapped[TM_MAX_EDGES];  // motif nodes bound before level i
     int pred_level = -1;
     bool generic = false;  // table-driven matcher for every motif with l edges
+    // temporal anti-edges: motif nodes, attach edge, and the level at which
+    // each is checked (its attach edge matched and both nodes bound)
+    int n_anti = 0;
+    int anti_a[TM_MAX_ANTI] = {}, anti_b[TM_MAX_ANTI] = {}, anti_at[TM_MAX_ANTI] = {}, anti_lvl[TM_MAX_ANTI] = {};
+    // anti-edge windows: launch values (in the gap slots the motif leaves
+    // free), not part of the structure key
+    int64_t anti_delta[TM_MAX_ANTI] = {};
+    // vertex labels: bit v of lab_mask = motif node v requires lab_val[v]
+    // (the mask is structure, the values are launch arguments)
+    int lab_mask = 0;
+    int32_t lab_val[TM_MAX_NODES] = {};
     std::string key() const;
 };
+
+// Launch-argument slot of anti-edge j's window: the gap slots from the top
+// down, which a motif of l edges leaves free when l + n_anti <= 9.
+inline int anti_slot(int j) { return 7 - j; }
 
 Plan generic_plan(int l);
 // Fill the plan tables a generic matcher reads (and that specialised ones ignore).
@@ -240,6 +258,8 @@ struct tm_graph {
     uint32_t *d_pos_out = nullptr, *d_pos_in = nullptr;
     int32_t *d_pr_nbr = nullptr;  // adjacency sorted by (neighbour, time): out [0,m), in [m,2m)
     void *d_pr_t = nullptr;
+    int32_t *d_nlab = nullptr;    // vertex labels (n entries), once attached
+    bool has_labels = false;
     std::vector<int64_t> h_t;     // sorted absolute times (root-range lookup)
     std::vector<int64_t> perm;    // empty when the input was sorted
     int64_t device_bytes = 0;

@@ -139,6 +139,12 @@ void publish(tm_server *s, const Pending &p, tm_status st, uint64_t count, int64
     s->cv_results.notify_all();
 }
 
+// A query launched on its own: an enumeration, or under the generic tier a
+// count with anti-edges (which the table-driven matchers lack; alone it runs
+// its own specialised matcher, compiled once per structure, instead of making
+// every batch it joins a module of its own).
+bool alone(const tm_server *s, const Pending *p) { return p->enumerate || (s->cfg.tier && p->motif.plan.n_anti > 0); }
+
 void slot_main(tm_server *s) {
     tm_ctx *ctx = s->ctx;
     hipSetDevice(ctx->device);
@@ -157,11 +163,11 @@ void slot_main(tm_server *s) {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_pending.wait(lk, [&] { return s->stopping || !s->pending.empty(); });
             if (s->pending.empty()) break;  // stopping and drained
-            if (s->pending.front()->enumerate) {
+            if (alone(s, s->pending.front())) {
                 batch.push_back(s->pending.front());
                 s->pending.pop_front();
             } else {
-                while (!s->pending.empty() && !s->pending.front()->enumerate &&
+                while (!s->pending.empty() && !alone(s, s->pending.front()) &&
                        (int)batch.size() < s->cfg.max_batch) {
                     batch.push_back(s->pending.front());
                     s->pending.pop_front();
@@ -206,9 +212,9 @@ void slot_main(tm_server *s) {
             counts.assign(batch.size(), 0);
             cancelled.assign(batch.size(), 0);
             const int64_t t_launch = now_ns();
+            const int tier = batch[0]->motif.plan.n_anti > 0 ? 0 : s->cfg.tier;
             tm_status st = tmo::count_batch_impl(ctx, s->g, (int)batch.size(), motifs.data(), ranges.data(),
-                                                 budgets.data(), s->cfg.tier, stream, w, counts.data(),
-                                                 cancelled.data());
+                                                 budgets.data(), tier, stream, w, counts.data(), cancelled.data());
             for (size_t i = 0; i < batch.size(); i++) {
                 const tm_status qs = st != TM_OK ? st : cancelled[i] ? TM_E_CANCELLED : TM_OK;
                 publish(s, *batch[i], qs, qs == TM_OK ? counts[i] : 0, nullptr, 0, t_launch);

@@ -64,6 +64,12 @@ def test_random_batch_motifs_compile():
     dict(edges=[(0, 1), (1, 2)], delta=1, gap=[-1]),  # negative gap
     dict(edges=[(0, 1)], delta=1, pred_edge=1),      # predicate edge out of range
     dict(edges=[(0, 1)], delta=1, pred_edge=0, pred_op=9),
+    dict(edges=[(0, 1), (1, 2)], delta=1, anti=[(0, 0, 0, 5)]),      # anti-edge with a == b
+    dict(edges=[(0, 1), (1, 2)], delta=1, anti=[(0, 3, 0, 5)]),      # anti-edge node not on an edge
+    dict(edges=[(0, 1), (1, 2)], delta=1, anti=[(0, 1, 2, 5)]),      # attach edge out of range
+    dict(edges=[(0, 1), (1, 2)], delta=1, anti=[(0, 1, 0, -1)]),     # negative window
+    dict(edges=[(0, 1), (1, 2)], delta=1, anti=[(0, 2, 0, 1)] * 5),  # more than four
+    dict(edges=[(i, (i + 1) % 8) for i in range(8)], delta=1, anti=[(0, 2, 0, 1), (1, 3, 0, 1)]),  # 8 + 2 > 9
 ])
 def test_invalid_motifs_rejected(bad):
     with pytest.raises(N.NativeError) as ei:
@@ -96,3 +102,23 @@ def test_motif_relabelled_to_first_appearance():
     a = api.motif_source([(2, 0), (0, 1)], 100)
     b = api.motif_source([(0, 1), (1, 2)], 100)
     assert a == b
+
+
+def test_anti_edge_checks_in_source():
+    """Each anti-edge is checked on the level where its attach edge is matched
+    and both its nodes are bound, reading the attach edge's time from the
+    candidate, the root or a kept edge id; one on the last level turns the
+    wavefront-cooperative and closed-form last level off."""
+    src = api.motif_source(synth.FOUR_CYCLE, 100, anti=[(2, 0, 2, 60), (3, 1, 1, 5)])
+    assert "anti_free(g, m2, m0, tt, adl0) && anti_free(g, nb, m1, g.tk[e1], adl1)" in src
+    assert "const i64 adl0 = q->gap[7];" in src and "const i64 adl1 = q->gap[6];" in src
+    assert "if (true) e1 = g.adj_eid[c];" in src  # e1 kept in every mode
+    star = api.motif_source(synth.OUT_STAR3, 100, anti=[(1, 2, 0, 10)])
+    assert "anti_free(g, m1, nb, g.tk[root], adl0)" in star
+    root = api.motif_source([(0, 1), (1, 2)], 100, anti=[(1, 0, 0, 10)])
+    assert "ok = ok && anti_free(g, d, s, tr, adl0);" in root
+    plain = api.motif_source(synth.TRIANGLE, 100)
+    last = api.motif_source(synth.TRIANGLE, 100, anti=[(2, 1, 2, 10)])
+    assert "ballot(ph == 3)" in plain and "ballot(ph == 3)" not in last
+    assert "wide && g.leaf_min" in plain and "wide && g.leaf_min" not in last
+    assert "anti_free" not in plain
