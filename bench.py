@@ -22,7 +22,8 @@ half with a weight predicate) as one persistent launch against 64
 synchronised single-query launches. "constraints" times the 4-cycle at
 delta = 86400 s on the same wiki-shaped graph with the constraints added one
 after another, as the paper's table of additional constraints does (Sec. 6):
-none, fine-grained gaps, then also a temporal anti-edge.
+none, vertex labels (two random labels), then also fine-grained gaps, then
+also a temporal anti-edge.
 """
 from __future__ import annotations
 
@@ -156,16 +157,20 @@ def bench_batch64(ctx, args, stream):
 
 
 def bench_constraints(ctx, dg, args, stream):
-    """The 4-cycle (delta = 86400 s) with no constraint (N), with every
-    consecutive gap <= 21600 s (T), and with those gaps plus an anti-edge from
-    motif node 2 to node 0 within 3600 s after edge 2 (T+A): count and the
-    time of one autotuned, synchronised tm_count each."""
+    """The 4-cycle (delta = 86400 s) with constraints added one after another:
+    none (N); two nodes of each of two random vertex labels (V); also every
+    consecutive gap <= 21600 s (V+T); also an anti-edge from motif node 2 to
+    node 0 within 3600 s after edge 2 (V+T+A). Count and the time of one
+    autotuned, synchronised tm_count each."""
     import torch
     from paper_2310_02800_amd import synth
+    dg.set_node_labels(synth.node_labels(2, dg.info()["n_nodes"], 2))
     four = list(synth.FOUR_CYCLE)
+    lab = [0, 1, 0, 1]
     forms = {"N": synth.Motif(four, 86_400),
-             "T": synth.Motif(four, 86_400, gap=[21_600] * 3),
-             "T+A": synth.Motif(four, 86_400, gap=[21_600] * 3, anti=[(2, 0, 2, 3600)])}
+             "V": synth.Motif(four, 86_400, node_labels=lab),
+             "V+T": synth.Motif(four, 86_400, gap=[21_600] * 3, node_labels=lab),
+             "V+T+A": synth.Motif(four, 86_400, gap=[21_600] * 3, anti=[(2, 0, 2, 3600)], node_labels=lab)}
     out = {}
     for name, mot in forms.items():
         h = ctx.compile(mot)
@@ -179,8 +184,48 @@ def bench_constraints(ctx, dg, args, stream):
         ms = (time.perf_counter() - t0) / args.steps * 1e3
         out[name] = {"count": c, "ms": ms}
         log(f"constraints {name}: {c} instances, {ms:.2f} ms")
-    return {"workload": "wiki-shaped graph, 4-cycle, delta 86400 s; T: gaps <= 21600 s; A: anti-edge 2->0 "
-                        "within 3600 s after edge 2", "forms": out}
+    return {"workload": "wiki-shaped graph, 4-cycle, delta 86400 s; V: node labels 0,1,0,1 of two uniform random "
+                        "labels; T: gaps <= 21600 s; A: anti-edge 2->0 within 3600 s after edge 2", "forms": out}
+
+
+def bench_tail(ctx, handles, dg, stream, label):
+    """Load balance over time of one batched launch, sampled every 20 us from
+    a side stream (TM_PARAM_TRACE_US), with splitting off and on: when the
+    root-chunk queue drained and how long wavefronts kept working after it
+    (the tail that the paper's relaunch-based redistribution targets)."""
+    import torch
+    from paper_2310_02800_amd import _native as N
+    from paper_2310_02800_amd import api
+    out = {}
+    old = {p: ctx.get_param(p) for p in (N.TM_PARAM_SPLIT, N.TM_PARAM_AUTOTUNE, N.TM_PARAM_TRACE_US)}
+    try:
+        ctx.set_param(N.TM_PARAM_AUTOTUNE, 0)
+        for split in (0, 1):
+            ctx.set_param(N.TM_PARAM_SPLIT, split)
+            ctx.set_param(N.TM_PARAM_TRACE_US, 0)
+            ctx.count_batch(dg, handles, stream=stream)  # warm
+            ctx.set_param(N.TM_PARAM_TRACE_US, 20)
+            ctx.count_batch(dg, handles, stream=stream)
+            torch.cuda.synchronize()
+            summ = api.tail_summary(ctx.last_trace())
+            out["split" if split else "no_split"] = summ
+            log(f"tail {label} split={split}: {summ}")
+    finally:
+        for p, v in old.items():
+            ctx.set_param(p, v)
+    return out
+
+
+def bench_tail_skew(ctx, args, stream):
+    """The heavy-skew graph (10M nodes, 50M edges, hubs of degree 1e6+) and
+    its 5-edge motif, sampled as in bench_tail."""
+    from paper_2310_02800_amd import synth
+    log("tail: generating the heavy-skew graph")
+    g = synth.skew_graph()
+    dg = ctx.load_synth(g)
+    res = bench_tail(ctx, [ctx.compile(synth.skew_query())], dg, stream, "skew")
+    res["workload"] = "heavy-skew graph n=1e7 m=5e7, 5-edge 4-node motif, gaps <= 600 s, delta 3600 s"
+    return res
 
 
 def rows_checksum(rows):
@@ -373,6 +418,9 @@ def main():
     ap.add_argument("--tune-table", default=None,
                     help="load launch settings from this file if it exists, save them there at the end")
     ap.add_argument("--no-batch64", action="store_true", help="skip the 64-query batch on the small graph")
+    ap.add_argument("--no-tail", action="store_true", help="skip sampling the headline launch's load balance")
+    ap.add_argument("--tail-skew", action="store_true",
+                    help="also sample the load balance on the heavy-skew graph (generates 50M edges)")
     ap.add_argument("--no-constraints", action="store_true",
                     help="skip the 4-cycle with added constraints (gaps, anti-edge)")
     ap.add_argument("--serve-queries", type=int, default=500,
@@ -556,6 +604,8 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
+    if not args.no_tail:
+        out["tail"] = bench_tail(ctx, handles, dg, stream, "wiki")
     if not args.no_constraints:
         out["constraints"] = bench_constraints(ctx, dg, args, stream)
     if not args.no_batch64:
@@ -564,6 +614,8 @@ def main():
         out["serve"] = bench_serve(ctx, dg, g, args)
     if args.tune_table:
         ctx.tune_save(args.tune_table)
+    if args.tail_skew:
+        out["tail_skew"] = bench_tail_skew(ctx, args, stream)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(g, motifs, args.cpu_budget)

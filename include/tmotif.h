@@ -118,6 +118,11 @@ void tm_destroy(tm_ctx *ctx);
  *                          candidates (default 512) whose count has a closed form is
  *                          counted with binary searches instead of a scan (see
  *                          tm_work_stats); 0 = always scan; else 32..2^24
+ *   TM_PARAM_TRACE_US      0 (default) = off; 10..100000 = while each mining kernel
+ *                          runs, sample its control words every this many
+ *                          microseconds from a side stream (the kernel is not
+ *                          changed; the call blocks until the kernel ends); read
+ *                          the samples of the last launch with tm_last_trace
  */
 enum {
     TM_PARAM_BLOCK = 1,
@@ -130,9 +135,24 @@ enum {
     TM_PARAM_AUTOTUNE = 9,
     TM_PARAM_WORK_BUDGET = 10,
     TM_PARAM_MIN_WAVES = 11,
-    TM_PARAM_LEAF_MIN = 12
+    TM_PARAM_LEAF_MIN = 12,
+    TM_PARAM_TRACE_US = 13
 };
 tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t value);
+
+/* Samples of the last mining launch taken with TM_PARAM_TRACE_US > 0, 7 int64
+ * per sample in time order (the load balance over time, Sec. 5.2.2):
+ *   0 host nanoseconds since the launch was queued
+ *   1 root chunks taken from the queue (>= column 2 once the queue is empty;
+ *     every wavefront that finds it empty adds one)
+ *   2 root chunks of the launch
+ *   3 wavefronts inside a matcher
+ *   4 wavefronts waiting for donated work
+ *   5 donated work items waiting in the queues
+ *   6 1 on the last sample, taken after the kernel ended
+ * out: host int64[cap][7], may be NULL when cap is 0; *n_out (host) receives
+ * the number of samples (at most cap rows are written). */
+tm_status tm_last_trace(tm_ctx *ctx, int64_t *out, int64_t cap, int64_t *n_out);
 tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
 
 /* Autotuning (the launch-setting counterpart of the paper's hyper-parameter
@@ -241,14 +261,14 @@ tm_status tm_graph_copy_csr(const tm_graph *g, int32_t dir, uint32_t *off, int32
  *   anti        host int32[3*n_anti] or NULL when n_anti is 0: a, b, i per
  *               anti-edge; a != b are motif nodes that appear on edges, i is the
  *               motif edge it is attached to
- *   node_label  host int32[n_nodes] or NULL: the vertex label each motif node
- *               requires (Sec. 5.4.1), -1 = any; checked when the node is
- *               first matched. Label values are launch arguments; which nodes
- *               carry one is part of the structure.
  *   anti_delta  host int64[n_anti], entries >= 0: a match is rejected when the
  *               graph has any edge phi(a) -> phi(b) (one of the match's own
  *               edges included) whose time lies in the closed range
  *               [t(e_i), t(e_i) + anti_delta]
+ *   node_label  host int32[n_nodes] or NULL: the vertex label each motif node
+ *               requires (Sec. 5.4.1), -1 = any; checked when the node is
+ *               first matched. Label values are launch arguments; which nodes
+ *               carry one is part of the structure.
  *
  * An anti-edge is checked when the candidate of level max(i, first level
  * binding a, first level binding b) is accepted, and a hit ends that branch of

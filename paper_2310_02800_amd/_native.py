@@ -18,12 +18,12 @@ STATUS_NAMES = {0: "TM_OK", 1: "TM_E_INVALID", 2: "TM_E_OOM", 3: "TM_E_COMPILE",
 
 TM_PARAM_BLOCK, TM_PARAM_ROOT_CHUNK, TM_PARAM_GRID = 1, 2, 3
 TM_PARAM_PROFILE, TM_PARAM_SPLIT, TM_PARAM_SPLIT_MIN, TM_PARAM_TIER, TM_PARAM_AUTOTUNE = 5, 6, 7, 8, 9
-TM_PARAM_WORK_BUDGET, TM_PARAM_MIN_WAVES, TM_PARAM_LEAF_MIN = 10, 11, 12
+TM_PARAM_WORK_BUDGET, TM_PARAM_MIN_WAVES, TM_PARAM_LEAF_MIN, TM_PARAM_TRACE_US = 10, 11, 12, 13
 
 # Every function the header declares, for the export check.
 EXPORTED = [
     "tm_last_error", "tm_version", "tm_create", "tm_destroy", "tm_set_param", "tm_get_param", "tm_last_kernel_ms",
-    "tm_last_launch", "tm_tune_save", "tm_tune_load", "tm_tune_clear",
+    "tm_last_launch", "tm_last_trace", "tm_tune_save", "tm_tune_load", "tm_tune_clear",
     "tm_load_graph", "tm_free_graph", "tm_graph_get_info", "tm_graph_edge_order", "tm_graph_copy_csr",
     "tm_graph_set_node_labels",
     "tm_compile_motif", "tm_free_motif", "tm_motif_source", "tm_motif_compile_check", "tm_batch_compile_check",
@@ -103,6 +103,7 @@ def lib():
         "tm_get_param": (i32, [P, i32, P]),
         "tm_last_kernel_ms": (i32, [P, P, P]),
         "tm_last_launch": (i32, [P, P, P, P, P, P]),
+        "tm_last_trace": (i32, [P, P, i64, P]),
         "tm_tune_save": (i32, [P, ctypes.c_char_p]),
         "tm_tune_load": (i32, [P, ctypes.c_char_p]),
         "tm_tune_clear": (i32, [P, P]),

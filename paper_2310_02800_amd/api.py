@@ -226,6 +226,16 @@ class Context:
         """(root chunk, split flag, tuned flag) of the last mining call."""
         return self.last_launch_full()[:3]
 
+    def last_trace(self) -> np.ndarray:
+        """Samples of the last mining launch taken with TM_PARAM_TRACE_US > 0:
+        int64[n, 7] rows of (ns since queued, chunks taken, chunks, busy
+        wavefronts, waiting wavefronts, donated items waiting, done)."""
+        n = ctypes.c_int64(0)
+        N.check(N.lib().tm_last_trace(self._h, None, 0, ctypes.byref(n)))
+        out = np.zeros((n.value, 7), np.int64)
+        N.check(N.lib().tm_last_trace(self._h, _ptr(out), n.value, ctypes.byref(n)))
+        return out[:n.value]
+
     def last_launch_full(self):
         """(root chunk, split flag, tuned flag, smallest split window, smallest
         window counted in closed form) of the last mining call."""
@@ -416,3 +426,24 @@ class Server:
             self.stop()
         except Exception:
             pass
+
+
+def tail_summary(samples) -> dict:
+    """Load balance of one sampled launch: when its root-chunk queue drained
+    and what ran after that. Times from the first sample with a wavefront at
+    work (or a chunk taken) to the first sample after the kernel ended, so
+    they carry the sampling period as error."""
+    s = np.asarray(samples)
+    if s.shape[0] == 0:
+        return {}
+    started = np.nonzero((s[:, 1] > 0) | (s[:, 3] > 0))[0]
+    t_start = int(s[started[0], 0]) if started.size else int(s[0, 0])
+    t_end = int(s[-1, 0])
+    drained = np.nonzero(s[:, 1] >= s[:, 2])[0]
+    t_drain = int(s[drained[0], 0]) if drained.size else t_end
+    tail = s[(s[:, 0] >= t_drain) & (s[:, 6] == 0)]
+    span = max(t_end - t_start, 1)
+    return {"samples": int(s.shape[0]), "run_ms": span / 1e6, "drain_ms": (t_drain - t_start) / 1e6,
+            "tail_ms": (t_end - t_drain) / 1e6, "tail_frac": (t_end - t_drain) / span,
+            "busy_after_drain_mean": float(tail[:, 3].mean()) if tail.shape[0] else 0.0,
+            "busy_peak": int(s[:, 3].max())}

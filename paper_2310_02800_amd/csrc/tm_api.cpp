@@ -1,10 +1,12 @@
 // C ABI of the temporal motif library: contexts, graph ingest, motif
 // compilation and the count / enumerate / batch entry points.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 
 #include "tm_internal.h"
 
@@ -210,6 +212,40 @@ int grid_for(tm_ctx *ctx, const tmo::Module *mod) {
     return std::max(1, per_cu * std::max(ctx->num_cus, 1));
 }
 
+// Launch sampler: while the kernel runs, copy its control words (root-chunk
+// cursor, busy and waiting wavefronts, donated items waiting) every `period`
+// microseconds on a side stream into pinned host memory, and keep the samples.
+// The kernel is untouched; the samples show when the root queue drained and
+// how many wavefronts were still busy after that (the tail the paper's
+// relaunch-based redistribution targets, Sec. 5.2.2). Blocks until the kernel
+// ends.
+tm_status sample_launch(tm_ctx *ctx, tm_ctx::Workspace *w, int64_t chunks, hipStream_t stream) {
+    HIP_TRY(hipEventRecord(w->tr_done, stream), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(w->tr_stream, w->tr_go, 0), "hipStreamWaitEvent");
+    std::vector<int64_t> rows;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int64_t k = 0; k < tmo::kTraceMaxSamples; k++) {
+        const hipError_t q = hipEventQuery(w->tr_done);
+        if (q != hipSuccess && q != hipErrorNotReady) return hip_fail(q, "hipEventQuery");
+        const bool done = q == hipSuccess;
+        HIP_TRY(hipMemcpyAsync(w->h_tr, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                               w->tr_stream), "sample copy");
+        HIP_TRY(hipStreamSynchronize(w->tr_stream), "sample copy");
+        const int64_t t = std::chrono::duration_cast<std::chrono::nanoseconds>(
+                              std::chrono::steady_clock::now() - t0).count();
+        const uint64_t *c = w->h_tr;
+        const int64_t row[tmo::kTraceCols] = {t, (int64_t)c[tmo::CTL_CURSOR], chunks, (int64_t)c[tmo::CTL_BUSY],
+                                              (int64_t)c[tmo::CTL_HUNGRY], (int64_t)c[tmo::CTL_AVAIL], done ? 1 : 0};
+        rows.insert(rows.end(), row, row + tmo::kTraceCols);
+        if (done) break;
+        std::this_thread::sleep_for(std::chrono::microseconds(ctx->trace_us));
+    }
+    (void)hipGetLastError();  // a not-ready query is no error
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
+    ctx->trace.swap(rows);
+    return TM_OK;
+}
+
 tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int mode, GArgs *a,
                  hipStream_t stream, bool timed) {
     hipFunction_t fn = mod->fn[mode];
@@ -235,10 +271,19 @@ tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int 
         a->epoch = 0;
     }
     void *params[] = {a};
+    const bool sampled = ctx->trace_us > 0;
+    if (sampled) {
+        if (!w->tr_stream) HIP_TRY(hipStreamCreateWithFlags(&w->tr_stream, hipStreamNonBlocking), "sampler stream");
+        if (!w->tr_go) HIP_TRY(hipEventCreateWithFlags(&w->tr_go, hipEventDisableTiming), "sampler event");
+        if (!w->tr_done) HIP_TRY(hipEventCreateWithFlags(&w->tr_done, hipEventDisableTiming), "sampler event");
+        if (!w->h_tr) HIP_TRY(hipHostMalloc((void **)&w->h_tr, tmo::CTL_WORDS * sizeof(uint64_t)), "sampler buffer");
+        HIP_TRY(hipEventRecord(w->tr_go, stream), "hipEventRecord");  // after the control words are reset
+    }
     if (timed) HIP_TRY(hipEventRecord(w->ev0, stream), "hipEventRecord");
     HIP_TRY(hipModuleLaunchKernel(fn, grid_for(ctx, mod), 1, 1, ctx->block, 1, 1, 0, stream, params, nullptr),
             "hipModuleLaunchKernel");
     if (timed) HIP_TRY(hipEventRecord(w->ev1, stream), "hipEventRecord");
+    if (sampled) return sample_launch(ctx, w, a->total_chunks, stream);
     return TM_OK;
 }
 
@@ -533,6 +578,10 @@ void tm_destroy(tm_ctx *ctx) {
         if (w->h_counts) hipHostFree(w->h_counts);
         if (w->ev0) hipEventDestroy(w->ev0);
         if (w->ev1) hipEventDestroy(w->ev1);
+        if (w->tr_go) hipEventDestroy(w->tr_go);
+        if (w->tr_done) hipEventDestroy(w->tr_done);
+        if (w->tr_stream) hipStreamDestroy(w->tr_stream);
+        if (w->h_tr) hipHostFree(w->h_tr);
     }
     for (auto &kv : ctx->compiler.cache)
         if (kv.second->mod) hipModuleUnload(kv.second->mod);
@@ -583,6 +632,10 @@ tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t v) {
         if (v != 0 && (v < 32 || v > (1 << 24))) return fail(TM_E_INVALID, "leaf minimum must be 0 or in [32, 2^24]");
         ctx->leaf_min = v;
         return TM_OK;
+    case TM_PARAM_TRACE_US:
+        if (v != 0 && (v < 10 || v > 100000)) return fail(TM_E_INVALID, "sampling period must be 0 or 10..100000 us");
+        ctx->trace_us = v;
+        return TM_OK;
     default:
         return fail(TM_E_INVALID, "unknown parameter");
     }
@@ -602,8 +655,18 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *v) {
     case TM_PARAM_WORK_BUDGET: *v = ctx->work_budget; return TM_OK;
     case TM_PARAM_MIN_WAVES: *v = ctx->min_waves; return TM_OK;
     case TM_PARAM_LEAF_MIN: *v = ctx->leaf_min; return TM_OK;
+    case TM_PARAM_TRACE_US: *v = ctx->trace_us; return TM_OK;
     default: return fail(TM_E_INVALID, "unknown parameter");
     }
+}
+
+tm_status tm_last_trace(tm_ctx *ctx, int64_t *out, int64_t cap, int64_t *n_out) {
+    if (!ctx || !n_out || (cap > 0 && !out)) return fail(TM_E_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
+    const int64_t n = (int64_t)ctx->trace.size() / tmo::kTraceCols;
+    *n_out = n;
+    if (cap > 0) std::memcpy(out, ctx->trace.data(), (size_t)std::min(n, cap) * tmo::kTraceCols * sizeof(int64_t));
+    return TM_OK;
 }
 
 tm_status tm_last_launch(tm_ctx *ctx, int64_t *root_chunk, int32_t *split, int64_t *split_min, int64_t *leaf_min,

@@ -163,7 +163,7 @@ hipError_t dev_sort_by_time(int64_t m, int64_t *d_t, int64_t *d_perm, hipStream_
     hipError_t e = hipMalloc(&t_out, m * sizeof(int64_t));
     if (e != hipSuccess) return e;
     e = hipMalloc(&idx_in, m * sizeof(int64_t));
-    if (e != hipSuccess) { hipFree(t_out); return e; }
+    if (e != hipSuccess) { (void)hipFree(t_out); return e; }
     k_iota_i64<<<blocks_for(m), kThreads, 0, s>>>(idx_in, m);
     e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, d_t, t_out, idx_in, d_perm, (int)m, 0, 64, s);
     if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes);
@@ -171,9 +171,9 @@ hipError_t dev_sort_by_time(int64_t m, int64_t *d_t, int64_t *d_perm, hipStream_
         e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, d_t, t_out, idx_in, d_perm, (int)m, 0, 64, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_t, t_out, m * sizeof(int64_t), hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(tmp);
-    hipFree(t_out);
-    hipFree(idx_in);
+    (void)hipFree(tmp);
+    (void)hipFree(t_out);
+    (void)hipFree(idx_in);
     return e;
 }
 
@@ -232,12 +232,12 @@ hipError_t dev_build_pairs(int64_t n, int64_t m, const int32_t *d_key, const int
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
 done:
-    hipStreamSynchronize(s);
-    hipFree(tmp);
-    hipFree(ids_out);
-    hipFree(ids_in);
-    hipFree(k_out);
-    hipFree(k_in);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    (void)hipFree(ids_out);
+    (void)hipFree(ids_in);
+    (void)hipFree(k_out);
+    (void)hipFree(k_in);
     return e;
 }
 
@@ -294,12 +294,12 @@ hipError_t dev_build_csr(int64_t n, int64_t m, const int32_t *d_key, const int32
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
 done:
-    hipStreamSynchronize(s);
-    hipFree(tmp);
-    hipFree(ids_out);
-    hipFree(ids_in);
-    hipFree(keys_out);
-    hipFree(deg);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    (void)hipFree(ids_out);
+    (void)hipFree(ids_in);
+    (void)hipFree(keys_out);
+    (void)hipFree(deg);
     return e;
 }
 

@@ -87,6 +87,8 @@ enum { CTL_CURSOR = 0, CTL_OVERFLOW = 1, CTL_STATS = 2, CTL_ERROR = 7, CTL_BUSY 
        CTL_LEAF = 10, CTL_AVAIL = 13, CTL_WORDS = 16 };
 constexpr uint32_t kItemWords = 32;
 constexpr uint64_t kItemsTotal = uint64_t(1) << 20;  // donated work items per launch (128 MiB)
+constexpr int kTraceCols = 7;            // t_ns, cursor, chunks, busy, waiting, items, done
+constexpr int64_t kTraceMaxSamples = 1 << 20;
 enum Mode { MODE_COUNT = 0, MODE_STATS = 1, MODE_ENUM_COUNT = 2, MODE_ENUM_WRITE = 3, MODE_COUNT_ = 4 };
 
 // Where a level takes its candidates from (Algorithm 1, GetCandidateEdgeList).
@@ -230,6 +232,10 @@ struct tm_ctx {
         uint32_t *items = nullptr;   // kItemsTotal * kItemWords, zeroed once
         uint32_t epoch = 0;
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        // launch sampler (TM_PARAM_TRACE_US): side stream, events, pinned mirror
+        hipStream_t tr_stream = nullptr;
+        hipEvent_t tr_go = nullptr, tr_done = nullptr;
+        uint64_t *h_tr = nullptr;
         bool busy = false;
     };
     std::vector<std::unique_ptr<Workspace>> ws;
@@ -238,6 +244,8 @@ struct tm_ctx {
     int last_launches = 0;
     tmo::LaunchCfg last_cfg;  // setting of the last mining launch
     int last_tuned = 0;       // 1: it came from the tune table
+    int64_t trace_us = 0;     // launch sampling period (0 = off)
+    std::vector<int64_t> trace;  // samples of the last sampled launch, kTraceCols each
 };
 
 struct tm_graph {
