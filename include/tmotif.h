@@ -439,6 +439,7 @@ typedef struct {
     int64_t *rows;            /* device int64[n_rows][n_edges], owned by the server until tm_release */
     uint64_t n_rows;
     int64_t t_arrival_ns, t_admit_ns, t_launch_ns, t_done_ns;
+    char error[128];          /* for a status other than TM_OK: what failed (NUL-terminated) */
 } tm_result;
 
 /* Start serving graph g of ctx. The graph and the context must outlive the

@@ -60,7 +60,7 @@ class Result(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
                 ("n_edges", ctypes.c_int32), ("count", ctypes.c_uint64), ("rows", ctypes.c_void_p),
                 ("n_rows", ctypes.c_uint64), ("t_arrival_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
-                ("t_launch_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
+                ("t_launch_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64), ("error", ctypes.c_char * 128)]
 
 
 class GraphInfo(ctypes.Structure):

@@ -393,7 +393,8 @@ class Server:
             out.append({"ticket": r.ticket, "tag": r.tag, "status": r.status, "count": r.count,
                         "rows": r.rows, "n_rows": r.n_rows, "n_edges": r.n_edges,
                         "t_arrival_ns": r.t_arrival_ns, "t_admit_ns": r.t_admit_ns,
-                        "t_launch_ns": r.t_launch_ns, "t_done_ns": r.t_done_ns})
+                        "t_launch_ns": r.t_launch_ns, "t_done_ns": r.t_done_ns,
+                        "error": r.error.decode(errors="replace")})
         return out
 
     def rows(self, result):

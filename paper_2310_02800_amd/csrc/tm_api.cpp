@@ -257,7 +257,11 @@ tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int 
         if (!w->items) {
             const size_t bytes = tmo::kItemsTotal * tmo::kItemWords * sizeof(uint32_t);
             HIP_TRY(hipMalloc(&w->items, bytes), "work item buffer");
-            HIP_TRY(hipMemset(w->items, 0, bytes), "work item buffer");
+            // zeroed on the launch stream: a memset on the null stream is not
+            // ordered before kernels on a non-blocking stream, and a late one
+            // would erase items the kernel has already published
+            HIP_TRY(tmo::dev_fill_u64((uint64_t *)w->items, 0, (int64_t)(bytes / sizeof(uint64_t)), stream),
+                    "work item buffer");
         }
         HIP_TRY(tmo::dev_fill_u64(w->qctl, 0, 2 * (int64_t)a->nq, stream), "reset queues");
         a->items = w->items;

@@ -25,6 +25,7 @@
 #include <hip/hiprtc.h>
 #include <sys/stat.h>
 #include <unistd.h>
+#include <utime.h>
 
 #include <algorithm>
 #include <chrono>
@@ -480,6 +481,7 @@ struct Emitter {
     // start the search collapses to the tie skip (not in the work-counter mode,
     // which follows the byte model's one search per window).
     void open(int i, const char *tp, const char *ind) {
+        if (leaf_cache() && i == p.l - 2) o << ind << "lq = false;\n";
         if (G) {
             const std::string in2 = std::string(ind) + "  ";
             o << ind << "if (MODE != 1 && gj" << i << " != 0) {\n";
@@ -654,6 +656,7 @@ struct Emitter {
             o << "            const int t_e" << j << " = " << e_cond(j) << " ? shf(e" << j << ", srcl) : 0;\n";
         o << "            if (thief) {\n";
         o << "              lvl = t_dj; base = t_dj; ph = 0; root = t_root; mych = t_mych; tmaxk = t_tmax;\n";
+        if (leaf_cache()) o << "              lq = false;\n";
         o << "              exact = 1u << t_dj;\n";
         for (int v = 0; v < K; v++) o << "              m" << v << " = t_m" << v << ";\n";
         for (int j = 1; j + 1 < L; j++) o << "              if (" << e_cond(j) << ") e" << j << " = t_e" << j << ";\n";
@@ -725,6 +728,7 @@ struct Emitter {
         o << ind << "if (item_ready(g, it)) {\n";
         o << ind << "  const int j = (int)ld_ag(it + 1);\n";
         o << ind << "  lvl = j; base = j; ph = 0; exact = 1u << j;\n";
+        if (leaf_cache()) o << ind << "  lq = false;\n";
         o << ind << "  root = (int)ld_ag(it + 7); mych = ld_ag64(it + 8); tmaxk = (tkey)ld_ag64(it + 10);\n";
         for (int v = 0; v < K; v++) o << ind << "  m" << v << " = (int)ld_ag(it + " << 12 + v << ");\n";
         for (int j = 1; j + 1 < L; j++)
@@ -758,6 +762,26 @@ struct Emitter {
                      !(p.kind[i] != LIST_BOTH && labelled(new_node(i))));
     }
 
+    // Closed-form last level whose list (the out- or in-list of one node) and
+    // some of whose subtracted nodes were bound before the level above it:
+    // while that level iterates, they stay fixed, so the start of each fixed
+    // node's run in the pair-sorted list is searched once per window of the
+    // level above (registers ls<v>, valid while lq). When the level above has
+    // no gap tighter than delta, every last-level window ends at the same time
+    // (t_root + delta), so the window's end position (lE) and each fixed run's
+    // end (le<v>) are kept too; a window then costs one search per new node
+    // and one per fixed node instead of three each plus the window's own.
+    bool leaf_cache() const {
+        if (G || p.l < 3 || !leaf_countable() || p.kind[p.l - 1] == LIST_BOTH) return false;
+        return fixed_at_leaf(new_node_list(p.l - 1));
+    }
+    int new_node_list(int i) const { return p.kind[i] == LIST_OUT ? p.a[i] : p.b[i]; }
+    bool fixed_at_leaf(int v) const {
+        for (int x : p.mapped[p.l - 2])
+            if (x == v) return true;
+        return false;
+    }
+
     // Closed-form count of the last level's window (registers cur, end, hi of
     // that level and sx = the previous edge's time) into lc_; w_ = the
     // window's length when computed; pr_ = entries read.
@@ -785,6 +809,36 @@ struct Emitter {
             o << in << "lc_ = pair_cnt(g.pr_nbr, g.pr_t, g.off_out[m" << p.a[i] << "], g.off_out[m" << p.a[i]
               << " + 1], m" << p.b[i] << ", sx, hi" << s << ", pr_);\n";
             if (need_w) o << in << "w_ = win_len(g.adj_t, cur" << s << ", end" << s << ", hi" << s << ", pr_);\n";
+        } else if (leaf_cache()) {
+            const bool out = p.kind[i] == LIST_OUT;
+            const int u = out ? p.a[i] : p.b[i];
+            const char *off = out ? "g.off_out" : "g.off_in";
+            const std::string h = "hi" + s;
+            o << in << "const u32 plo = " << off << "[m" << u << "], phi = " << off << "[m" << u << " + 1];\n";
+            o << in << "if (!lq) {\n";
+            o << in << "  lq = true;\n";
+            o << in << "  if (q_gf) lE = plo + win_len(g.adj_t, plo, phi, " << h << ", pr_);\n";
+            for (int v : p.mapped[i]) {
+                if (!fixed_at_leaf(v)) continue;
+                const std::string V = I(v);
+                o << in << "  ls" << V << " = nbr_lb(g.pr_nbr, plo, phi, m" << V << ", pr_); ++pr_;\n";
+                o << in << "  if (ls" << V << " >= phi || g.pr_nbr[ls" << V << "] != m" << V << ") ls" << V << " = ~0u;\n";
+                o << in << "  else if (q_gf) le" << V << " = run_ub(g.pr_nbr, g.pr_t, ls" << V << ", phi, m" << V << ", "
+                  << h << ", pr_);\n";
+            }
+            o << in << "}\n";
+            o << in << "w_ = q_gf ? (lE > cur" << s << " ? lE - cur" << s << " : 0u) : win_len(g.adj_t, cur" << s
+              << ", end" << s << ", " << h << ", pr_);\n";
+            o << in << "lc_ = w_;\n";
+            for (int v : p.mapped[i]) {
+                const std::string V = I(v);
+                if (fixed_at_leaf(v))
+                    o << in << "if (ls" << V << " != ~0u) lc_ -= (u64)((q_gf ? le" << V << " : run_ub(g.pr_nbr, g.pr_t, ls"
+                      << V << ", phi, m" << V << ", " << h << ", pr_)) - run_ub(g.pr_nbr, g.pr_t, ls" << V << ", phi, m"
+                      << V << ", sx, pr_));\n";
+                else
+                    o << in << "lc_ -= pair_cnt(g.pr_nbr, g.pr_t, plo, phi, m" << V << ", sx, " << h << ", pr_);\n";
+            }
         } else {
             const bool out = p.kind[i] == LIST_OUT;
             const int u = out ? p.a[i] : p.b[i];
@@ -984,6 +1038,12 @@ struct Emitter {
         o << "  tkey tmaxk = 0, sx = 0; u32 sb = 0u, sn = 0u;\n";
         o << "  u64 cnt = 0, rcnt = 0, st_win = 0, st_probe = 0, st_visit = 0, st_pv = 0, st_root = 0;\n";
         o << "  u64 st_lc = 0, st_lcw = 0, st_lcp = 0;  // windows counted without a scan: number, visits, reads\n";
+        if (leaf_cache()) {
+            o << "  bool lq = false; const bool q_gf = gap" << L - 2 << " >= q_delta; u32 lE = 0u;"
+              << "  // fixed-node searches of the closed-form last level\n";
+            for (int v : p.mapped[L - 1])
+                if (fixed_at_leaf(v)) o << "  u32 ls" << v << " = 0u, le" << v << " = 0u;\n";
+        }
         o << "  u32 iter = 0u, steps = 0u; i64 ghungry = 0;\n";
         o << "  i64 pnext = 0, pend = 0, pchunk = chunk, pending = -1;\n";
         o << "  bool drained = chunk < 0;\n";
@@ -1424,7 +1484,9 @@ bool compile_to_code(const std::string &src, std::vector<char> *code, std::strin
 // source text it was compiled from and the code object; it is used only when
 // the stored source equals the requested one byte for byte, so a stale or
 // colliding entry is recompiled, never loaded. Directory: $TMOTIF_KERNEL_CACHE,
-// else `_kcache` beside the library; an unwritable directory disables it.
+// else `_kcache` beside the library; an unwritable directory disables it. A
+// hit refreshes the file's modification time, so entries not used since a
+// given time can be deleted safely.
 static std::string cache_dir() {
     static std::string dir = [] {
         const char *env = std::getenv("TMOTIF_KERNEL_CACHE");
@@ -1473,6 +1535,7 @@ static bool cache_load(const std::string &src, std::vector<char> *code) {
         if (ok) code->swap(buf);
     }
     std::fclose(f);
+    if (ok) utime(cache_path(src).c_str(), nullptr);  // mark as recently used
     return ok;
 }
 

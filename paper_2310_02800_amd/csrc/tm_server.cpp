@@ -133,6 +133,7 @@ void publish(tm_server *s, const Pending &p, tm_status st, uint64_t count, int64
     r.t_admit_ns = p.t_admit;
     r.t_launch_ns = t_launch;
     r.t_done_ns = now_ns();
+    if (st != TM_OK) std::snprintf(r.error, sizeof(r.error), "%s", tm_last_error());
     std::lock_guard<std::mutex> lk(s->mu);
     s->results.push_back(r);
     s->served++;

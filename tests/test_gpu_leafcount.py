@@ -8,7 +8,10 @@ multigraph (12 nodes, 30,000 edges, self-loops, repeated pairs and tied
 times) where windows hold dozens of candidates: out- and in-stars (one new
 endpoint, with self-loops to subtract), triangles and repeated pairs (both
 endpoints bound), gaps, and predicates on and off the last level (a predicate
-on the last level rules the closed form out). Exact comparisons throughout;
+on the last level rules the closed form out), and last levels whose list and
+subtracted nodes were bound before the level above (their searches are kept
+across that level's iterations; with a gap before the last level only the
+run starts are). Exact comparisons throughout;
 the enumeration's counting pass uses the closed form and its writing pass
 scans, and the library checks that they agree.
 """
@@ -71,6 +74,9 @@ CASES = [
     Motif([(0, 1), (0, 2), (0, 3)], 600, gap=[100, 250]),      # gaps bound the window
     Motif([(0, 1), (0, 2), (2, 3)], 400, pred_edge=1, pred_op=synth.PRED_GE, pred_theta=0.8),  # predicate above
     Motif([(0, 1), (0, 2), (0, 3)], 300, pred_edge=2, pred_op=synth.PRED_LT, pred_theta=1.5),  # predicate on last
+    Motif([(0, 1), (0, 2), (0, 3), (0, 4)], 150),               # 4-edge star: three fixed nodes, one new
+    Motif([(1, 0), (2, 1), (3, 0)], 400),                       # last level on another list than its parent
+    Motif([(1, 0), (2, 1), (3, 0)], 400, gap=[300, 120]),       # the same with a gap before the last level
 ]
 
 

@@ -226,8 +226,9 @@ def test_server_cancels_over_budget_queries(ctx, tiny_g, tiny_og):
         srv.stop()
     assert len(done) == 4
     assert done[0][0]["status"] == N.TM_OK and done[0][0]["count"] == oracle.count(tiny_og, light[0])
-    assert done[1][0]["status"] == N.TM_E_CANCELLED
-    assert done[2][0]["status"] == N.TM_E_CANCELLED and done[2][1] is None
+    assert done[1][0]["status"] == N.TM_E_CANCELLED, done[1][0]["error"]
+    assert done[2][0]["status"] == N.TM_E_CANCELLED and done[2][1] is None, done[2][0]["error"]
+    assert done[1][0]["error"] and done[0][0]["error"] == ""
     assert done[3][0]["status"] == N.TM_OK
     assert same_rows(done[3][1], oracle.enumerate(tiny_og, light[1]))
 
