@@ -46,7 +46,8 @@ struct DeviceGuard {
 
 void free_graph_buffers(tm_graph *g) {
     void *ptrs[] = {g->d_src, g->d_dst, g->d_tk, g->d_w, g->d_adj_t, g->d_adj_nbr, g->d_adj_eid, g->d_adj_w,
-                    g->d_off_out, g->d_off_in, g->d_pos_out, g->d_pos_in, g->d_pr_nbr, g->d_pr_t, g->d_nlab};
+                    g->d_off_out, g->d_off_in, g->d_pos_out, g->d_pos_in, g->d_pr_nbr, g->d_pr_t, g->d_pr_pos,
+                    g->d_nlab};
     for (void *p : ptrs)
         if (p) hipFree(p);
 }
@@ -194,6 +195,7 @@ GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w, const tmo::LaunchCfg &c
     a.pos_in = g->d_pos_in;
     a.pr_nbr = g->d_pr_nbr;
     a.pr_t = g->d_pr_t;
+    a.pr_pos = g->d_pr_pos;
     a.nlab = g->d_nlab;
     a.qa = (const QArgs *)w->qa;
     a.ctl = w->ctl;
@@ -878,11 +880,13 @@ tm_status tm_load_graph(tm_ctx *ctx, int64_t n, int64_t m, const int32_t *src, c
     e = dmalloc(&g->d_pr_nbr, 2 * m, &acc);
     if (e == hipSuccess) e = hipMalloc(&g->d_pr_t, std::max<int64_t>(2 * m, 1) * g->key_bytes);
     if (e == hipSuccess) acc += std::max<int64_t>(2 * m, 1) * g->key_bytes;
+    if (e == hipSuccess) e = dmalloc(&g->d_pr_pos, 2 * m, &acc);
     if (e != hipSuccess) return cleanup(hip_fail(e, "pair list allocation"));
-    e = tmo::dev_build_pairs(n, m, g->d_src, g->d_dst, g->d_tk, g->key_bytes, g->d_pr_nbr, g->d_pr_t, s);
+    e = tmo::dev_build_pairs(n, m, g->d_src, g->d_dst, g->d_tk, g->key_bytes, g->d_pr_nbr, g->d_pr_t, g->d_pos_out,
+                             0u, g->d_pr_pos, s);
     if (e == hipSuccess)
         e = tmo::dev_build_pairs(n, m, g->d_dst, g->d_src, g->d_tk, g->key_bytes, g->d_pr_nbr + m,
-                                 (char *)g->d_pr_t + m * g->key_bytes, s);
+                                 (char *)g->d_pr_t + m * g->key_bytes, g->d_pos_in, (uint32_t)m, g->d_pr_pos, s);
     if (e != hipSuccess) return cleanup(hip_fail(e, "pair list build"));
     g->device_bytes = acc;
     hipStreamDestroy(s);

@@ -206,9 +206,10 @@ struct GArgs {
   const u32* pos_out; const u32* pos_in;
   const int* pr_nbr; const tkey* pr_t;
   const int* nlab;
+  const u32* pr_pos;
 };
 static_assert(sizeof(QArgs) == 224, "QArgs layout");
-static_assert(sizeof(GArgs) == 232, "GArgs layout");
+static_assert(sizeof(GArgs) == 240, "GArgs layout");
 // generic matchers: motif node slot by run-time index, and the bound-node check
 #define mget(ix) ((ix) == 0 ? m0 : (ix) == 1 ? m1 : (ix) == 2 ? m2 : (ix) == 3 ? m3 : \
                   (ix) == 4 ? m4 : (ix) == 5 ? m5 : (ix) == 6 ? m6 : m7)
@@ -776,6 +777,15 @@ struct Emitter {
         return fixed_at_leaf(new_node_list(p.l - 1));
     }
     int new_node_list(int i) const { return p.kind[i] == LIST_OUT ? p.a[i] : p.b[i]; }
+    // The node the level above binds when it scans the last level's own list
+    // (-1 otherwise): its candidate is then an entry of that node's run.
+    int parent_node() const {
+        const int i = p.l - 1, j = p.l - 2;
+        if (j < 1 || p.kind[j] != p.kind[i]) return -1;
+        if (p.kind[i] == LIST_OUT && p.a[j] == p.a[i]) return p.b[j];
+        if (p.kind[i] == LIST_IN && p.b[j] == p.b[i]) return p.a[j];
+        return -1;
+    }
     bool fixed_at_leaf(int v) const {
         for (int x : p.mapped[p.l - 2])
             if (x == v) return true;
@@ -836,7 +846,18 @@ struct Emitter {
                     o << in << "if (ls" << V << " != ~0u) lc_ -= (u64)((q_gf ? le" << V << " : run_ub(g.pr_nbr, g.pr_t, ls"
                       << V << ", phi, m" << V << ", " << h << ", pr_)) - run_ub(g.pr_nbr, g.pr_t, ls" << V << ", phi, m"
                       << V << ", sx, pr_));\n";
-                else
+                else if (v == parent_node()) {
+                    // the level above's own candidate is an entry of this node's
+                    // run: start there (when this lane scanned that level itself)
+                    const std::string P = I(p.l - 2);
+                    o << in << "if (base <= " << P << ") {\n";
+                    o << in << "  const u32 s_ = g.pr_pos[cur" << P << " - 1u]; ++pr_;\n";
+                    o << in << "  lc_ -= (u64)(run_ub(g.pr_nbr, g.pr_t, s_, phi, m" << V << ", " << h
+                      << ", pr_) - run_ub(g.pr_nbr, g.pr_t, s_, phi, m" << V << ", sx, pr_));\n";
+                    o << in << "} else {\n";
+                    o << in << "  lc_ -= pair_cnt(g.pr_nbr, g.pr_t, plo, phi, m" << V << ", sx, " << h << ", pr_);\n";
+                    o << in << "}\n";
+                } else
                     o << in << "lc_ -= pair_cnt(g.pr_nbr, g.pr_t, plo, phi, m" << V << ", sx, " << h << ", pr_);\n";
             }
         } else {

@@ -110,6 +110,13 @@ __global__ void k_pair_keys(int64_t m, const int32_t *key, const int32_t *other,
         k64[i] = ((uint64_t)(uint32_t)key[i] << 32) | (uint64_t)(uint32_t)other[i];
 }
 
+// pr_pos[pos[e]] = add + i: where the adjacency entry of edge e sits in the
+// pair-sorted order of the same lists
+__global__ void k_pair_pos(int64_t m, const int32_t *ids, const uint32_t *pos, uint32_t add, uint32_t *pr_pos) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        pr_pos[pos[ids[i]]] = add + (uint32_t)i;
+}
+
 template <typename K>
 __global__ void k_gather_pairs(int64_t m, const int32_t *ids, const int32_t *other, const K *tk, int32_t *pr_nbr,
                                K *pr_t) {
@@ -199,7 +206,8 @@ hipError_t dev_make_keys(int64_t m, const int64_t *d_t, int64_t t_min, int key_b
 // two given nodes inside a time window with binary searches. Same grouping by
 // node (and so the same offsets) as the time-sorted lists below.
 hipError_t dev_build_pairs(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
-                           int key_bytes, int32_t *d_pr_nbr, void *d_pr_t, hipStream_t s) {
+                           int key_bytes, int32_t *d_pr_nbr, void *d_pr_t, const uint32_t *d_pos, uint32_t add,
+                           uint32_t *d_pr_pos, hipStream_t s) {
     clear_stale_error();
     if (m <= 0) return hipSuccess;
     hipError_t e = hipSuccess;
@@ -229,6 +237,7 @@ hipError_t dev_build_pairs(int64_t n, int64_t m, const int32_t *d_key, const int
     else
         k_gather_pairs<int64_t><<<blocks_for(m), kThreads, 0, s>>>(m, ids_out, d_other, (const int64_t *)d_tk,
                                                                     d_pr_nbr, (int64_t *)d_pr_t);
+    k_pair_pos<<<blocks_for(m), kThreads, 0, s>>>(m, ids_out, d_pos, add, d_pr_pos);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
 done:

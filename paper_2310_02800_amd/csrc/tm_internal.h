@@ -78,8 +78,9 @@ struct GArgs {
     const int32_t *pr_nbr;    // adjacency sorted by (neighbour, time), same offsets
     const void *pr_t;
     const int32_t *nlab;      // vertex labels (n entries) or null
+    const uint32_t *pr_pos;   // per adjacency entry: its position in the pair-sorted lists
 };
-static_assert(sizeof(GArgs) == 232, "GArgs layout");
+static_assert(sizeof(GArgs) == 240, "GArgs layout");
 
 // ctl words: [10..12] work counters of the windows counted without a scan,
 // [13] donated items waiting in all queues
@@ -158,7 +159,8 @@ bool cached_code(const std::string &src, std::vector<char> *code, std::string *e
 
 // device helpers (tm_device.hip)
 hipError_t dev_build_pairs(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
-                           int key_bytes, int32_t *d_pr_nbr, void *d_pr_t, hipStream_t s);
+                           int key_bytes, int32_t *d_pr_nbr, void *d_pr_t, const uint32_t *d_pos, uint32_t add,
+                           uint32_t *d_pr_pos, hipStream_t s);
 hipError_t dev_build_csr(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
                          int key_bytes, const float *d_w, uint32_t add, uint32_t *d_off, void *d_adj_t,
                          int32_t *d_adj_nbr, int32_t *d_adj_eid, float *d_adj_w, uint32_t *d_pos, hipStream_t s);
@@ -266,6 +268,7 @@ struct tm_graph {
     uint32_t *d_pos_out = nullptr, *d_pos_in = nullptr;
     int32_t *d_pr_nbr = nullptr;  // adjacency sorted by (neighbour, time): out [0,m), in [m,2m)
     void *d_pr_t = nullptr;
+    uint32_t *d_pr_pos = nullptr;  // per adjacency entry: its position in the pair-sorted lists
     int32_t *d_nlab = nullptr;    // vertex labels (n entries), once attached
     bool has_labels = false;
     std::vector<int64_t> h_t;     // sorted absolute times (root-range lookup)

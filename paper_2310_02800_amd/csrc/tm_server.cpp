@@ -118,8 +118,10 @@ void pool_free_locked(tm_server *s, uint64_t ticket) {
     s->cv_pool.notify_all();
 }
 
+// `why` describes a failure the calling thread's last error does not (a query
+// cancelled inside a batch that itself succeeded).
 void publish(tm_server *s, const Pending &p, tm_status st, uint64_t count, int64_t *rows, uint64_t n_rows,
-             int64_t t_launch) {
+             int64_t t_launch, const char *why = nullptr) {
     tm_result r;
     std::memset(&r, 0, sizeof(r));
     r.ticket = p.ticket;
@@ -133,7 +135,7 @@ void publish(tm_server *s, const Pending &p, tm_status st, uint64_t count, int64
     r.t_admit_ns = p.t_admit;
     r.t_launch_ns = t_launch;
     r.t_done_ns = now_ns();
-    if (st != TM_OK) std::snprintf(r.error, sizeof(r.error), "%s", tm_last_error());
+    if (st != TM_OK) std::snprintf(r.error, sizeof(r.error), "%s", why ? why : tm_last_error());
     std::lock_guard<std::mutex> lk(s->mu);
     s->results.push_back(r);
     s->served++;
@@ -197,7 +199,8 @@ void slot_main(tm_server *s) {
                 pool_free_locked(s, p->ticket);
                 rows = nullptr;
             }
-            publish(s, *p, st, n, rows, rows ? n : 0, t_launch);
+            publish(s, *p, st, n, rows, rows ? n : 0, t_launch,
+                    st == TM_E_CAPACITY ? "rows exceed the enumeration pool" : nullptr);
             delete p;
         } else {
             motifs.clear();
@@ -218,7 +221,8 @@ void slot_main(tm_server *s) {
                                                  budgets.data(), tier, stream, w, counts.data(), cancelled.data());
             for (size_t i = 0; i < batch.size(); i++) {
                 const tm_status qs = st != TM_OK ? st : cancelled[i] ? TM_E_CANCELLED : TM_OK;
-                publish(s, *batch[i], qs, qs == TM_OK ? counts[i] : 0, nullptr, 0, t_launch);
+                publish(s, *batch[i], qs, qs == TM_OK ? counts[i] : 0, nullptr, 0, t_launch,
+                        st == TM_OK && cancelled[i] ? "work budget exceeded" : nullptr);
                 delete batch[i];
             }
         }
