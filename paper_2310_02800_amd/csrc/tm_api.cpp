@@ -922,8 +922,12 @@ tm_status tm_graph_set_node_labels(tm_graph *g, const int32_t *labels) {
         if (labels[v] < 0) return fail(TM_E_INVALID, "vertex labels must be >= 0");
     DeviceGuard dg(g->device);
     if (!g->d_nlab) HIP_TRY(dmalloc(&g->d_nlab, g->n, &g->device_bytes), "hipMalloc labels");
-    if (g->n > 0)
+    if (g->n > 0) {
         HIP_TRY(hipMemcpy(g->d_nlab, labels, (size_t)g->n * sizeof(int32_t), hipMemcpyHostToDevice), "upload labels");
+        // a copy from pageable memory may return before it lands; kernels on
+        // non-blocking streams are not ordered after it, so wait here
+        HIP_TRY(hipDeviceSynchronize(), "upload labels");
+    }
     g->has_labels = true;
     return TM_OK;
 }
