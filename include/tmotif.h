@@ -161,10 +161,10 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
  * TM_PARAM_AUTOTUNE = 1 the first tm_count or tm_count_batch of a key runs
  * its launch under each candidate setting (roots per chunk in {16, 64, 256,
  * 1024}, each with splitting off and with splitting of windows of 32 or more;
- * at 256 roots also splitting from 2, 8 and 128; then, at the best of those,
- * TM_PARAM_LEAF_MIN in {0, 128, 2048}), checks that every trial
- * returns the same
- * counts (else TM_E_DEVICE), returns them, and keeps the fastest setting for
+ * at 256 roots also splitting from 2, 8 and 128; then half and twice the
+ * best roots per chunk at its splitting setting; then, at the best of those,
+ * TM_PARAM_LEAF_MIN in {0, 128, 2048}), checks that every trial returns the
+ * same counts (else TM_E_DEVICE), returns them, and keeps the fastest setting for
  * the key. Later counts, batches and enumerations with the key use it. The
  * key is the graph (node and edge counts, time span), the kernel module, and
  * power-of-two buckets of the largest delta (clamped to the span), of the

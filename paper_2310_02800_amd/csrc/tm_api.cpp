@@ -500,11 +500,26 @@ tm_status run_tuned(tm_ctx *ctx, const std::string &key, int64_t roots, F &&once
                 have = true;
                 return TM_OK;
             };
-            // stage 1: roots per chunk and splitting; stage 2: the closed-form
-            // threshold at the best of those
+            // stage 1: roots per chunk and splitting; stage 2: half and twice
+            // the best roots per chunk at its splitting setting; stage 3: the
+            // closed-form threshold at the best of those
             for (const tmo::LaunchCfg &c : tune_candidates(ctx, roots)) {
                 const tm_status st = trial(c);
                 if (st != TM_OK) return st;
+            }
+            if (have) {
+                const tmo::LaunchCfg base_c = best_c;
+                const int64_t base_chunks = (roots + base_c.rch - 1) / base_c.rch;
+                for (int64_t rch : {base_c.rch / 2, base_c.rch * 2}) {
+                    if (rch < 1 || (roots + rch - 1) / rch == base_chunks) continue;
+                    bool tried = false;
+                    for (int64_t t : {16, 64, 256, 1024}) tried |= t == rch;
+                    if (tried) continue;
+                    tmo::LaunchCfg c = base_c;
+                    c.rch = rch;
+                    const tm_status st = trial(c);
+                    if (st != TM_OK) return st;
+                }
             }
             if (have) {
                 const tmo::LaunchCfg base_c = best_c;

@@ -85,7 +85,7 @@ def test_single_count_is_tuned_once_and_reused(tuned, tiny_g, tiny_og):
     say("tuning a 4-cycle count")
     assert ctx.count(tiny_g, mm) == want
     first = ctx.last_launch()
-    assert first[2] == 1 and first[0] in (16, 64, 256, 1024) and first[1] in (0, 1)
+    assert first[2] == 1 and first[0] in (8, 16, 32, 64, 128, 256, 512, 1024, 2048) and first[1] in (0, 1)
     assert ctx.count(tiny_g, mm) == want
     assert ctx.last_launch() == first
     # an enumeration of the same key runs both passes under the tuned setting
