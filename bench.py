@@ -428,6 +428,8 @@ def main():
     ap.add_argument("--no-tail", action="store_true", help="skip sampling the headline launch's load balance")
     ap.add_argument("--tail-skew", action="store_true",
                     help="also sample the load balance on the heavy-skew graph (generates 50M edges)")
+    ap.add_argument("--constraints-only", action="store_true",
+                    help="run only the constraints section and print its JSON (for kernel traces of it)")
     ap.add_argument("--no-constraints", action="store_true",
                     help="skip the 4-cycle with added constraints (gaps, anti-edge)")
     ap.add_argument("--serve-queries", type=int, default=500,
@@ -486,6 +488,10 @@ def main():
     torch.cuda.synchronize()
     load_s = time.perf_counter() - t0
     log(f"graph loaded in {load_s:.2f} s ({dg.info()['device_bytes'] / 1e9:.3f} GB in HBM)")
+    if args.constraints_only:
+        print(json.dumps({"constraints": bench_constraints(ctx, dg, args, stream), "tuned_from": tuned_from}),
+              flush=True)
+        return
 
     t0 = time.perf_counter()
     handles = [ctx.compile(m) for m in motifs]
