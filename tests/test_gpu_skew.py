@@ -96,3 +96,29 @@ def test_skew_root_slices(ctx, skew_g, gold):
     mm = ctx.compile(synth.skew_query())
     for s in gold["slices"]:
         assert ctx.count(skew_g, mm, t_lo=s["t_lo"], t_hi=s["t_hi"]) == s["count"]
+
+
+# the same graph with four uniform random vertex labels, and the motif with
+# an anti-edge and/or labels: counts against the oracle computed here
+SKEW_VARIANTS = [
+    dict(anti=[(1, 3, 1, 600)]),                                  # checked at level 2, below its attach level
+    dict(node_labels=[0, -1, 1, -1]),
+    dict(anti=[(2, 0, 3, 300)], node_labels=[-1, 2, -1, 3]),
+]
+
+
+def test_skew_anti_edges_and_labels(ctx, skew, skew_g):
+    import oracle
+    labels = synth.node_labels(5, skew.n, 4)
+    skew_g.set_node_labels(labels)
+    og = oracle.OracleGraph(skew.n, skew.src, skew.dst, skew.t, skew.w, labels)
+    base = synth.skew_query()
+    for kw in SKEW_VARIANTS:
+        mot = synth.Motif(base.edges, base.delta, gap=base.gap, **kw)
+        t0 = time.time()
+        want = oracle.count(og, mot, nthreads=16)
+        say(f"skew variant {kw}: oracle {want} in {time.time() - t0:.1f} s")
+        mm = ctx.compile(mot)
+        assert ctx.count(skew_g, mm) == want
+        rows = ctx.enumerate(skew_g, mm)
+        assert rows_sha256(rows) == rows_sha256(oracle.enumerate(og, mot))
