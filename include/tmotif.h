@@ -15,7 +15,13 @@
  *      (isomorphism semantics: a bijection between motif and matched nodes),
  *   5. optionally w(e_j) OP theta for one motif edge j (edge-attribute
  *      constraint, Sec. 5.4.1; an exact IEEE float32 comparison),
- *   6. t_lo <= t(e_0) <= t_hi when a root range is given.
+ *   6. t_lo <= t(e_0) <= t_hi when a root range is given,
+ *   7. optionally, every motif node with a required vertex label maps to a
+ *      graph node carrying it (Sec. 5.4.1; labels attached with
+ *      tm_graph_set_node_labels),
+ *   8. optionally, for each temporal anti-edge (a, b, attached to edge i,
+ *      window w), no graph edge phi(a) -> phi(b) has a time in
+ *      [t(e_i), t(e_i) + w] (Sec. 2.1).
  * Graph self-loops can never match (condition 4). Edge ids are positions in
  * the time-sorted edge list (ties keep input order).
  *
