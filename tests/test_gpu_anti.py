@@ -305,3 +305,11 @@ def test_wiki_sampled_enumeration(ctx, wiki_g, wiki_og):
             say("wiki anti range", mot.edges, lo, hi)
             assert same_rows(ctx.enumerate(wiki_g, mm, t_lo=lo, t_hi=hi),
                              oracle.enumerate(wiki_og, mot, t_lo=lo, t_hi=hi))
+
+
+def test_huge_windows_are_clamped(ctx, tiny_g, tiny_og):
+    """Windows near the int64 limit (clamped to the time span on the device,
+    saturated in the oracle) forbid the pair at any later time."""
+    for w in (2**40, 2**63 - 1):
+        mot = Motif([(0, 1), (1, 2)], 20_000, anti=[(1, 0, 0, w)])
+        assert ctx.count(tiny_g, ctx.compile(mot)) == oracle.count(tiny_og, mot, nthreads=8)

@@ -188,3 +188,16 @@ def test_rejects_invalid_anti_edges():
     for anti in ([(0, 0, 0, 5)], [(0, 3, 0, 5)], [(0, 1, 2, 5)], [(0, 1, 0, -1)], [(0, 2, 0, 1)] * 5):
         with pytest.raises(ValueError):
             oracle.count(og, Motif(me, 10, anti=anti))
+
+
+def test_huge_anti_windows_saturate():
+    """A window near the int64 limit saturates instead of wrapping: the
+    anti-edge then forbids the pair at any time from the attached edge on,
+    which brute force (whose integers do not overflow) agrees with."""
+    rng = np.random.Generator(np.random.PCG64(8))
+    for seed in range(40):
+        g = synth.random_graph(rng, 5, 14, 20)
+        for w in (2**62, 2**63 - 1):
+            mot = Motif([(0, 1), (1, 2)], 30, anti=[(2, 0, 1, w)])
+            og = og_of(g)
+            assert rows(oracle.enumerate(og, mot)) == brute.enumerate_all(g, mot), (seed, w)
