@@ -243,3 +243,20 @@ def test_wiki_full_counts(ctx):
         assert ctx.count_batch(dg, [ctx.compile(m) for m in WIKI_CASES]) == want
     finally:
         with_params(ctx, old)
+
+
+def test_large_labels_and_int64_time_keys(ctx, tiny):
+    """Label values near INT32_MAX on a graph whose time span needs 64-bit
+    relative times."""
+    big = (2**31 - 1) - tiny.labels.astype(np.int64) * 1_000_003
+    g = synth.with_labels(synth.TemporalGraph(tiny.n, tiny.src, tiny.dst, tiny.t * 10_000, tiny.w), big)
+    dg = ctx.load_synth(g)
+    assert dg.info()["key_bytes"] == 8 and dg.info()["has_labels"] == 1
+    og = oracle.OracleGraph.from_graph(g)
+    lab = [(2**31 - 1) - v * 1_000_003 for v in (0, 1, 0, 1)]
+    mot = Motif(synth.FOUR_CYCLE, 86_400 * 10_000, node_labels=lab)
+    want = oracle.count(og, mot, nthreads=8)
+    assert want > 0
+    mm = ctx.compile(mot)
+    assert ctx.count(dg, mm) == want
+    assert same_rows(ctx.enumerate(dg, mm), oracle.enumerate(og, mot))
