@@ -440,8 +440,8 @@ def main():
     ap.add_argument("--serve-pool-gib", type=float, default=8.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the method shards by root-time "
-              "ranges; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the count would shard over GPUs by "
+              "root-time ranges, one tm_root_range each). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
