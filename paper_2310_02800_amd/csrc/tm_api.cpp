@@ -337,12 +337,13 @@ void batch_plans(const std::vector<const tmo::Plan *> &qp, int tier, std::vector
     }
 }
 
-tm_status get_module(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, int tier,
+// The module holding the kernel of `mode` for this motif and graph.
+tm_status get_module(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, int tier, int mode,
                      std::shared_ptr<tmo::Module> *out) {
     std::string err;
     const tmo::Plan gp = tmo::generic_plan(m->plan.l);
     auto mod = ctx->compiler.get(use_generic(tier, m) ? gp : m->plan, g->key_bytes, ctx->block, &err,
-                                 ctx->min_waves);
+                                 ctx->min_waves, tmo::mode_group(mode));
     if (!mod) return fail(TM_E_COMPILE, err);
     *out = mod;
     return TM_OK;
@@ -999,7 +1000,8 @@ tm_status tm_compile_motif(tm_ctx *ctx, const tm_motif_desc *desc, tm_motif **ou
     // compile eagerly for 32-bit time keys (the common case) so errors surface
     // here; with the generic tier this is the shared module of the motif length
     const tmo::Plan gp = tmo::generic_plan(m->plan.l);
-    if (!ctx->compiler.get(use_generic(ctx->tier, m) ? gp : m->plan, 4, ctx->block, &err, ctx->min_waves)) {
+    if (!ctx->compiler.get(use_generic(ctx->tier, m) ? gp : m->plan, 4, ctx->block, &err, ctx->min_waves,
+                           tmo::mode_group(tmo::MODE_COUNT))) {
         delete m;
         return fail(TM_E_COMPILE, err);
     }
@@ -1024,6 +1026,24 @@ tm_status tm_motif_source(const tm_motif_desc *desc, int32_t key_bytes, char *bu
         std::memcpy(buf, s.data(), n);
         buf[n] = '\0';
     }
+    return TM_OK;
+}
+
+// Compile (or find in the on-disk cache) the modules a motif's calls load:
+// one per group of kernel modes, as get_module builds them at the default
+// block size. *code_bytes gets their total size.
+static tm_status compile_groups(const tmo::Plan &p, int32_t key_bytes, int64_t *code_bytes) {
+    const unsigned groups[3] = {tmo::mode_group(tmo::MODE_COUNT), tmo::mode_group(tmo::MODE_STATS),
+                                tmo::mode_group(tmo::MODE_ENUM_COUNT)};
+    int64_t total = 0;
+    for (unsigned gm : groups) {
+        std::vector<char> code;
+        std::string err;
+        if (!tmo::cached_code(tmo::generate_source(p, key_bytes, tmo::kDefaultBlock, 0, gm), &code, &err))
+            return fail(TM_E_COMPILE, err);
+        total += (int64_t)code.size();
+    }
+    if (code_bytes) *code_bytes = total;
     return TM_OK;
 }
 
@@ -1061,12 +1081,7 @@ tm_status tm_motif_compile_check(const tm_motif_desc *descs, int32_t q, int32_t 
         std::string err;
         if (!tmo::build_plan(&descs[0], &plan, gaps, &err)) return fail(TM_E_INVALID, err);
     }
-    std::string src = tmo::generate_source(plan, key_bytes, 256);
-    std::vector<char> code;
-    std::string err;
-    if (!tmo::cached_code(src, &code, &err)) return fail(TM_E_COMPILE, err);
-    if (code_bytes) *code_bytes = (int64_t)code.size();
-    return TM_OK;
+    return compile_groups(plan, key_bytes, code_bytes);
 }
 
 tm_status tm_generic_compile_check(int32_t l, int32_t key_bytes, int64_t *code_bytes) {
@@ -1074,7 +1089,7 @@ tm_status tm_generic_compile_check(int32_t l, int32_t key_bytes, int64_t *code_b
     if (key_bytes != 4 && key_bytes != 8) return fail(TM_E_INVALID, "key_bytes must be 4 or 8");
     std::string src;
     if (l > 0) {
-        src = tmo::generate_source(tmo::generic_plan(l), key_bytes, 256);
+        return compile_groups(tmo::generic_plan(l), key_bytes, code_bytes);
     } else {
         std::vector<tmo::Plan> gplans;
         for (int k = 1; k <= TM_MAX_EDGES; k++) gplans.push_back(tmo::generic_plan(k));
@@ -1098,7 +1113,7 @@ tm_status tm_count(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_r
     if (!count_out) return fail(TM_E_INVALID, "count_out is null");
     DeviceGuard dg(ctx->device);
     std::shared_ptr<tmo::Module> mod;
-    if ((st = get_module(ctx, g, m, ctx->tier, &mod)) != TM_OK) return st;
+    if ((st = get_module(ctx, g, m, ctx->tier, tmo::MODE_COUNT, &mod)) != TM_OK) return st;
     WsLease lease(ctx);
     tm_ctx::Workspace *w = lease.w;
     int64_t r0, r1, chunks = 0;
@@ -1142,7 +1157,7 @@ tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const
     if (!stats_out) return fail(TM_E_INVALID, "stats_out is null");
     DeviceGuard dg(ctx->device);
     std::shared_ptr<tmo::Module> mod;
-    if ((st = get_module(ctx, g, m, ctx->tier, &mod)) != TM_OK) return st;
+    if ((st = get_module(ctx, g, m, ctx->tier, tmo::MODE_STATS, &mod)) != TM_OK) return st;
     WsLease lease(ctx);
     tm_ctx::Workspace *w = lease.w;
     int64_t chunks = 0, r0 = 0;
@@ -1173,7 +1188,7 @@ tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, cons
     std::shared_ptr<tmo::Module> mod;
     tm_status st;
     if (rows_out) *rows_out = nullptr;
-    if ((st = get_module(ctx, g, m, tier, &mod)) != TM_OK) return st;
+    if ((st = get_module(ctx, g, m, tier, tmo::MODE_ENUM_COUNT, &mod)) != TM_OK) return st;
     int64_t r0, r1;
     root_ids(g, range, &r0, &r1);
     // the setting a count of this key was tuned to, else the defaults

@@ -38,6 +38,10 @@
 
 namespace tmo {
 
+// Batched modules with more matchers than this emit them as separate
+// functions (see Emitter::matcher).
+constexpr int kMaxInlinedMatchers = 8;
+
 Plan generic_plan(int l) {
     Plan p;
     p.l = l;
@@ -997,7 +1001,14 @@ struct Emitter {
         (void)K;
     }
 
-    void matcher(int fi) {
+    // `outlined`: the matcher is a separate (non-inlined) function of the
+    // kernel. A module with many matchers compiles in time superlinear in the
+    // kernel's size when all of them are inlined into it (register
+    // coalescing over one huge function); as separate functions each is
+    // compiled on its own. Such a matcher reads the launch arguments from the
+    // kernel argument segment (scalar loads, as the inlined form does) and
+    // makes its uniform parameters wave-uniform again on entry.
+    void matcher(int fi, bool outlined = false) {
         const int L = p.l, K = p.k;
         const bool glob = has_global();
         o << "// motif " << p.key() << "\n";
@@ -1015,8 +1026,17 @@ struct Emitter {
             o << "  return (i64)g.pr_t[f] > (i64)t0 + d;\n";
             o << "}\n#endif\n";
         }
-        o << "template <int MODE>\n__device__ __forceinline__ i64 match" << fi
-          << "(const GArgs& g, int qi, i64 chunk, i64 ih, int in) {\n";
+        if (outlined) {
+            o << "template <int MODE>\n__device__ __noinline__ i64 match" << fi
+              << "(int qi_, i64 chunk_, i64 ih_, int in_) {\n";
+            o << "  const GArgs g = *(const __attribute__((address_space(4))) GArgs*)"
+                 "__builtin_amdgcn_kernarg_segment_ptr();\n";
+            o << "  const int qi = __builtin_amdgcn_readfirstlane(qi_), in = __builtin_amdgcn_readfirstlane(in_);\n";
+            o << "  const i64 chunk = bcast64(chunk_), ih = bcast64(ih_);\n";
+        } else {
+            o << "template <int MODE>\n__device__ __forceinline__ i64 match" << fi
+              << "(const GArgs& g, int qi, i64 chunk, i64 ih, int in) {\n";
+        }
         o << "  const int lane = lane_id();\n";
         o << "  const QArgs* q = g.qa + qi;\n";
         o << "  const i64 q_r0 = q->r0, q_delta = q->delta, q_c0 = q->c0, q_c1 = q->c0 + q->nchunks;\n";
@@ -1356,15 +1376,20 @@ struct Emitter {
 const char *const kSingleNames[4] = {"tm_count", "tm_stats", "tm_enum_count", "tm_enum_write"};
 const char *const kBatchName = "tm_count_batch";
 
-void emit_kernels(std::ostringstream &o, int nfn, int block, bool all_modes, int min_waves) {
-    const char *const *names = all_modes ? kSingleNames : &kBatchName;
-    const int nmodes = all_modes ? 4 : 1;
+// `modes`: bit set of the single-query kernels to emit (bit i = mode i), or
+// 0 for the batched module's one counting kernel.
+void emit_kernels(std::ostringstream &o, int nfn, int block, unsigned modes, int min_waves, bool outlined) {
+    const bool batch = modes == 0;
+    const char *const *names = batch ? &kBatchName : kSingleNames;
+    const int nmodes = batch ? 1 : 4;
     for (int mode = 0; mode < nmodes; mode++) {
+        if (!batch && !((modes >> mode) & 1u)) continue;
         auto run = [&](const char *ind, const char *qv, const char *cv, const char *ih, const char *in) {
             o << ind << "{ const int fn = __builtin_amdgcn_readfirstlane(g.qa[" << qv << "].fn);\n";
             o << ind << "  switch (fn) {\n";
             for (int f = 0; f < nfn; f++)
-                o << ind << "    case " << f << ": c = match" << f << "<" << mode << ">(g, " << qv << ", " << cv
+                o << ind << "    case " << f << ": c = match" << f << "<" << mode << ">(" << (outlined ? "" : "g, ")
+                  << qv << ", " << cv
                   << ", " << ih << ", " << in << "); break;\n";
             o << ind << "    default: c = -1; break;\n";
             o << ind << "  } }\n";
@@ -1452,11 +1477,11 @@ static std::string header(int key_bytes) {
     return o.str();
 }
 
-std::string generate_source(const Plan &p, int key_bytes, int block, int min_waves) {
+std::string generate_source(const Plan &p, int key_bytes, int block, int min_waves, unsigned modes) {
     Emitter e(p, p.generic);
     e.o << header(key_bytes);
     e.matcher(0);
-    emit_kernels(e.o, 1, block, true, min_waves);
+    emit_kernels(e.o, 1, block, modes & kAllModes, min_waves, false);
     return e.o.str();
 }
 
@@ -1464,16 +1489,24 @@ std::string generate_batch_source(const std::vector<const Plan *> &plans, int ke
                                   int min_waves) {
     std::ostringstream all;
     all << header(key_bytes);
+    int n_generic = 0;
+    for (auto *pl : plans) n_generic += pl->generic ? 1 : 0;
+    const bool outlined = (int)plans.size() > kMaxInlinedMatchers || n_generic > 1;
     for (size_t f = 0; f < plans.size(); f++) {
         Emitter e(*plans[f], plans[f]->generic);
-        e.matcher((int)f);
+        e.matcher((int)f, outlined);
         all << e.o.str();
     }
-    emit_kernels(all, (int)plans.size(), block, false, min_waves);
+    emit_kernels(all, (int)plans.size(), block, 0u, min_waves, outlined);
     return all.str();
 }
 
 // ---------------------------------------------------------------- compiling
+
+// hipRTC options of every motif module (packed fp32 instructions disabled)
+static const char *const kRtcOpts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+                                       "-Xclang", "-packed-fp32-ops"};
+static const int kRtcNopts = (int)(sizeof(kRtcOpts) / sizeof(kRtcOpts[0]));
 
 bool compile_to_code(const std::string &src, std::vector<char> *code, std::string *err) {
     hiprtcProgram prog;
@@ -1481,9 +1514,7 @@ bool compile_to_code(const std::string &src, std::vector<char> *code, std::strin
         *err = "hiprtcCreateProgram failed";
         return false;
     }
-    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
-                          "-packed-fp32-ops"};
-    hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+    hiprtcResult rc = hiprtcCompileProgram(prog, kRtcNopts, kRtcOpts);
     if (rc != HIPRTC_SUCCESS) {
         size_t n = 0;
         hiprtcGetProgramLogSize(prog, &n);
@@ -1577,18 +1608,23 @@ static void cache_store(const std::string &src, const std::vector<char> &code) {
 }
 
 bool cached_code(const std::string &src, std::vector<char> *code, std::string *err) {
-    // the cache key is the compiler version plus the exact source text
+    // the cache key is the compiler version, its options and the exact source text
     int major = 0, minor = 0;
     hiprtcVersion(&major, &minor);
-    const std::string key = "// hiprtc " + std::to_string(major) + "." + std::to_string(minor) + "\n" + src;
+    std::string key = "// hiprtc " + std::to_string(major) + "." + std::to_string(minor);
+    for (int i = 0; i < kRtcNopts; i++) key += std::string(" ") + kRtcOpts[i];
+    key += "\n" + src;
     if (cache_load(key, code)) return true;
     if (!compile_to_code(src, code, err)) return false;
     cache_store(key, *code);
     return true;
 }
 
-static bool compile_module(const std::string &src, int block, int nmodes, Module *out, std::string *err) {
-    const char *const *names = nmodes == 1 ? &kBatchName : kSingleNames;
+// `modes` as for emit_kernels: the kernels the module holds.
+static bool compile_module(const std::string &src, int block, unsigned modes, Module *out, std::string *err) {
+    const bool batch = modes == 0;
+    const char *const *names = batch ? &kBatchName : kSingleNames;
+    const int nmodes = batch ? 1 : 4;
     auto t0 = std::chrono::steady_clock::now();
     std::vector<char> code;
     if (!cached_code(src, &code, err)) return false;
@@ -1598,6 +1634,7 @@ static bool compile_module(const std::string &src, int block, int nmodes, Module
         return false;
     }
     for (int mode = 0; mode < nmodes; mode++) {
+        if (!batch && !((modes >> mode) & 1u)) continue;
         he = hipModuleGetFunction(&out->fn[mode], out->mod, names[mode]);
         if (he != hipSuccess) {
             *err = std::string("hipModuleGetFunction(") + names[mode] + "): " + hipGetErrorString(he);
@@ -1607,13 +1644,15 @@ static bool compile_module(const std::string &src, int block, int nmodes, Module
         }
     }
     int nb = 0;
-    if (out->fn[0] && hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, out->fn[0], block, 0) == hipSuccess)
+    hipFunction_t any = nullptr;
+    for (int mode = 0; mode < MODE_COUNT_ && !any; mode++) any = out->fn[mode];
+    if (any && hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, any, block, 0) == hipSuccess)
         out->max_blocks_per_cu = nb;
     out->compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return true;
 }
 
-std::shared_ptr<Module> Compiler::lookup_or_build(const std::string &key, int block, int nmodes,
+std::shared_ptr<Module> Compiler::lookup_or_build(const std::string &key, int block, unsigned modes,
                                                   const std::function<std::string()> &make, std::string *err) {
     {
         std::unique_lock<std::mutex> lk(mu);
@@ -1626,7 +1665,7 @@ std::shared_ptr<Module> Compiler::lookup_or_build(const std::string &key, int bl
         inflight.insert(key);
     }
     auto m = std::make_shared<Module>();
-    const bool ok = compile_module(make(), block, nmodes, m.get(), err);
+    const bool ok = compile_module(make(), block, modes, m.get(), err);
     std::lock_guard<std::mutex> lk(mu);
     inflight.erase(key);
     if (ok) cache[key] = m;
@@ -1634,10 +1673,13 @@ std::shared_ptr<Module> Compiler::lookup_or_build(const std::string &key, int bl
     return ok ? m : nullptr;
 }
 
-std::shared_ptr<Module> Compiler::get(const Plan &p, int key_bytes, int block, std::string *err, int min_waves) {
+std::shared_ptr<Module> Compiler::get(const Plan &p, int key_bytes, int block, std::string *err, int min_waves,
+                                      unsigned modes) {
     const std::string key = "S" + std::to_string(key_bytes) + "b" + std::to_string(block) +
-                            (min_waves ? "w" + std::to_string(min_waves) : std::string()) + ":" + p.key();
-    return lookup_or_build(key, block, 4, [&] { return generate_source(p, key_bytes, block, min_waves); }, err);
+                            (min_waves ? "w" + std::to_string(min_waves) : std::string()) + "m" +
+                            std::to_string(modes) + ":" + p.key();
+    return lookup_or_build(key, block, modes,
+                           [&] { return generate_source(p, key_bytes, block, min_waves, modes); }, err);
 }
 
 std::shared_ptr<Module> Compiler::get_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
@@ -1645,7 +1687,7 @@ std::shared_ptr<Module> Compiler::get_batch(const std::vector<const Plan *> &pla
     std::string key = "B" + std::to_string(key_bytes) + "b" + std::to_string(block) +
                       (min_waves ? "w" + std::to_string(min_waves) : std::string()) + ":";
     for (auto *p : plans) key += p->key() + "|";
-    return lookup_or_build(key, block, 1,
+    return lookup_or_build(key, block, 0u,
                            [&] { return generate_batch_source(plans, key_bytes, block, min_waves); }, err);
 }
 

@@ -141,16 +141,27 @@ struct Compiler {
     std::set<std::string> inflight;            // keys some thread is compiling now
     int device = 0;
     // min_waves > 0 asks the compiler to fit that many waves per SIMD
-    std::shared_ptr<Module> get(const Plan &p, int key_bytes, int block, std::string *err, int min_waves = 0);
+    // `modes`: the kernels the module holds (bit i = Mode i; see mode_group)
+    std::shared_ptr<Module> get(const Plan &p, int key_bytes, int block, std::string *err, int min_waves,
+                                unsigned modes);
     std::shared_ptr<Module> get_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
                                       std::string *err, int min_waves = 0);
-    // the cached module for `key`, else one built by `make` (which compiles
-    // `nmodes` kernels); concurrent callers of one key share a single compile
-    std::shared_ptr<Module> lookup_or_build(const std::string &key, int block, int nmodes,
+    // the cached module for `key`, else one built by `make` (holding the
+    // kernels of `modes`, 0 = the batched kernel); concurrent callers of one
+    // key share a single compile
+    std::shared_ptr<Module> lookup_or_build(const std::string &key, int block, unsigned modes,
                                             const std::function<std::string()> &make, std::string *err);
 };
 
-std::string generate_source(const Plan &p, int key_bytes, int block, int min_waves = 0);
+constexpr int kDefaultBlock = 256;  // threads per workgroup of the mining kernels
+// every single-query kernel; a module is compiled per group of modes one call
+// needs (mode_group), so a count compiles one kernel, not four
+constexpr unsigned kAllModes = 0xFu;
+inline unsigned mode_group(int mode) {
+    return mode == MODE_ENUM_COUNT || mode == MODE_ENUM_WRITE ? (1u << MODE_ENUM_COUNT) | (1u << MODE_ENUM_WRITE)
+                                                              : 1u << mode;
+}
+std::string generate_source(const Plan &p, int key_bytes, int block, int min_waves = 0, unsigned modes = kAllModes);
 std::string generate_batch_source(const std::vector<const Plan *> &plans, int key_bytes, int block,
                                   int min_waves = 0);
 bool build_plan(const tm_motif_desc *d, Plan *p, int64_t *gaps, std::string *err);
@@ -202,7 +213,7 @@ struct TuneEntry {
 struct tm_ctx {
     int device = 0;
     int num_cus = 0;
-    int block = 256;
+    int block = tmo::kDefaultBlock;
     int64_t root_chunk = 256;
     int64_t grid = 0;
     int profile = 0;
