@@ -70,6 +70,55 @@ def algorithmic_bytes(st: dict, l: int, n_enum: int = 0) -> int:
             + 12 * st.get("leaf_count_reads", 0))
 
 
+class fixed_setting:
+    """Context manager: launch with a fixed setting (autotuning off) and
+    restore the context's parameters afterwards."""
+
+    def __init__(self, ctx, root_chunk, split, split_min, leaf_min):
+        from paper_2310_02800_amd import _native as N
+        self.ctx = ctx
+        self.want = {N.TM_PARAM_AUTOTUNE: 0, N.TM_PARAM_ROOT_CHUNK: root_chunk, N.TM_PARAM_SPLIT: split,
+                     N.TM_PARAM_SPLIT_MIN: split_min, N.TM_PARAM_LEAF_MIN: leaf_min}
+
+    def __enter__(self):
+        self.old = {p: self.ctx.get_param(p) for p in self.want}
+        for p, v in self.want.items():
+            self.ctx.set_param(p, v)
+
+    def __exit__(self, *exc):
+        for p, v in self.old.items():
+            self.ctx.set_param(p, v)
+
+
+def time_launches(ctx, fn, steps, warmup, launches_per_call):
+    """Average kernel ms per launch (HIP events on the launch stream) and
+    wall ms per call of ``fn``."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+        kms.append(ctx.last_kernel_ms()[0])
+    torch.cuda.synchronize()
+    return statistics.mean(kms) / launches_per_call, (time.perf_counter() - t0) / steps * 1e3
+
+
+def roofline_entry(kernel, byte_model, bytes_per_launch, launch_ms, traffic=None):
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel, "byte_model": byte_model,
+            "bytes_per_launch": bytes_per_launch, "avg_launch_ms": launch_ms}
+
+
+METHOD_MODEL = ("method (every window searched, every candidate visited): 16 B per root + per window 8 B + "
+                "8 B per binary-search probe + 12 B per candidate visit + 4 B per predicate visit")
+CLOSED_MODEL = ("closed-form counting kernel: the method's bytes, except that each last-level window counted in "
+                "closed form reads the entries its searches probe (12 B each) instead of its candidates")
+
+
 def kernel_source_hash(motifs) -> str:
     from paper_2310_02800_amd import api
     h = hashlib.sha256()
@@ -96,10 +145,29 @@ def cpu_baseline(graph, motifs, budget_s: float):
         if dt >= budget_s / 4 or frac >= 1.0:
             break
         frac = min(1.0, frac * max(2.0, budget_s / 4 / max(dt, 1e-3)))
+    # one thread, on a slice about `threads` times narrower (same start)
+    frac1 = frac / threads
+    hi1 = lo + max(1, int(frac1 * (t_max - t_min)))
+    t0 = time.perf_counter()
+    total1 = sum(oracle.count(og, m, t_lo=lo, t_hi=hi1, nthreads=1) for m in motifs)
+    dt1 = time.perf_counter() - t0
     return {"value": total / dt, "unit": "instances/s", "cores": threads, "kind": "oracle",
             "sample": f"all six queries, roots with t in a {frac:.3f} slice of the span [{lo}, {hi}]; "
                       f"{total} instances in {dt:.2f} s",
-            "seconds": round(dt, 3)}
+            "seconds": round(dt, 3), "cpu_model": cpu_model(),
+            "one_thread": {"value": total1 / dt1 if dt1 > 0 else None, "unit": "instances/s", "cores": 1,
+                           "sample": f"roots with t in [{lo}, {hi1}]; {total1} instances in {dt1:.2f} s"}}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_batch64(ctx, args, stream):
@@ -563,23 +631,51 @@ def main():
 
     avg_launch_ms = statistics.mean(kernel_ms) / launches_per_step
     bytes_per_launch = bytes_per_step / launches_per_step
-    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-    traffic = None
     # HBM bytes per launch from the committed counter runs, valid only for the
     # same generated kernels, form and launch setting
     tfile = os.path.join(ROOT, "profiles", "tm_count_batch_wiki6_traffic.json")
     src_hash = kernel_source_hash(motifs)
+    records = []
     if os.path.exists(tfile):
         with open(tfile) as f:
             tr = json.load(f)
         if tr.get("kernel_source_hash") == src_hash and tr.get("form") == form:
-            for rec in tr.get("records", []):
-                lc = rec["launch"]
-                if (lc["root_chunk"], lc["split"], lc.get("split_min", 32) if lc["split"] else 0,
-                        lc.get("leaf_min")) == \
-                        (batch_setting[0], batch_setting[1], batch_setting[3] if batch_setting[1] else 0,
-                         batch_setting[4]):
-                    traffic = rec["bytes_per_launch"]
+            records = tr.get("records", [])
+
+    def traffic_for(setting):
+        for rec in records:
+            lc = rec["launch"]
+            if (lc["root_chunk"], lc["split"], lc.get("split_min", 32) if lc["split"] else 0,
+                    lc.get("leaf_min")) == (setting[0], setting[1], setting[3] if setting[1] else 0, setting[4]):
+                return rec["bytes_per_launch"]
+        return None
+
+    kname = "tm_count_batch" if form == "batched" else "tm_count"
+    # The same launches with the closed-form last level off: they do the
+    # method's whole search, so the method's byte model applies to them.
+    open_setting = (batch_setting[0], batch_setting[1], batch_setting[2], batch_setting[3], 0)
+    with fixed_setting(ctx, batch_setting[0], batch_setting[1], batch_setting[3], 0):
+        # per query, alone, closed form off
+        open_q = []
+        for h in handles:
+            open_q.append(time_launches(ctx, lambda: ctx.count(dg, h, stream=stream), args.steps, 1, 1)[0])
+        if form == "batched":
+            open_ms, open_wall = time_launches(ctx, batch_step, args.steps, args.warmup, 1)
+        else:
+            open_ms, open_wall = statistics.mean(open_q), sum(open_q)
+    log(f"closed form off: {open_ms:.2f} ms per launch")
+    roof_method = roofline_entry(f"{kname} (closed-form last level off)", METHOD_MODEL,
+                                 method_bytes_per_step / launches_per_step, open_ms, traffic_for(open_setting))
+    roof_closed = roofline_entry(kname, CLOSED_MODEL, bytes_per_launch, avg_launch_ms, traffic_for(batch_setting))
+    q_ms = [statistics.mean(kms_plain[i::len(handles)]) for i in range(len(handles))]
+    per_query = []
+    for i, (m, s_, c) in enumerate(zip(motifs, stats, counts)):
+        mb, ab = method_bytes(s_, m.l), algorithmic_bytes(s_, m.l)
+        per_query.append({"edges": m.edges, "delta": m.delta, "count": c,
+                          "kernel_ms": q_ms[i], "algorithmic_bytes": ab,
+                          "frac_closed_form_model": ab / (q_ms[i] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "kernel_ms_closed_form_off": open_q[i], "method_bytes": mb,
+                          "frac_method_model": mb / (open_q[i] * 1e-3) / 1e9 / HBM_PEAK_GBS})
 
     out = {
         "metric": "motif instances counted/sec per MI355X vs plain; p50/p99 query latency",
@@ -601,16 +697,16 @@ def main():
                   "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
                                  "p99": 1e3 * float(np.percentile(lat, 99))}},
         "vs_plain": (plain_s * 1e3) / result_ms,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "tm_count_batch" if form == "batched" else "tm_count", "avg_launch_ms": avg_launch_ms,
-                     "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "method_bytes_per_launch": method_bytes_per_step / launches_per_step,
-                     "leaf_windows_counted": sum(s["leaf_counted"] for s in stats)},
+        # the method's byte model on launches that do the method's work
+        "roofline": roof_method,
+        # the timed (closed-form) kernel under its own algorithm's byte model
+        "roofline_closed_form": roof_closed,
+        "closed_form": {"speedup": open_ms / avg_launch_ms, "leaf_windows_counted": sum(s["leaf_counted"] for s in stats),
+                        "ms_per_step_off": open_wall, "value_off": total_instances / (open_wall * 1e-3)},
         "setup": {"generate_s": round(gen_s, 2), "load_graph_s": round(load_s, 3),
                   "compile_single_s": round(compile_single_s, 2), "compile_batch_s": round(compile_batch_s, 2),
                   "kernel_source_hash": src_hash},
-        "per_query": [{"edges": m.edges, "delta": m.delta, "count": c} for m, c in zip(motifs, counts)],
+        "per_query": per_query,
         "launch": {"autotune": not args.no_autotune, "tuned_from": tuned_from,
                    "root_chunk": batch_setting[0], "split": batch_setting[1],
                    "split_min": batch_setting[3], "leaf_min": batch_setting[4], "tuned": batch_setting[2]},

@@ -240,13 +240,15 @@ tm_status tm_graph_set_node_labels(tm_graph *g, const int32_t *labels);
 tm_status tm_graph_edge_order(const tm_graph *g, int64_t *perm_out);
 
 /* Copy one direction of the device adjacency back to host memory, for
- * inspection (dir 0 = out-lists, 1 = in-lists). Any output may be NULL.
+ * inspection (dir 0 = out-lists, 1 = in-lists; 2 and 3 = the same lists
+ * sorted by (neighbour, time, edge id) instead, as the closed-form counts
+ * read them). Any output may be NULL.
  *   off     host uint32[n_nodes+1]: list of node v = positions [off[v], off[v+1])
  *           (in-list positions start at n_edges)
  *   nbr     host int32[n_edges]: the other endpoint, in list order
  *   eid     host int32[n_edges]: the edge id, in list order
  *   t_rel   host int64[n_edges]: time minus t_min, in list order
- * Each list is sorted by (time, edge id). */
+ * Lists of dir 0 and 1 are sorted by (time, edge id). */
 tm_status tm_graph_copy_csr(const tm_graph *g, int32_t dir, uint32_t *off, int32_t *nbr, int32_t *eid,
                             int64_t *t_rel);
 

@@ -79,7 +79,8 @@ class Graph:
         return out
 
     def csr(self, direction: int):
-        """(off, nbr, eid, t_rel) of the out- (0) or in- (1) adjacency."""
+        """(off, nbr, eid, t_rel) of the out- (0) or in- (1) adjacency, sorted
+        by time; 2 and 3: the same lists sorted by (neighbour, time)."""
         inf = self.info()
         n, m = inf["n_nodes"], inf["n_edges"]
         off = np.zeros(n + 1, np.uint32)
@@ -169,6 +170,14 @@ def motif_compile_check(edges, delta=0, key_bytes=4, **kw) -> int:
     d, keep = make_desc(edges, delta, **kw)
     n = ctypes.c_int64(0)
     N.check(N.lib().tm_motif_compile_check(ctypes.byref(d), 1, key_bytes, ctypes.byref(n)))
+    return n.value
+
+
+def generic_compile_check(l: int, key_bytes=4) -> int:
+    """Compile the table-driven (tier 1) modules for motifs of ``l`` edges, or
+    with ``l`` = 0 their batched module for 1-8 edges (no device)."""
+    n = ctypes.c_int64(0)
+    N.check(N.lib().tm_generic_compile_check(int(l), key_bytes, ctypes.byref(n)))
     return n.value
 
 

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtmotif.so")
-SOURCES = ["tm_api.cpp", "tm_codegen.cpp", "tm_server.cpp", "tm_device.hip"]
+SOURCES = ["tm_api.cpp", "tm_codegen.cpp", "tm_server.cpp", "tm_device.hip", "tm_sort.hip"]
 # Packed fp32 instructions are disabled for all device code.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang",
              "-packed-fp32-ops"]

@@ -956,22 +956,39 @@ tm_status tm_graph_edge_order(const tm_graph *g, int64_t *perm_out) {
 
 tm_status tm_graph_copy_csr(const tm_graph *g, int32_t dir, uint32_t *off, int32_t *nbr, int32_t *eid,
                             int64_t *t_rel) {
-    if (!g || (dir != 0 && dir != 1)) return fail(TM_E_INVALID, "bad argument");
+    if (!g || dir < 0 || dir > 3) return fail(TM_E_INVALID, "bad argument");
     DeviceGuard dg(g->device);
-    const int64_t m = g->m, base = dir ? m : 0;
-    if (off) HIP_TRY(hipMemcpy(off, dir ? g->d_off_in : g->d_off_out, (g->n + 1) * sizeof(uint32_t),
+    const bool pair = dir >= 2;
+    const int64_t m = g->m, base = (dir & 1) ? m : 0;
+    if (off) HIP_TRY(hipMemcpy(off, (dir & 1) ? g->d_off_in : g->d_off_out, (g->n + 1) * sizeof(uint32_t),
                                hipMemcpyDeviceToHost), "copy offsets");
     if (m == 0) return TM_OK;
-    if (nbr) HIP_TRY(hipMemcpy(nbr, g->d_adj_nbr + base, m * sizeof(int32_t), hipMemcpyDeviceToHost), "copy nbr");
-    if (eid) HIP_TRY(hipMemcpy(eid, g->d_adj_eid + base, m * sizeof(int32_t), hipMemcpyDeviceToHost), "copy eid");
+    if (nbr) HIP_TRY(hipMemcpy(nbr, (pair ? g->d_pr_nbr : g->d_adj_nbr) + base, m * sizeof(int32_t),
+                               hipMemcpyDeviceToHost), "copy nbr");
+    if (eid && !pair)
+        HIP_TRY(hipMemcpy(eid, g->d_adj_eid + base, m * sizeof(int32_t), hipMemcpyDeviceToHost), "copy eid");
+    if (eid && pair) {
+        // the pair-sorted lists keep no edge ids: place each time-sorted
+        // entry's id at its pair-sorted position
+        std::vector<int32_t> ids(m);
+        std::vector<uint32_t> pos(m);
+        HIP_TRY(hipMemcpy(ids.data(), g->d_adj_eid + base, m * sizeof(int32_t), hipMemcpyDeviceToHost), "copy eid");
+        HIP_TRY(hipMemcpy(pos.data(), g->d_pr_pos + base, m * sizeof(uint32_t), hipMemcpyDeviceToHost), "copy pos");
+        for (int64_t i = 0; i < m; i++) {
+            const int64_t p = (int64_t)pos[i] - base;
+            if (p < 0 || p >= m) return fail(TM_E_DEVICE, "pair-sorted position out of range");
+            eid[p] = ids[i];
+        }
+    }
     if (t_rel) {
+        const void *src = pair ? g->d_pr_t : g->d_adj_t;
         if (g->key_bytes == 8) {
-            HIP_TRY(hipMemcpy(t_rel, (const int64_t *)g->d_adj_t + base, m * sizeof(int64_t), hipMemcpyDeviceToHost),
+            HIP_TRY(hipMemcpy(t_rel, (const int64_t *)src + base, m * sizeof(int64_t), hipMemcpyDeviceToHost),
                     "copy t");
         } else {
             std::vector<int32_t> tmp(m);
-            HIP_TRY(hipMemcpy(tmp.data(), (const int32_t *)g->d_adj_t + base, m * sizeof(int32_t),
-                              hipMemcpyDeviceToHost), "copy t");
+            HIP_TRY(hipMemcpy(tmp.data(), (const int32_t *)src + base, m * sizeof(int32_t), hipMemcpyDeviceToHost),
+                    "copy t");
             for (int64_t i = 0; i < m; i++) t_rel[i] = tmp[i];
         }
     }
@@ -1214,8 +1231,7 @@ tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, cons
     if (st != TM_OK) return st;
     // exclusive scan -> per-chunk output offsets (one extra entry: the total)
     HIP_TRY(tmo::dev_fill_u64(w->chunk_cnt + chunks, 0, 1, stream), "scan tail");
-    size_t need = 0;
-    HIP_TRY(tmo::dev_exclusive_scan_u64(w->chunk_cnt, w->chunk_off, chunks + 1, nullptr, &need, stream), "scan size");
+    const size_t need = (size_t)tmo::scan_tmp_elems(chunks + 1) * sizeof(uint64_t);
     if (need > w->scan_tmp_bytes) {
         if (w->scan_tmp) hipFree(w->scan_tmp);
         w->scan_tmp = nullptr;
@@ -1223,8 +1239,8 @@ tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, cons
         HIP_TRY(hipMalloc(&w->scan_tmp, need), "scan workspace");
         w->scan_tmp_bytes = need;
     }
-    size_t have = w->scan_tmp_bytes;
-    HIP_TRY(tmo::dev_exclusive_scan_u64(w->chunk_cnt, w->chunk_off, chunks + 1, w->scan_tmp, &have, stream), "scan");
+    HIP_TRY(tmo::dev_exclusive_scan_u64(w->chunk_cnt, w->chunk_off, chunks + 1, (uint64_t *)w->scan_tmp, stream),
+            "scan");
     HIP_TRY(hipMemcpyAsync(w->h_ctl + 64, w->chunk_off + chunks, sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
             "read total");
     HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),

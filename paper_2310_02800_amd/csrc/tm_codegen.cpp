@@ -1027,10 +1027,12 @@ struct Emitter {
             o << "}\n#endif\n";
         }
         if (outlined) {
+            // `ga_` is the address of the kernel's argument segment (the
+            // kernel's only argument is the GArgs); a callee cannot read that
+            // address itself, so the kernel passes it
             o << "template <int MODE>\n__device__ __noinline__ i64 match" << fi
-              << "(int qi_, i64 chunk_, i64 ih_, int in_) {\n";
-            o << "  const GArgs g = *(const __attribute__((address_space(4))) GArgs*)"
-                 "__builtin_amdgcn_kernarg_segment_ptr();\n";
+              << "(u64 ga_, int qi_, i64 chunk_, i64 ih_, int in_) {\n";
+            o << "  const GArgs g = *(const __attribute__((address_space(4))) GArgs*)(u64)bcast64((i64)ga_);\n";
             o << "  const int qi = __builtin_amdgcn_readfirstlane(qi_), in = __builtin_amdgcn_readfirstlane(in_);\n";
             o << "  const i64 chunk = bcast64(chunk_), ih = bcast64(ih_);\n";
         } else {
@@ -1388,7 +1390,7 @@ void emit_kernels(std::ostringstream &o, int nfn, int block, unsigned modes, int
             o << ind << "{ const int fn = __builtin_amdgcn_readfirstlane(g.qa[" << qv << "].fn);\n";
             o << ind << "  switch (fn) {\n";
             for (int f = 0; f < nfn; f++)
-                o << ind << "    case " << f << ": c = match" << f << "<" << mode << ">(" << (outlined ? "" : "g, ")
+                o << ind << "    case " << f << ": c = match" << f << "<" << mode << ">(" << (outlined ? "ga, " : "g, ")
                   << qv << ", " << cv
                   << ", " << ih << ", " << in << "); break;\n";
             o << ind << "    default: c = -1; break;\n";
@@ -1398,6 +1400,7 @@ void emit_kernels(std::ostringstream &o, int nfn, int block, unsigned modes, int
         if (min_waves > 0) o << ", " << min_waves;  // minimum waves per SIMD
         o << ") void " << names[mode] << "(GArgs g) {\n";
         o << "  const int lane = lane_id();\n";
+        if (outlined) o << "  const u64 ga = (u64)__builtin_amdgcn_kernarg_segment_ptr();\n";
         o << "  i64 c = 0;\n";
         o << "  if (lane == 0) { atomicAdd(&g.ctl[8], 1ull); c = (i64)atomicAdd(&g.ctl[0], 1ull); }\n";
         o << "  c = bcast64(c);\n";

@@ -8,14 +8,14 @@
 //   2. times are rebased to the minimum (int32 when the span allows);
 //   3. per direction, a stable radix sort of (node, edge id) groups edge ids by
 //      node while keeping id order, which is time order, inside each node; a
-//      degree histogram and an exclusive scan give the offsets;
+//      degree histogram and an exclusive scan give the offsets (the sort and
+//      scan kernels are in tm_sort.hip);
 //   4. a gather writes the adjacency as structure-of-arrays (time, neighbour,
 //      edge id, weight), so the search kernels read contiguous windows.
 // Out-lists occupy positions [0, m) and in-lists [m, 2m) of one unified
 // adjacency, so a candidate window is a plain index range whichever list a
 // motif level uses.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include "tm_internal.h"
 
@@ -105,11 +105,6 @@ __global__ void k_gather_adj(int64_t m, const int32_t *eids, const int32_t *othe
 // makes the check report this helper's own launches.
 void clear_stale_error() { (void)hipGetLastError(); }
 
-__global__ void k_pair_keys(int64_t m, const int32_t *key, const int32_t *other, uint64_t *k64) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-        k64[i] = ((uint64_t)(uint32_t)key[i] << 32) | (uint64_t)(uint32_t)other[i];
-}
-
 // pr_pos[pos[e]] = add + i: where the adjacency entry of edge e sits in the
 // pair-sorted order of the same lists
 __global__ void k_pair_pos(int64_t m, const int32_t *ids, const uint32_t *pos, uint32_t add, uint32_t *pr_pos) {
@@ -127,6 +122,28 @@ __global__ void k_gather_pairs(int64_t m, const int32_t *ids, const int32_t *oth
     }
 }
 
+// int64 time -> unsigned key with the same order (sign bit flipped), and back
+__global__ void k_time_keys(int64_t m, const int64_t *t, uint64_t *k) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        k[i] = (uint64_t)t[i] ^ (1ull << 63);
+}
+
+__global__ void k_untime_keys(int64_t m, const uint64_t *k, int64_t *t) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        t[i] = (int64_t)(k[i] ^ (1ull << 63));
+}
+
+// (node, neighbour) as one key: node in the high bits
+__global__ void k_pair_keys(int64_t m, const int32_t *key, const int32_t *other, int nbits, uint64_t *k64) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        k64[i] = ((uint64_t)(uint32_t)key[i] << nbits) | (uint64_t)(uint32_t)other[i];
+}
+
+__global__ void k_copy_u32(int64_t m, const int32_t *in, uint32_t *out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (uint32_t)in[i];
+}
+
 int bits_for(int64_t n) {
     int b = 1;
     while (b < 31 && (int64_t(1) << b) < n) b++;
@@ -140,12 +157,6 @@ hipError_t dev_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     k_fill_u64<<<blocks_for(n), kThreads, 0, s>>>(p, v, n);
     return hipGetLastError();
-}
-
-hipError_t dev_exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, void *tmp, size_t *tmp_bytes,
-                                  hipStream_t s) {
-    clear_stale_error();
-    return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, in, out, (int)n, s);
 }
 
 hipError_t dev_check_ids(int64_t m, int64_t n, const int32_t *d_src, const int32_t *d_dst, uint32_t *d_bad,
@@ -164,23 +175,35 @@ hipError_t dev_sort_by_time(int64_t m, int64_t *d_t, int64_t *d_perm, hipStream_
         if (m == 1) k_iota_i64<<<1, kThreads, 0, s>>>(d_perm, m);
         return hipGetLastError();
     }
-    int64_t *t_out = nullptr, *idx_in = nullptr;
-    void *tmp = nullptr;
-    size_t tmp_bytes = 0;
-    hipError_t e = hipMalloc(&t_out, m * sizeof(int64_t));
-    if (e != hipSuccess) return e;
-    e = hipMalloc(&idx_in, m * sizeof(int64_t));
-    if (e != hipSuccess) { (void)hipFree(t_out); return e; }
-    k_iota_i64<<<blocks_for(m), kThreads, 0, s>>>(idx_in, m);
-    e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, d_t, t_out, idx_in, d_perm, (int)m, 0, 64, s);
-    if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes);
-    if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, d_t, t_out, idx_in, d_perm, (int)m, 0, 64, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_t, t_out, m * sizeof(int64_t), hipMemcpyDeviceToDevice, s);
+    uint64_t *k = nullptr, *k_alt = nullptr;
+    int64_t *v_alt = nullptr;
+    uint32_t *hist = nullptr, *stmp = nullptr;
+    bool in_alt = false;
+    const int64_t nh = radix_hist_elems(m);
+    hipError_t e = hipMalloc(&k, m * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&k_alt, m * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&v_alt, m * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc(&hist, nh * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&stmp, scan_tmp_elems(nh) * sizeof(uint32_t));
+    if (e == hipSuccess) {
+        k_time_keys<<<blocks_for(m), kThreads, 0, s>>>(m, d_t, k);
+        k_iota_i64<<<blocks_for(m), kThreads, 0, s>>>(d_perm, m);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = dev_radix_sort_pairs<uint64_t, int64_t>(k, d_perm, k_alt, v_alt, m, 64, hist, stmp, s,
+                                                                      &in_alt);
+    if (e == hipSuccess && in_alt) e = hipMemcpyAsync(d_perm, v_alt, m * sizeof(int64_t), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) {
+        k_untime_keys<<<blocks_for(m), kThreads, 0, s>>>(m, in_alt ? k_alt : k, d_t);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(tmp);
-    (void)hipFree(t_out);
-    (void)hipFree(idx_in);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(stmp);
+    (void)hipFree(hist);
+    (void)hipFree(v_alt);
+    (void)hipFree(k_alt);
+    (void)hipFree(k);
     return e;
 }
 
@@ -211,42 +234,45 @@ hipError_t dev_build_pairs(int64_t n, int64_t m, const int32_t *d_key, const int
     clear_stale_error();
     if (m <= 0) return hipSuccess;
     hipError_t e = hipSuccess;
-    uint64_t *k_in = nullptr, *k_out = nullptr;
-    int32_t *ids_in = nullptr, *ids_out = nullptr;
-    void *tmp = nullptr;
-    size_t tmp_bytes = 0;
-    const int end_bit = 32 + bits_for(n);
-    e = hipMalloc(&k_in, m * sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMalloc(&k_out, m * sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMalloc(&ids_in, m * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc(&ids_out, m * sizeof(int32_t));
+    uint64_t *k = nullptr, *k_alt = nullptr;
+    int32_t *ids = nullptr, *ids_alt = nullptr;
+    uint32_t *hist = nullptr, *stmp = nullptr;
+    bool in_alt = false;
+    const int nbits = bits_for(n);
+    const int64_t nh = radix_hist_elems(m);
+    e = hipMalloc(&k, m * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&k_alt, m * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&ids, m * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&ids_alt, m * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&hist, nh * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&stmp, scan_tmp_elems(nh) * sizeof(uint32_t));
     if (e != hipSuccess) goto done;
-    k_pair_keys<<<blocks_for(m), kThreads, 0, s>>>(m, d_key, d_other, k_in);
-    k_iota_i32<<<blocks_for(m), kThreads, 0, s>>>(ids_in, m);
-    // radix sort is stable: equal (node, neighbour) keys keep edge-id order,
+    k_pair_keys<<<blocks_for(m), kThreads, 0, s>>>(m, d_key, d_other, nbits, k);
+    k_iota_i32<<<blocks_for(m), kThreads, 0, s>>>(ids, m);
+    // the sort is stable: equal (node, neighbour) keys keep edge-id order,
     // which is time order
-    e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k_in, k_out, ids_in, ids_out, (int)m, 0, end_bit, s);
+    e = dev_radix_sort_pairs<uint64_t, int32_t>(k, ids, k_alt, ids_alt, m, 2 * nbits, hist, stmp, s, &in_alt);
     if (e != hipSuccess) goto done;
-    e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1);
-    if (e != hipSuccess) goto done;
-    e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, k_in, k_out, ids_in, ids_out, (int)m, 0, end_bit, s);
-    if (e != hipSuccess) goto done;
-    if (key_bytes == 4)
-        k_gather_pairs<int32_t><<<blocks_for(m), kThreads, 0, s>>>(m, ids_out, d_other, (const int32_t *)d_tk,
-                                                                    d_pr_nbr, (int32_t *)d_pr_t);
-    else
-        k_gather_pairs<int64_t><<<blocks_for(m), kThreads, 0, s>>>(m, ids_out, d_other, (const int64_t *)d_tk,
-                                                                    d_pr_nbr, (int64_t *)d_pr_t);
-    k_pair_pos<<<blocks_for(m), kThreads, 0, s>>>(m, ids_out, d_pos, add, d_pr_pos);
+    {
+        const int32_t *sorted = in_alt ? ids_alt : ids;
+        if (key_bytes == 4)
+            k_gather_pairs<int32_t><<<blocks_for(m), kThreads, 0, s>>>(m, sorted, d_other, (const int32_t *)d_tk,
+                                                                        d_pr_nbr, (int32_t *)d_pr_t);
+        else
+            k_gather_pairs<int64_t><<<blocks_for(m), kThreads, 0, s>>>(m, sorted, d_other, (const int64_t *)d_tk,
+                                                                        d_pr_nbr, (int64_t *)d_pr_t);
+        k_pair_pos<<<blocks_for(m), kThreads, 0, s>>>(m, sorted, d_pos, add, d_pr_pos);
+    }
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
 done:
     (void)hipStreamSynchronize(s);
-    (void)hipFree(tmp);
-    (void)hipFree(ids_out);
-    (void)hipFree(ids_in);
-    (void)hipFree(k_out);
-    (void)hipFree(k_in);
+    (void)hipFree(stmp);
+    (void)hipFree(hist);
+    (void)hipFree(ids_alt);
+    (void)hipFree(ids);
+    (void)hipFree(k_alt);
+    (void)hipFree(k);
     return e;
 }
 
@@ -258,56 +284,56 @@ hipError_t dev_build_csr(int64_t n, int64_t m, const int32_t *d_key, const int32
                          int32_t *d_adj_nbr, int32_t *d_adj_eid, float *d_adj_w, uint32_t *d_pos, hipStream_t s) {
     clear_stale_error();
     hipError_t e = hipSuccess;
-    uint32_t *deg = nullptr;
-    int32_t *keys_out = nullptr, *ids_in = nullptr, *ids_out = nullptr;
-    void *tmp = nullptr;
-    size_t tmp_bytes = 0, scan_bytes = 0;
+    uint32_t *deg = nullptr, *keys = nullptr, *keys_alt = nullptr, *hist = nullptr, *stmp = nullptr;
+    int32_t *ids = nullptr, *ids_alt = nullptr;
+    bool in_alt = false;
     const int nbits = bits_for(n);
+    const int64_t nh = radix_hist_elems(std::max<int64_t>(m, 1));
+    const int64_t ntmp = std::max(scan_tmp_elems(nh), scan_tmp_elems(n + 1));
     e = hipMalloc(&deg, (n + 1) * sizeof(uint32_t));
-    if (e != hipSuccess) return e;
+    if (e == hipSuccess) e = hipMalloc(&stmp, ntmp * sizeof(uint32_t));
+    if (e != hipSuccess) goto done;
     k_fill_u32<<<blocks_for(n + 1), kThreads, 0, s>>>(deg, 0u, n + 1);
     if (m > 0) {
-        e = hipMalloc(&keys_out, m * sizeof(int32_t));
-        if (e == hipSuccess) e = hipMalloc(&ids_in, m * sizeof(int32_t));
-        if (e == hipSuccess) e = hipMalloc(&ids_out, m * sizeof(int32_t));
+        e = hipMalloc(&keys, m * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&keys_alt, m * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&ids, m * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&ids_alt, m * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&hist, nh * sizeof(uint32_t));
         if (e != hipSuccess) goto done;
         k_degree<<<blocks_for(m), kThreads, 0, s>>>(m, d_key, deg);
-        k_iota_i32<<<blocks_for(m), kThreads, 0, s>>>(ids_in, m);
-        e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, d_key, keys_out, ids_in, ids_out, (int)m, 0,
-                                               nbits, s);
+        k_copy_u32<<<blocks_for(m), kThreads, 0, s>>>(m, d_key, keys);
+        k_iota_i32<<<blocks_for(m), kThreads, 0, s>>>(ids, m);
+        e = hipGetLastError();
+        if (e != hipSuccess) goto done;
+        e = dev_radix_sort_pairs<uint32_t, int32_t>(keys, ids, keys_alt, ids_alt, m, nbits, hist, stmp, s, &in_alt);
         if (e != hipSuccess) goto done;
     }
-    e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, deg, d_off, (int)(n + 1), s);
-    if (e != hipSuccess) goto done;
-    if (scan_bytes > tmp_bytes) tmp_bytes = scan_bytes;
-    e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1);
-    if (e != hipSuccess) goto done;
-    if (m > 0) {
-        e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, d_key, keys_out, ids_in, ids_out, (int)m, 0, nbits,
-                                               s);
-        if (e != hipSuccess) goto done;
-    }
-    e = hipcub::DeviceScan::ExclusiveSum(tmp, scan_bytes, deg, d_off, (int)(n + 1), s);
+    // offsets: exclusive scan of the degrees (n + 1 entries, the last one 0)
+    e = dev_exclusive_scan_u32(deg, d_off, n + 1, stmp, s);
     if (e != hipSuccess) goto done;
     if (add) k_add_u32<<<blocks_for(n + 1), kThreads, 0, s>>>(d_off, add, n + 1);
     if (m > 0) {
+        const int32_t *sorted = in_alt ? ids_alt : ids;
         if (key_bytes == 4)
             k_gather_adj<int32_t><<<blocks_for(m), kThreads, 0, s>>>(
-                m, ids_out, d_other, (const int32_t *)d_tk, d_w, (int32_t *)d_adj_t + add, d_adj_nbr + add,
+                m, sorted, d_other, (const int32_t *)d_tk, d_w, (int32_t *)d_adj_t + add, d_adj_nbr + add,
                 d_adj_eid + add, d_w ? d_adj_w + add : nullptr, d_pos, add);
         else
             k_gather_adj<int64_t><<<blocks_for(m), kThreads, 0, s>>>(
-                m, ids_out, d_other, (const int64_t *)d_tk, d_w, (int64_t *)d_adj_t + add, d_adj_nbr + add,
+                m, sorted, d_other, (const int64_t *)d_tk, d_w, (int64_t *)d_adj_t + add, d_adj_nbr + add,
                 d_adj_eid + add, d_w ? d_adj_w + add : nullptr, d_pos, add);
     }
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
 done:
     (void)hipStreamSynchronize(s);
-    (void)hipFree(tmp);
-    (void)hipFree(ids_out);
-    (void)hipFree(ids_in);
-    (void)hipFree(keys_out);
+    (void)hipFree(hist);
+    (void)hipFree(ids_alt);
+    (void)hipFree(ids);
+    (void)hipFree(keys_alt);
+    (void)hipFree(keys);
+    (void)hipFree(stmp);
     (void)hipFree(deg);
     return e;
 }

@@ -182,8 +182,18 @@ hipError_t dev_make_keys(int64_t m, const int64_t *d_t, int64_t t_min, int key_b
 hipError_t dev_check_ids(int64_t m, int64_t n, const int32_t *d_src, const int32_t *d_dst, uint32_t *d_bad,
                          hipStream_t s);
 hipError_t dev_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
-hipError_t dev_exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, void *tmp, size_t *tmp_bytes,
-                                  hipStream_t s);
+// own scan and radix sort (tm_sort.hip). Scans: exclusive, in == out allowed,
+// `tmp` holds scan_tmp_elems(n) elements. Radix sort: stable, keys below
+// 2^end_bit, ping-pong between (keys, vals) and the *_alt buffers (*in_alt
+// tells where the result is); hist holds radix_hist_elems(n) entries and
+// scan_tmp scan_tmp_elems(radix_hist_elems(n)).
+int64_t scan_tmp_elems(int64_t n);
+int64_t radix_hist_elems(int64_t n);
+hipError_t dev_exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
+hipError_t dev_exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *tmp, hipStream_t s);
+template <typename K, typename V>
+hipError_t dev_radix_sort_pairs(K *keys, V *vals, K *keys_alt, V *vals_alt, int64_t n, int end_bit, uint32_t *hist,
+                                uint32_t *scan_tmp, hipStream_t s, bool *in_alt);
 
 }  // namespace tmo
 

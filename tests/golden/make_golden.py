@@ -3,7 +3,7 @@
 Calls only the CPU oracle (``oracle/``) on the seeded synthetic inputs; no
 value here comes from the GPU path. Run from the repository root:
 
-    python tests/golden/make_golden.py [wiki] [skew]
+    python tests/golden/make_golden.py [wiki] [skew] [serve]
 """
 from __future__ import annotations
 
@@ -79,10 +79,62 @@ def skew_counts(nthreads: int):
         json.dump(out, f, indent=1)
 
 
+# The served stream's oracle sample: seeded choice of 200 of its 10,000
+# queries; enumerations whose rows fit the test's 1 GiB row pool are stored
+# as the SHA-256 of their sorted rows, larger ones by count only (the server
+# returns such a query's exact count with TM_E_CAPACITY).
+SERVE_SAMPLE_SEED = 5
+SERVE_SAMPLE = 200
+SERVE_POOL_BYTES = 1 << 30
+
+
+def serve_sample_indices(n_queries: int):
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(SERVE_SAMPLE_SEED))
+    return sorted(int(i) for i in rng.choice(n_queries, SERVE_SAMPLE, replace=False))
+
+
+def query_key(q) -> str:
+    """Hash of everything that defines a served query's result."""
+    import hashlib
+    m = q.motif
+    txt = json.dumps([[list(e) for e in m.edges], m.delta, list(m.gaps()), m.pred_edge, m.pred_op,
+                      float(m.pred_theta), q.t_lo, q.t_hi, bool(q.enumerate)])
+    return hashlib.sha256(txt.encode()).hexdigest()[:16]
+
+
+def serve_counts(nthreads: int):
+    g = synth.wiki_graph()
+    og = oracle.OracleGraph.from_graph(g)
+    qs = synth.serve_queries(int(g.t.min()), int(g.t.max()))
+    out = {"source": "oracle/tm_oracle.c via tests/golden/make_golden.py", "generator": synth.GEN_VERSION,
+           "graph": g.name, "graph_hash": synth.content_hash(g), "stream_seed": 4, "stream_queries": len(qs),
+           "sample_seed": SERVE_SAMPLE_SEED, "pool_bytes": SERVE_POOL_BYTES, "queries": []}
+    t_all = time.time()
+    for i in serve_sample_indices(len(qs)):
+        q = qs[i]
+        t0 = time.time()
+        c = oracle.count(og, q.motif, t_lo=q.t_lo, t_hi=q.t_hi, nthreads=nthreads)
+        rec = {"index": i, "key": query_key(q), "l": q.motif.l, "enumerate": bool(q.enumerate), "count": c}
+        if q.enumerate and 8 * q.motif.l * c <= SERVE_POOL_BYTES:
+            rows = oracle.enumerate(og, q.motif, t_lo=q.t_lo, t_hi=q.t_hi, capacity=c)
+            assert rows.shape[0] == c
+            rec["rows_sha256"] = sorted_rows_sha256(rows)
+        rec["oracle_s"] = round(time.time() - t0, 2)
+        out["queries"].append(rec)
+        print(i, q.motif.edges, q.motif.delta, q.enumerate, c, rec["oracle_s"], flush=True)
+    out["oracle_total_s"] = round(time.time() - t_all, 1)
+    out["threads"] = nthreads
+    with open(os.path.join(HERE, "serve_sample.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["wiki", "skew"]
+    which = sys.argv[1:] or ["wiki", "skew", "serve"]
     threads = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
     if "wiki" in which:
         wiki_counts(threads)
     if "skew" in which:
         skew_counts(threads)
+    if "serve" in which:
+        serve_counts(threads)
