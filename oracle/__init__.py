@@ -6,9 +6,9 @@ package. The product path never imports it and shares no code with it.
 Two independent implementations of the problem definition (Sec. 2.1):
 
 * ``count`` / ``enumerate`` call the plain C depth-first search in
-  ``tm_oracle.c`` (Algorithm 1 with the fine-grained gap, attribute, vertex
-  label, temporal anti-edge and root-range constraints of Sec. 2.1 and
-  Sec. 5.4);
+  ``tm_oracle.c`` (Algorithm 1 with the fine-grained gap, edge-attribute
+  predicate, vertex and edge label, temporal anti-edge and root-range
+  constraints of Sec. 2.1 and Sec. 5.4);
 * ``brute.py`` checks every ordered l-tuple of distinct edges against the
   definition literally, for tiny graphs.
 """
@@ -53,13 +53,14 @@ def _load():
         lib.oracle_graph_free.argtypes = [P]
         lib.oracle_count.restype = i32
         lib.oracle_count.argtypes = [P, i32, i32, P, i64, P, i32, i32, ctypes.c_float, i64, i64, i32,
-                                     i32, P, P, P, i32, P, P]
+                                     i32, P, P, P, i32, P, P, P, P, P, i32, P, P]
         lib.oracle_enumerate.restype = i32
         lib.oracle_enumerate.argtypes = [P, i32, i32, P, i64, P, i32, i32, ctypes.c_float, i64, i64,
-                                         i32, P, P, P, P, ctypes.c_uint64, P]
+                                         i32, P, P, P, i32, P, P, P, P, P, P, ctypes.c_uint64, P]
         lib.oracle_graph_set_labels.argtypes = [P, P]
+        lib.oracle_graph_set_edge_labels.argtypes = [P, P]
         lib.oracle_version.restype = i32
-        if lib.oracle_version() != 3:
+        if lib.oracle_version() != 4:
             raise RuntimeError("stale oracle library: rebuild it with oracle.build()")
         _lib = lib
     return _lib
@@ -72,7 +73,7 @@ def _ptr(a: Optional[np.ndarray]):
 class OracleGraph:
     """Holds the time-sorted edge arrays and the per-node in/out id lists."""
 
-    def __init__(self, n: int, src, dst, t, w=None, labels=None):
+    def __init__(self, n: int, src, dst, t, w=None, labels=None, edge_labels=None):
         lib = _load()
         self.src = np.ascontiguousarray(src, dtype=np.int32)
         self.dst = np.ascontiguousarray(dst, dtype=np.int32)
@@ -90,10 +91,16 @@ class OracleGraph:
             if self.labels.shape != (self.n,) or (self.n and self.labels.min() < 0):
                 raise ValueError("labels: one non-negative int32 per node")
             lib.oracle_graph_set_labels(self._h, _ptr(self.labels))
+        self.edge_labels = None
+        if edge_labels is not None:
+            self.edge_labels = np.ascontiguousarray(edge_labels, dtype=np.int32)
+            if self.edge_labels.shape != (self.m,) or (self.m and self.edge_labels.min() < 0):
+                raise ValueError("edge_labels: one non-negative int32 per edge")
+            lib.oracle_graph_set_edge_labels(self._h, _ptr(self.edge_labels))
 
     @classmethod
     def from_graph(cls, g) -> "OracleGraph":
-        return cls(g.n, g.src, g.dst, g.t, g.w, getattr(g, "labels", None))
+        return cls(g.n, g.src, g.dst, g.t, g.w, getattr(g, "labels", None), getattr(g, "edge_labels", None))
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -123,6 +130,20 @@ def _label_args(motif):
     return None if lab is None else np.ascontiguousarray(np.array(lab, dtype=np.int32))
 
 
+def _attr_args(motif):
+    """Extra weight predicates (count, edges, operators, thresholds), upper
+    ends of node label ranges, and edge label ranges (lo, hi per edge)."""
+    preds = getattr(motif, "preds", None) or []
+    pe = np.ascontiguousarray(np.array([p[0] for p in preds], dtype=np.int32)) if preds else None
+    po = np.ascontiguousarray(np.array([p[1] for p in preds], dtype=np.int32)) if preds else None
+    pt = np.ascontiguousarray(np.array([p[2] for p in preds], dtype=np.float32)) if preds else None
+    hi = getattr(motif, "node_label_hi", None)
+    hi = None if hi is None else np.ascontiguousarray(np.array(hi, dtype=np.int32))
+    el = getattr(motif, "edge_labels", None)
+    el = None if el is None else np.ascontiguousarray(np.array(el, dtype=np.int32).reshape(-1))
+    return len(preds), pe, po, pt, hi, el
+
+
 def count(og: OracleGraph, motif, t_lo: int = I64_MIN, t_hi: int = I64_MAX, nthreads: int = 1,
           list_rule: int = 0, with_stats: bool = False):
     """Number of instances. With ``with_stats`` also returns a dict of the
@@ -131,11 +152,13 @@ def count(og: OracleGraph, motif, t_lo: int = I64_MIN, t_hi: int = I64_MAX, nthr
     edges, gaps = _motif_args(motif)
     na, trip, win = _anti_args(motif)
     lab = _label_args(motif)
+    npd, pe, po, pt, lhi, el = _attr_args(motif)
     out = np.zeros(1, np.uint64)
     st = np.zeros(6, np.uint64)
     rc = lib.oracle_count(og._h, motif.l, motif.k, _ptr(edges), int(motif.delta), _ptr(gaps),
                           int(motif.pred_edge), int(motif.pred_op), float(motif.pred_theta),
-                          int(t_lo), int(t_hi), int(list_rule), na, _ptr(trip), _ptr(win), _ptr(lab), int(nthreads),
+                          int(t_lo), int(t_hi), int(list_rule), na, _ptr(trip), _ptr(win), _ptr(lab),
+                          npd, _ptr(pe), _ptr(po), _ptr(pt), _ptr(lhi), _ptr(el), int(nthreads),
                           _ptr(out), _ptr(st))
     if rc != 0:
         raise ValueError("oracle rejected the query")
@@ -152,13 +175,15 @@ def enumerate(og: OracleGraph, motif, t_lo: int = I64_MIN, t_hi: int = I64_MAX,
     edges, gaps = _motif_args(motif)
     na, trip, win = _anti_args(motif)
     lab = _label_args(motif)
+    npd, pe, po, pt, lhi, el = _attr_args(motif)
     n_out = np.zeros(1, np.uint64)
     if capacity is None:
         capacity = count(og, motif, t_lo, t_hi)
     buf = np.zeros((max(capacity, 1), motif.l), np.int64)
     rc = lib.oracle_enumerate(og._h, motif.l, motif.k, _ptr(edges), int(motif.delta), _ptr(gaps),
                               int(motif.pred_edge), int(motif.pred_op), float(motif.pred_theta),
-                              int(t_lo), int(t_hi), na, _ptr(trip), _ptr(win), _ptr(lab), _ptr(buf), int(capacity),
+                              int(t_lo), int(t_hi), na, _ptr(trip), _ptr(win), _ptr(lab),
+                              npd, _ptr(pe), _ptr(po), _ptr(pt), _ptr(lhi), _ptr(el), _ptr(buf), int(capacity),
                               _ptr(n_out))
     if rc != 0:
         raise ValueError("oracle rejected the query")

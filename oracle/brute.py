@@ -4,8 +4,9 @@ TEST INFRASTRUCTURE ONLY. For tiny graphs (m up to a few dozen) this checks
 each condition of the problem definition (Sec. 2.1) directly: strictly
 increasing times, the delta window (inclusive), the fine-grained gaps delta_i,
 the existence of an injective node map phi with phi(a_i)=src(e_i) and
-phi(b_i)=dst(e_i) (isomorphism: a bijection onto the matched nodes), an
-edge-weight predicate, vertex labels, temporal anti-edges (absence of an edge between two
+phi(b_i)=dst(e_i) (isomorphism: a bijection onto the matched nodes),
+edge-weight predicates, vertex and edge labels (single values or ranges),
+temporal anti-edges (absence of an edge between two
 mapped nodes in a closed time range after the attached edge), and the
 root-range filter. It shares nothing with the
 C oracle or the GPU path.
@@ -55,13 +56,24 @@ def is_instance(g, motif, tup, t_lo=I64_MIN, t_hi=I64_MAX) -> bool:
             phi[mnode] = gnode
     if len(set(phi.values())) != len(phi):  # injective
         return False
-    # vertex labels: a motif node with a required label maps to a node carrying it
+    # vertex labels: a motif node with a required label (or label range)
+    # maps to a node whose label is that one (lies in the range)
+    his = getattr(motif, "node_label_hi", None)
     for v, want in enumerate(getattr(motif, "node_labels", None) or []):
-        if want >= 0 and int(g.labels[phi[v]]) != want:
+        if want < 0:
+            continue
+        top = want if his is None else his[v]
+        if not want <= int(g.labels[phi[v]]) <= top:
             return False
-    if motif.pred_edge >= 0:
-        e = tup[motif.pred_edge]
-        if not _pred(motif.pred_op, np.float32(g.w[e]), np.float32(motif.pred_theta)):
+    # edge labels: each constrained motif edge's graph edge carries a label in range
+    for i, (lo, hi) in enumerate(getattr(motif, "edge_labels", None) or []):
+        if lo >= 0 and not lo <= int(g.edge_labels[tup[i]]) <= hi:
+            return False
+    # weight predicates: the single one and any further ones
+    preds = ([(motif.pred_edge, motif.pred_op, motif.pred_theta)] if motif.pred_edge >= 0 else [])
+    preds += list(getattr(motif, "preds", None) or [])
+    for j, op, theta in preds:
+        if not _pred(op, np.float32(g.w[tup[j]]), np.float32(theta)):
             return False
     # temporal anti-edges: no graph edge at all (the tuple's own included) from
     # phi(a) to phi(b) with a time in [t(e_i), t(e_i) + window]

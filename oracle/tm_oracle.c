@@ -13,13 +13,17 @@
  *   - t(e_{i+1}) - t(e_i) <= gap_i for every i (fine-grained delta_i);
  *   - a node map phi with phi(a_i) = src(e_i), phi(b_i) = dst(e_i) exists and
  *     is injective (isomorphism semantics: bijections onto the sub-graph);
- *   - an optional edge-attribute constraint w(e_j) OP theta holds (float32
- *     comparison; label/attribute constraints, Sec. 5.4.1);
+ *   - every edge-attribute predicate w(e_j) OP theta holds (float32
+ *     comparisons; several may name one edge; attribute constraints, Sec. 2.1
+ *     and Sec. 5.4.1);
  *   - the root edge's time lies in [t_lo, t_hi] (a root-range filter; later
  *     edges may exceed t_hi by up to delta, so counts add over root ranges);
- *   - every motif node v with a required label L(v) >= 0 maps to a graph node
- *     carrying that label (vertex labels, Sec. 5.4.1: checked when the node
- *     is newly matched);
+ *   - every motif node v with a required label range [lo(v), hi(v)] (lo >= 0)
+ *     maps to a graph node whose label lies in it (vertex labels, Sec. 5.4.1:
+ *     checked when the node is newly matched; one label is lo == hi);
+ *   - every motif edge i with a required label range [elo(i), ehi(i)] is
+ *     matched by a graph edge whose label lies in it (edge labels, Sec. 5.4.1:
+ *     checked when the edge is matched);
  *   - for every temporal anti-edge (a, b, attached to motif edge i, delta_ab)
  *     the graph has no edge phi(a) -> phi(b) with time in the closed range
  *     [t(e_i), t(e_i) + delta_ab] (absence of an edge, Sec. 2.1), whether or
@@ -64,6 +68,7 @@
 #define OR_MAXL 8
 #define OR_MAXK 8
 #define OR_MAXA 4
+#define OR_MAXP 9 /* weight predicates: the single one plus up to 8 more */
 
 enum { OR_GE = 0, OR_GT = 1, OR_LE = 2, OR_LT = 3 };
 
@@ -73,6 +78,7 @@ typedef struct {
     const int64_t *t;
     const float *w;
     const int32_t *lab;        /* node labels (n entries, >= 0) or NULL */
+    const int32_t *elab;       /* edge labels (m entries, >= 0) or NULL */
     int64_t *out_off, *in_off; /* n+1 each */
     int64_t *out_ids, *in_ids; /* edge ids per node, ascending id order */
 } or_graph;
@@ -82,14 +88,17 @@ typedef struct {
     int a[OR_MAXL], b[OR_MAXL];
     int64_t delta;
     int64_t gap[OR_MAXL];
-    int pred_edge, pred_op;
-    float theta;
+    int np; /* weight predicates: edge, operator, threshold */
+    int p_edge[OR_MAXP], p_op[OR_MAXP];
+    float p_th[OR_MAXP];
+    int pred_level[OR_MAXL]; /* 1: level i has at least one predicate */
     int64_t t_lo, t_hi;
     int list_rule;
     int n_anti;
     int anti_a[OR_MAXA], anti_b[OR_MAXA], anti_at[OR_MAXA], anti_lvl[OR_MAXA];
     int64_t anti_delta[OR_MAXA];
-    int32_t nlab[OR_MAXK]; /* required label per motif node, -1 = any */
+    int32_t nlab[OR_MAXK], nlab_hi[OR_MAXK]; /* required label range per motif node, lo -1 = any */
+    int32_t elab_lo[OR_MAXL], elab_hi[OR_MAXL]; /* required label range per motif edge, lo -1 = any */
 } or_query;
 
 typedef struct {
@@ -141,13 +150,27 @@ static int64_t upper_bound_all(const int64_t *t, int64_t lo, int64_t hi, int64_t
     return lo;
 }
 
-static int pred_ok(const or_query *q, float w) {
-    switch (q->pred_op) {
-    case OR_GE: return w >= q->theta;
-    case OR_GT: return w > q->theta;
-    case OR_LE: return w <= q->theta;
-    default: return w < q->theta;
+static int cmp_ok(int op, float w, float th) {
+    switch (op) {
+    case OR_GE: return w >= th;
+    case OR_GT: return w > th;
+    case OR_LE: return w <= th;
+    default: return w < th;
     }
+}
+
+/* Every weight predicate on motif edge i holds for weight w. */
+static int preds_ok(const or_query *q, int i, float w) {
+    for (int j = 0; j < q->np; j++)
+        if (q->p_edge[j] == i && !cmp_ok(q->p_op[j], w, q->p_th[j])) return 0;
+    return 1;
+}
+
+/* Edge labels (Sec. 5.4.1): graph edge e matched to motif edge i carries a
+ * label in the edge's required range. */
+static int elabel_ok(const or_query *q, const int32_t *elab, int i, int64_t e) {
+    if (q->elab_lo[i] < 0) return 1;
+    return elab[e] >= q->elab_lo[i] && elab[e] <= q->elab_hi[i];
 }
 
 /* UpdateDataStructures: bind both endpoints of motif edge i to graph edge e. */
@@ -195,11 +218,19 @@ static int needs_labels(const or_query *q) {
     return 0;
 }
 
+static int needs_edge_labels(const or_query *q) {
+    for (int i = 0; i < q->l; i++)
+        if (q->elab_lo[i] >= 0) return 1;
+    return 0;
+}
+
 /* Vertex labels (Sec. 5.4.1): a newly matched graph node carries the label
  * its motif node requires. Nodes bound earlier were checked then. */
 static int label_ok(const or_ctx *c, int v, int64_t gnode) {
-    const int32_t want = c->q->nlab[v];
-    return want < 0 || c->g->lab[gnode] == want;
+    const int32_t lo = c->q->nlab[v];
+    if (lo < 0) return 1;
+    const int32_t x = c->g->lab[gnode];
+    return x >= lo && x <= c->q->nlab_hi[v];
 }
 
 /* Absence check of anti-edge j once its nodes are bound and its attach edge
@@ -278,12 +309,13 @@ static void dfs(or_ctx *c, int i, int64_t t_prev) {
     for (int64_t p = lo; p < end; p++) {
         int64_t e = ids ? ids[p] : p;
         c->st.visits++;
-        if (i == q->pred_edge) c->st.pred_visits++;
+        if (q->pred_level[i]) c->st.pred_visits++;
         if (g->t[e] > hi) break;
         if (!struct_ok(c, e, ug, vg)) continue;
         if (ug < 0 && !label_ok(c, q->a[i], g->src[e])) continue;
         if (vg < 0 && !label_ok(c, q->b[i], g->dst[e])) continue;
-        if (i == q->pred_edge && !pred_ok(q, g->w[e])) continue;
+        if (q->pred_level[i] && !preds_ok(q, i, g->w[e])) continue;
+        if (!elabel_ok(q, g->elab, i, e)) continue;
         /* NextLevel: bookkeeping and push, then descend; Backtrack on return */
         update_ds(c, i, e);
         c->estack[i] = e;
@@ -296,10 +328,11 @@ static void run_root(or_ctx *c, int64_t r) {
     const or_graph *g = c->g;
     const or_query *q = c->q;
     c->st.roots++;
-    if (q->pred_edge == 0) c->st.pred_visits++;
+    if (q->pred_level[0]) c->st.pred_visits++;
     if (g->src[r] == g->dst[r]) return; /* both motif nodes new: must differ */
     if (!label_ok(c, q->a[0], g->src[r]) || !label_ok(c, q->b[0], g->dst[r])) return;
-    if (q->pred_edge == 0 && !pred_ok(q, g->w[r])) return;
+    if (q->pred_level[0] && !preds_ok(q, 0, g->w[r])) return;
+    if (!elabel_ok(q, g->elab, 0, r)) return;
     update_ds(c, 0, r);
     c->estack[0] = r;
     c->tprime = sat_add(g->t[r], q->delta);
@@ -338,9 +371,20 @@ void oracle_graph_free(void *h) {
     free(g);
 }
 
+/* Attribute constraints beyond the single predicate: extra weight predicates,
+ * upper ends of node label ranges, edge label ranges (each may be NULL). */
+typedef struct {
+    int n_pred;
+    const int32_t *pred_edge, *pred_op;
+    const float *pred_theta;
+    const int32_t *node_label_hi; /* k entries */
+    const int32_t *edge_label;    /* 2*l entries: lo, hi per motif edge */
+} or_attrs;
+
 static int make_query(or_query *q, int l, int k, const int32_t *edges, int64_t delta, const int64_t *gaps,
                       int pred_edge, int pred_op, float theta, int64_t t_lo, int64_t t_hi, int list_rule,
-                      int n_anti, const int32_t *anti, const int64_t *anti_delta, const int32_t *node_label) {
+                      int n_anti, const int32_t *anti, const int64_t *anti_delta, const int32_t *node_label,
+                      const or_attrs *at) {
     if (l < 1 || l > OR_MAXL || k < 2 || k > OR_MAXK || delta < 0) return 1;
     memset(q, 0, sizeof(*q));
     q->l = l; q->k = k; q->delta = delta;
@@ -352,13 +396,36 @@ static int make_query(or_query *q, int l, int k, const int32_t *edges, int64_t d
         q->gap[i] = gaps ? gaps[i] : INT64_MAX;
         if (q->gap[i] < 0) return 1;
     }
-    q->pred_edge = pred_edge; q->pred_op = pred_op; q->theta = theta;
+    q->np = 0;
+    if (pred_edge >= 0) {
+        if (pred_edge >= l || pred_op < OR_GE || pred_op > OR_LT) return 1;
+        q->p_edge[0] = pred_edge; q->p_op[0] = pred_op; q->p_th[0] = theta; q->np = 1;
+    }
+    if (at && at->n_pred) {
+        if (at->n_pred < 0 || at->n_pred > OR_MAXP - 1 || !at->pred_edge || !at->pred_op || !at->pred_theta) return 1;
+        for (int j = 0; j < at->n_pred; j++) {
+            if (at->pred_edge[j] < 0 || at->pred_edge[j] >= l || at->pred_op[j] < OR_GE || at->pred_op[j] > OR_LT)
+                return 1;
+            q->p_edge[q->np] = at->pred_edge[j]; q->p_op[q->np] = at->pred_op[j]; q->p_th[q->np] = at->pred_theta[j];
+            q->np++;
+        }
+    }
+    for (int j = 0; j < q->np; j++) q->pred_level[q->p_edge[j]] = 1;
     q->t_lo = t_lo; q->t_hi = t_hi; q->list_rule = list_rule;
-    for (int v = 0; v < OR_MAXK; v++) q->nlab[v] = -1;
+    for (int v = 0; v < OR_MAXK; v++) q->nlab[v] = q->nlab_hi[v] = -1;
     if (node_label)
         for (int v = 0; v < k; v++) {
             if (node_label[v] < -1) return 1;
             q->nlab[v] = node_label[v];
+            q->nlab_hi[v] = (at && at->node_label_hi) ? at->node_label_hi[v] : node_label[v];
+            if (q->nlab[v] >= 0 && q->nlab_hi[v] < q->nlab[v]) return 1;
+        }
+    for (int i = 0; i < OR_MAXL; i++) q->elab_lo[i] = q->elab_hi[i] = -1;
+    if (at && at->edge_label)
+        for (int i = 0; i < l; i++) {
+            const int32_t lo = at->edge_label[2 * i], hi = at->edge_label[2 * i + 1];
+            if (lo < -1 || (lo >= 0 && hi < lo)) return 1;
+            q->elab_lo[i] = lo; q->elab_hi[i] = hi;
         }
     /* anti-edges: (a, b, attach edge) triples; checked at the level where the
      * attach edge is matched and both nodes are bound */
@@ -432,14 +499,18 @@ static void *worker_main(void *arg) {
 int oracle_count(void *gh, int l, int k, const int32_t *edges, int64_t delta, const int64_t *gaps,
                  int pred_edge, int pred_op, float theta, int64_t t_lo, int64_t t_hi, int list_rule,
                  int n_anti, const int32_t *anti, const int64_t *anti_delta, const int32_t *node_label,
+                 int n_pred, const int32_t *p_edge, const int32_t *p_op, const float *p_theta,
+                 const int32_t *node_label_hi, const int32_t *edge_label,
                  int nthreads, uint64_t *count_out, uint64_t *stats_out) {
     const or_graph *g = (const or_graph *)gh;
     or_query q;
+    const or_attrs at = {n_pred, p_edge, p_op, p_theta, node_label_hi, edge_label};
     if (make_query(&q, l, k, edges, delta, gaps, pred_edge, pred_op, theta, t_lo, t_hi, list_rule, n_anti, anti,
-                   anti_delta, node_label))
+                   anti_delta, node_label, &at))
         return 1;
     if (needs_labels(&q) && !g->lab) return 1; /* labels required, graph has none */
-    if (pred_edge >= l || (pred_edge >= 0 && !g->w)) return 1;
+    if (needs_edge_labels(&q) && !g->elab) return 1;
+    if (q.np > 0 && !g->w) return 1;
     int64_t r0 = first_root(g, t_lo), r1 = end_root(g, t_hi);
     if (r1 < r0) r1 = r0;
     if (nthreads < 1) nthreads = 1;
@@ -477,14 +548,18 @@ int oracle_count(void *gh, int l, int k, const int32_t *edges, int64_t delta, co
 int oracle_enumerate(void *gh, int l, int k, const int32_t *edges, int64_t delta, const int64_t *gaps,
                      int pred_edge, int pred_op, float theta, int64_t t_lo, int64_t t_hi,
                      int n_anti, const int32_t *anti, const int64_t *anti_delta, const int32_t *node_label,
+                     int n_pred, const int32_t *p_edge, const int32_t *p_op, const float *p_theta,
+                     const int32_t *node_label_hi, const int32_t *edge_label,
                      int64_t *out, uint64_t capacity, uint64_t *n_out) {
     const or_graph *g = (const or_graph *)gh;
     or_query q;
+    const or_attrs at = {n_pred, p_edge, p_op, p_theta, node_label_hi, edge_label};
     if (make_query(&q, l, k, edges, delta, gaps, pred_edge, pred_op, theta, t_lo, t_hi, 0, n_anti, anti,
-                   anti_delta, node_label))
+                   anti_delta, node_label, &at))
         return 1;
     if (needs_labels(&q) && !g->lab) return 1; /* labels required, graph has none */
-    if (pred_edge >= l || (pred_edge >= 0 && !g->w)) return 1;
+    if (needs_edge_labels(&q) && !g->elab) return 1;
+    if (q.np > 0 && !g->w) return 1;
     int64_t r0 = first_root(g, t_lo), r1 = end_root(g, t_hi);
     or_ctx c;
     ctx_init(&c, g, &q);
@@ -498,4 +573,7 @@ int oracle_enumerate(void *gh, int l, int k, const int32_t *edges, int64_t delta
 /* Attach node labels (n entries, >= 0; the caller keeps them alive). */
 void oracle_graph_set_labels(void *gh, const int32_t *lab) { ((or_graph *)gh)->lab = lab; }
 
-int oracle_version(void) { return 3; }
+/* Attach edge labels (m entries in edge id order, >= 0; kept alive by the caller). */
+void oracle_graph_set_edge_labels(void *gh, const int32_t *elab) { ((or_graph *)gh)->elab = elab; }
+
+int oracle_version(void) { return 4; }

@@ -52,6 +52,7 @@ class TemporalGraph:
     w: Optional[np.ndarray] = None  # float32[m]
     name: str = ""
     labels: Optional[np.ndarray] = None  # int32[n], node labels >= 0
+    edge_labels: Optional[np.ndarray] = None  # int32[m], edge labels >= 0 (edge id order)
 
     @property
     def m(self) -> int:
@@ -66,7 +67,12 @@ class Motif:
     ``pred_edge >= 0``, requires ``w[e_pred_edge] OP theta`` in float32.
     ``anti`` lists temporal anti-edges as (a, b, i, window): no graph edge
     phi(a) -> phi(b) may have a time in [t(e_i), t(e_i) + window].
-    ``node_labels`` gives each motif node's required vertex label (-1 = any).
+    ``node_labels`` gives each motif node's required vertex label (-1 = any);
+    with ``node_label_hi`` the label must lie in [node_labels[v],
+    node_label_hi[v]] instead. ``preds`` adds weight predicates (edge, op,
+    theta) beyond the one above; all must hold. ``edge_labels`` gives each
+    motif edge an inclusive range (lo, hi) its graph edge's label must lie
+    in (lo = -1: any).
     """
 
     edges: List[Tuple[int, int]]
@@ -77,6 +83,9 @@ class Motif:
     pred_theta: float = 0.0
     anti: Optional[List[Tuple[int, int, int, int]]] = None
     node_labels: Optional[List[int]] = None
+    node_label_hi: Optional[List[int]] = None
+    preds: Optional[List[Tuple[int, int, float]]] = None
+    edge_labels: Optional[List[Tuple[int, int]]] = None
 
     @property
     def l(self) -> int:
@@ -365,6 +374,9 @@ def content_hash(g: TemporalGraph) -> str:
     if g.labels is not None:
         h.update(b"labels")
         h.update(np.ascontiguousarray(g.labels).tobytes())
+    if g.edge_labels is not None:
+        h.update(b"edge_labels")
+        h.update(np.ascontiguousarray(g.edge_labels).tobytes())
     return h.hexdigest()[:16]
 
 
@@ -377,3 +389,14 @@ def node_labels(seed: int, n: int, n_labels: int) -> np.ndarray:
 
 def with_labels(g: TemporalGraph, labels) -> TemporalGraph:
     return dataclasses.replace(g, labels=np.ascontiguousarray(labels, dtype=np.int32))
+
+
+def edge_labels(seed: int, m: int, n_labels: int) -> np.ndarray:
+    """Uniform random edge labels 0..n_labels-1 (random edge features, as the
+    paper attaches to its non-attributed graphs, Sec. 6)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, n_labels, m).astype(np.int32)
+
+
+def with_edge_labels(g: TemporalGraph, labels) -> TemporalGraph:
+    return dataclasses.replace(g, edge_labels=np.ascontiguousarray(labels, dtype=np.int32))
