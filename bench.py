@@ -51,23 +51,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def method_bytes(st: dict, l: int, n_enum: int = 0) -> int:
-    """Byte model of the method's search for one query: each root reads src,
-    dst and t (16 B); each window reads two offsets (8 B) and one 8 B time per
-    binary-search probe (ceil(log2(L+1)) probes); each candidate visit reads
-    t and the neighbour (12 B) plus the weight (4 B) at the predicate level;
-    each enumerated instance writes l int64 ids."""
-    return (16 * st["roots"] + 8 * st["windows"] + 8 * st["probes"] + 12 * st["visits"]
+def method_bytes(st: dict, l: int, n_enum: int = 0, tb: int = 8) -> int:
+    """Byte model of the method's search for one query, with timestamps of
+    ``tb`` bytes (8 = the int64 times of the model as stated; the library
+    stores times relative to the minimum, 4 bytes wide when the span allows):
+    each root reads src, dst and t (8 + tb B); each window reads two offsets
+    (8 B) and one time per binary-search probe (ceil(log2(L+1)) probes); each
+    candidate visit reads t and the neighbour (4 + tb B) plus the weight (4 B)
+    at a predicate level; each enumerated instance writes l int64 ids."""
+    return ((8 + tb) * st["roots"] + 8 * st["windows"] + tb * st["probes"] + (4 + tb) * st["visits"]
             + 4 * st["pred_visits"] + 8 * l * n_enum)
 
 
-def algorithmic_bytes(st: dict, l: int, n_enum: int = 0) -> int:
+def algorithmic_bytes(st: dict, l: int, n_enum: int = 0, tb: int = 8) -> int:
     """Bytes the counting kernels' algorithm reads: the method's search, except
     that last-level windows counted in closed form read, instead of their
-    candidates (12 B each), the entries their binary searches probe (a
-    neighbour and a time, 12 B each)."""
-    return (method_bytes(st, l, n_enum) - 12 * st.get("leaf_counted_visits", 0)
-            + 12 * st.get("leaf_count_reads", 0))
+    candidates (4 + tb B each), the entries their binary searches probe (a
+    neighbour and a time, 4 + tb B each)."""
+    return (method_bytes(st, l, n_enum, tb) - (4 + tb) * st.get("leaf_counted_visits", 0)
+            + (4 + tb) * st.get("leaf_count_reads", 0))
 
 
 class fixed_setting:
@@ -106,6 +108,18 @@ def time_launches(ctx, fn, steps, warmup, launches_per_call):
     return statistics.mean(kms) / launches_per_call, (time.perf_counter() - t0) / steps * 1e3
 
 
+def calib_copy(dev):
+    """A device copy of 1 GiB: a kernel of known size that scales HBM byte
+    counters to bytes."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"read": src.numel() * 4, "write": dst.numel() * 4}
+
+
 def roofline_entry(kernel, byte_model, bytes_per_launch, launch_ms, traffic=None):
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -113,10 +127,12 @@ def roofline_entry(kernel, byte_model, bytes_per_launch, launch_ms, traffic=None
             "bytes_per_launch": bytes_per_launch, "avg_launch_ms": launch_ms}
 
 
-METHOD_MODEL = ("method (every window searched, every candidate visited): 16 B per root + per window 8 B + "
-                "8 B per binary-search probe + 12 B per candidate visit + 4 B per predicate visit")
-CLOSED_MODEL = ("closed-form counting kernel: the method's bytes, except that each last-level window counted in "
-                "closed form reads the entries its searches probe (12 B each) instead of its candidates")
+METHOD_MODEL = ("method (every window searched, every candidate visited) at the stored timestamp width tb: "
+                "(8 + tb) B per root + per window 8 B + tb B per binary-search probe + (4 + tb) B per candidate "
+                "visit + 4 B per predicate visit")
+CLOSED_MODEL = ("closed-form counting kernel at the stored timestamp width tb: the method's bytes, except that each "
+                "last-level window counted in closed form reads the entries its searches probe ((4 + tb) B each) "
+                "instead of its candidates")
 
 
 def kernel_source_hash(motifs) -> str:
@@ -263,26 +279,29 @@ def bench_constraints(ctx, dg, args, stream):
 
 def bench_tail(ctx, handles, dg, stream, label):
     """Load balance over time of one batched launch, sampled every 20 us from
-    a side stream (TM_PARAM_TRACE_US), with splitting off and on: when the
-    root-chunk queue drained and how long wavefronts kept working after it
-    (the tail that the paper's relaunch-based redistribution targets)."""
+    a side stream (TM_PARAM_TRACE_US), with splitting off, on, and on with
+    the handoff of unstarted roots: when the root-chunk queue drained and how
+    long wavefronts kept working after it (the tail that the paper's
+    redistribution targets)."""
     import torch
     from paper_2310_02800_amd import _native as N
     from paper_2310_02800_amd import api
     out = {}
-    old = {p: ctx.get_param(p) for p in (N.TM_PARAM_SPLIT, N.TM_PARAM_AUTOTUNE, N.TM_PARAM_TRACE_US)}
+    old = {p: ctx.get_param(p) for p in (N.TM_PARAM_SPLIT, N.TM_PARAM_AUTOTUNE, N.TM_PARAM_TRACE_US,
+                                         N.TM_PARAM_ROOT_HANDOFF)}
     try:
         ctx.set_param(N.TM_PARAM_AUTOTUNE, 0)
-        for split in (0, 1):
+        for name, split, handoff in (("no_split", 0, 0), ("split", 1, 0), ("split_handoff", 1, 1)):
             ctx.set_param(N.TM_PARAM_SPLIT, split)
+            ctx.set_param(N.TM_PARAM_ROOT_HANDOFF, handoff)
             ctx.set_param(N.TM_PARAM_TRACE_US, 0)
             ctx.count_batch(dg, handles, stream=stream)  # warm
             ctx.set_param(N.TM_PARAM_TRACE_US, 20)
             ctx.count_batch(dg, handles, stream=stream)
             torch.cuda.synchronize()
             summ = api.tail_summary(ctx.last_trace())
-            out["split" if split else "no_split"] = summ
-            log(f"tail {label} split={split}: {summ}")
+            out[name] = summ
+            log(f"tail {label} {name}: {summ}")
     finally:
         for p, v in old.items():
             ctx.set_param(p, v)
@@ -299,6 +318,41 @@ def bench_tail_skew(ctx, args, stream):
     res = bench_tail(ctx, [ctx.compile(synth.skew_query())], dg, stream, "skew")
     res["workload"] = "heavy-skew graph n=1e7 m=5e7, 5-edge 4-node motif, gaps <= 600 s, delta 3600 s"
     return res
+
+
+def bench_enum_large(ctx, dg, args, stream):
+    """A large enumeration: the 3-edge out-star at delta 3600 s on the
+    wiki-shaped graph (about 7.2e7 rows of three int64 edge ids) into one
+    device buffer sized by the counting pass. Times the whole call (counting
+    pass, prefix sum of the chunk counts, writing pass) and reports rows/s
+    and the rows' bytes written per second (8 l bytes per row)."""
+    import torch
+    from paper_2310_02800_amd import synth
+    mot = synth.Motif(list(synth.OUT_STAR3), 3600)
+    h = ctx.compile(mot)
+    _, n = ctx.enumerate_into(dg, h, 0, 0, stream=stream)  # the counting pass alone gives the size
+    out = torch.empty((n, mot.l), dtype=torch.int64, device=f"cuda:{ctx.device}")
+    ptr = out.data_ptr()
+    for _ in range(max(args.warmup, 1)):
+        st, got = ctx.enumerate_into(dg, h, ptr, n, stream=stream)
+        assert got == n
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, got = ctx.enumerate_into(dg, h, ptr, n, stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    kms, launches = ctx.last_kernel_ms()
+    # every row holds distinct edge ids in time order (a cheap validity check
+    # of the whole buffer on the device)
+    ok = bool(((out[:, 0] < out[:, 1]) & (out[:, 1] < out[:, 2])).all().item())
+    assert ok, "enumerated rows out of time order"
+    del out
+    torch.cuda.empty_cache()
+    log(f"enum_large: {n} rows in {dt * 1e3:.2f} ms")
+    return {"workload": "wiki-shaped graph, 3-edge out-star, delta 3600 s: every instance written as l int64 edge ids",
+            "rows": n, "ms": dt * 1e3, "kernel_ms_both_passes": kms, "launches": launches,
+            "rows_per_s": n / dt, "row_bytes_per_s": 8 * mot.l * n / dt}
 
 
 def rows_checksum(rows):
@@ -382,7 +436,7 @@ def bench_serve(ctx, dg, g, args):
             done = max(done, a) + sv
             lat_plain.append(done - a)
 
-        def serve(arr_s):
+        def serve(arr_s, nq):
             srv = api.Server(ctx, dg, stream_slots=args.serve_slots, max_batch=args.serve_batch,
                              enum_pool_bytes=pool_bytes, tier=1, work_budget=budget)
             res = {}
@@ -391,7 +445,7 @@ def bench_serve(ctx, dg, g, args):
                 t_base = time.monotonic_ns() + 20_000_000
 
                 def producer():
-                    for i, q in enumerate(qs):
+                    for i, q in enumerate(qs[:nq]):
                         due = t_base + int(arr_s[i] * 1e9)
                         while True:
                             now = time.monotonic_ns()
@@ -405,35 +459,38 @@ def bench_serve(ctx, dg, g, args):
                 th.start()
                 t_last = time.perf_counter()
                 deadline = time.perf_counter() + 60 + 3 * (float(arr_s[-1]) + float(svc.sum()))
-                while len(res) < n:
+                while len(res) < nq:
                     if time.perf_counter() > deadline:
-                        raise RuntimeError(f"server returned {len(res)} of {n} results before the deadline")
+                        raise RuntimeError(f"server returned {len(res)} of {nq} results before the deadline")
                     for r in srv.poll(256, timeout_ms=100):
                         rows = srv.rows(r) if r["rows"] else None
                         res[r["tag"]] = (r, rows_checksum(rows))  # 0 for no rows, as in the plain pass
                         srv.release(r["ticket"])
                     if time.perf_counter() - t_last > 10:
                         t_last = time.perf_counter()
-                        log(f"serve: {len(res)}/{n} results")
+                        log(f"serve: {len(res)}/{nq} results")
                 th.join()
             finally:
                 srv.stop()
             t0 = min(sched.values())
             t1 = max(r["t_done_ns"] for r, _ in res.values())
-            lat = np.array([(res[i][0]["t_done_ns"] - sched[i]) / 1e9 for i in range(n)])
+            lat = np.array([(res[i][0]["t_done_ns"] - sched[i]) / 1e9 for i in range(nq)])
             return res, lat, (t1 - t0) / 1e9
 
         # load the batched kernels the server launches before anything is timed
         ctx.count_batch(dg, handles[:2], ranges=[(qs[0].t_lo, qs[0].t_lo), (qs[1].t_lo, qs[1].t_lo)])
         torch.cuda.synchronize()
-        log(f"serve: served at {rate:.1f} queries/s")
-        res, lat_served, span_s = serve(arrivals)
+        n_rate = min(n, args.serve_rate_queries) if args.serve_rate_queries > 0 else n
+        log(f"serve: served at {rate:.1f} queries/s ({n_rate} queries)")
+        res, lat_served, span_s = serve(arrivals[:n_rate], n_rate)
         log("serve: served capacity (all submitted at once)")
-        res_f, _, span_f = serve(np.zeros(n))
+        res_f, _, span_f = serve(np.zeros(n), n)
         # agreement: every query that both forms finished
         both, bad = 0, []
         for i in range(n):
             for form, rr in (("rate", res), ("flood", res_f)):
+                if i not in rr:
+                    continue
                 r, chk = rr[i]
                 if r["status"] == plain[i][0] and r["status"] in (N.TM_OK, N.TM_E_CAPACITY):
                     both += 1
@@ -444,25 +501,50 @@ def bench_serve(ctx, dg, g, args):
             log("serve: MISMATCH", b)
         agree = not bad
         assert agree, f"served and plain results differ on {len(bad)} results"
-        ok = [i for i in range(n) if res[i][0]["status"] == N.TM_OK]
+        # the oracle's results for a seeded sample of the stream (written by
+        # tests/golden/make_golden.py, which calls only the oracle): compare
+        # every served count of the sample with them
+        oracle_checked, oracle_bad = 0, []
+        gold_path = os.path.join(ROOT, "tests", "golden", "serve_sample.json")
+        if os.path.exists(gold_path) and n == len(synth.serve_queries(t_min, t_max)):
+            with open(gold_path) as f:
+                gold = json.load(f)
+            if gold.get("graph_hash") == synth.content_hash(g) and gold.get("generator") == synth.GEN_VERSION:
+                for rec in gold["queries"]:
+                    i = rec["index"]
+                    for rr in (res, res_f):
+                        if i in rr and rr[i][0]["status"] in (N.TM_OK, N.TM_E_CAPACITY):
+                            oracle_checked += 1
+                            if rr[i][0]["count"] != rec["count"]:
+                                oracle_bad.append(i)
+        assert not oracle_bad, f"served counts differ from the oracle's on queries {oracle_bad[:10]}"
+        ok = [i for i in range(n_rate) if res[i][0]["status"] == N.TM_OK]
         inst = sum(res[i][0]["count"] for i in ok)
+        ok_f = [i for i in range(n) if res_f[i][0]["status"] == N.TM_OK]
+        inst_f = sum(res_f[i][0]["count"] for i in ok_f)
         pct = lambda a, p: 1e3 * float(np.percentile(a, p))
         return {
-            "workload": f"first {n} queries of the 10,000-query stream (seed 4) on the wiki-shaped graph; "
+            "workload": f"{n} queries of the 10,000-query stream (seed 4) on the wiki-shaped graph; "
                         "motifs with 3-6 edges and 3-5 nodes, delta log-uniform in [600, 86400], root range "
                         "1-100% of the span, 10% enumerations",
             "queries": n, "work_budget_steps": budget,
             "cancelled": {"plain": sum(1 for p in plain if p[0] == N.TM_E_CANCELLED),
-                          "served": sum(1 for r, _ in res.values() if r["status"] == N.TM_E_CANCELLED)},
+                          "served": sum(1 for r, _ in list(res.values()) + list(res_f.values())
+                                        if r["status"] == N.TM_E_CANCELLED)},
             "over_pool": sum(1 for p in plain if p[0] == N.TM_E_CAPACITY),
             "plain": {"capacity_qps": cap_plain, "service_ms": {"p50": pct(svc, 50), "p99": pct(svc, 99)},
-                      "latency_ms_at_rate": {"p50": pct(lat_plain, 50), "p99": pct(lat_plain, 99)},
+                      # one first-in-first-out worker at the served arrival times: the measured service
+                      # times replayed (no second run)
+                      "fifo_replay_latency_ms_at_rate": {"p50": pct(lat_plain[:n_rate], 50),
+                                                         "p99": pct(lat_plain[:n_rate], 99)},
                       "instances_per_s": sum(p[1] for p in plain if p[0] == N.TM_OK) / svc.sum()},
-            "served": {"rate_qps": rate, "throughput_qps": len(ok) / span_s, "instances_per_s": inst / span_s,
+            "served": {"rate_qps": rate, "rate_queries": n_rate, "throughput_qps": len(ok) / span_s,
+                       "instances_per_s_at_rate": inst / span_s,
                        "latency_ms": {"p50": pct(lat_served, 50), "p99": pct(lat_served, 99)},
-                       "capacity_qps": n / span_f, "slots": args.serve_slots, "max_batch": args.serve_batch},
+                       "capacity_qps": n / span_f, "instances_per_s_at_capacity": inst_f / span_f,
+                       "slots": args.serve_slots, "max_batch": args.serve_batch},
             "capacity_vs_plain": (n / span_f) / cap_plain,
-            "results_compared": both, "agree": agree,
+            "results_compared": both, "agree": agree, "oracle_checked": oracle_checked,
         }
     finally:
         for p, v in old.items():
@@ -498,11 +580,18 @@ def main():
                     help="also sample the load balance on the heavy-skew graph (generates 50M edges)")
     ap.add_argument("--constraints-only", action="store_true",
                     help="run only the constraints section and print its JSON (for kernel traces of it)")
+    ap.add_argument("--no-enum-large", action="store_true", help="skip the large enumeration (7.2e7 rows)")
     ap.add_argument("--no-constraints", action="store_true",
                     help="skip the 4-cycle with added constraints (gaps, anti-edge)")
-    ap.add_argument("--serve-queries", type=int, default=500,
+    ap.add_argument("--serve-queries", type=int, default=10_000,
                     help="queries of the served stream to run (0 = skip; the full stream has 10,000)")
-    ap.add_argument("--serve-budget", type=int, default=1 << 31, help="work budget per served query (steps)")
+    ap.add_argument("--serve-rate-queries", type=int, default=0,
+                    help="queries of the stream served at the Poisson rate for latency (0 = all of them)")
+    ap.add_argument("--serve-only", action="store_true", help="run only the served stream and print its JSON")
+    ap.add_argument("--query-only", type=int, default=None,
+                    help="time only headline query i (0..5: 3-cycle, 4-cycle, out-star at 3600 s, then at 86400 s) "
+                         "as plain counts and print its JSON (for kernel traces and counters of one query)")
+    ap.add_argument("--serve-budget", type=int, default=0, help="work budget per served query (steps, 0 = none)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=64)
     ap.add_argument("--serve-pool-gib", type=float, default=8.0)
@@ -560,6 +649,27 @@ def main():
         print(json.dumps({"constraints": bench_constraints(ctx, dg, args, stream), "tuned_from": tuned_from}),
               flush=True)
         return
+    if args.serve_only:
+        print(json.dumps({"serve": bench_serve(ctx, dg, g, args)}), flush=True)
+        return
+    if args.query_only is not None:
+        mot = motifs[args.query_only]
+        h = ctx.compile(mot)
+        c = ctx.count(dg, h, stream=stream)  # compiles, tunes (autotuning on) and loads
+        st = ctx.work_stats(dg, h, stream=stream, leaf=True)
+        tb = dg.info()["key_bytes"]
+        ms, wall = time_launches(ctx, lambda: ctx.count(dg, h, stream=stream), args.steps, args.warmup, 1)
+        setting = ctx.last_launch_full()
+        calib = calib_copy(dev) if args.calib_copy else None
+        print(json.dumps({"query": {"edges": mot.edges, "delta": mot.delta}, "count": c, "kernel_ms": ms,
+                          "calib_copy_bytes": calib,
+                          "wall_ms": wall, "work": st, "timestamp_bytes": tb,
+                          "algorithmic_bytes": algorithmic_bytes(st, mot.l, tb=tb),
+                          "method_bytes": method_bytes(st, mot.l, tb=tb),
+                          "launch": {"root_chunk": setting[0], "split": setting[1], "split_min": setting[3],
+                                     "leaf_min": setting[4], "tuned": setting[2]}, "tuned_from": tuned_from}),
+              flush=True)
+        return
 
     t0 = time.perf_counter()
     handles = [ctx.compile(m) for m in motifs]
@@ -575,8 +685,11 @@ def main():
     counts = [s["matches"] for s in stats]
     assert counts == counts_b, (counts, counts_b)
     total_instances = sum(counts)
-    bytes_per_step = sum(algorithmic_bytes(s, m.l) for s, m in zip(stats, motifs))
-    method_bytes_per_step = sum(method_bytes(s, m.l) for s, m in zip(stats, motifs))
+    tb = dg.info()["key_bytes"]  # stored timestamp width
+    bytes_per_step = sum(algorithmic_bytes(s, m.l, tb=tb) for s, m in zip(stats, motifs))
+    method_bytes_per_step = sum(method_bytes(s, m.l, tb=tb) for s, m in zip(stats, motifs))
+    # the method's bytes with int64 times, as the model states them (reported, no fraction)
+    method_bytes_i64 = sum(method_bytes(s, m.l) for s, m in zip(stats, motifs))
 
     def plain_step(lat):
         for h in handles:
@@ -670,7 +783,7 @@ def main():
     q_ms = [statistics.mean(kms_plain[i::len(handles)]) for i in range(len(handles))]
     per_query = []
     for i, (m, s_, c) in enumerate(zip(motifs, stats, counts)):
-        mb, ab = method_bytes(s_, m.l), algorithmic_bytes(s_, m.l)
+        mb, ab = method_bytes(s_, m.l, tb=tb), algorithmic_bytes(s_, m.l, tb=tb)
         per_query.append({"edges": m.edges, "delta": m.delta, "count": c,
                           "kernel_ms": q_ms[i], "algorithmic_bytes": ab,
                           "frac_closed_form_model": ab / (q_ms[i] * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -701,6 +814,8 @@ def main():
         "roofline": roof_method,
         # the timed (closed-form) kernel under its own algorithm's byte model
         "roofline_closed_form": roof_closed,
+        "timestamp_bytes": tb,
+        "method_bytes_int64_per_step": method_bytes_i64,
         "closed_form": {"speedup": open_ms / avg_launch_ms, "leaf_windows_counted": sum(s["leaf_counted"] for s in stats),
                         "ms_per_step_off": open_wall, "value_off": total_instances / (open_wall * 1e-3)},
         "setup": {"generate_s": round(gen_s, 2), "load_graph_s": round(load_s, 3),
@@ -712,17 +827,13 @@ def main():
                    "split_min": batch_setting[3], "leaf_min": batch_setting[4], "tuned": batch_setting[2]},
     }
     if args.calib_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        out["calib_copy_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
-        del src, dst
+        out["calib_copy_bytes"] = calib_copy(dev)
     if not args.no_tail:
         out["tail"] = bench_tail(ctx, handles, dg, stream, "wiki")
     if not args.no_constraints:
         out["constraints"] = bench_constraints(ctx, dg, args, stream)
+    if not args.no_enum_large:
+        out["enum_large"] = bench_enum_large(ctx, dg, args, stream)
     if not args.no_batch64:
         out["batch64"] = bench_batch64(ctx, args, stream)
     if args.serve_queries > 0:

@@ -66,6 +66,7 @@ enum { TM_PRED_GE = 0, TM_PRED_GT = 1, TM_PRED_LE = 2, TM_PRED_LT = 3 };
 #define TM_MAX_EDGES 8
 #define TM_MAX_NODES 8
 #define TM_MAX_ANTI 4
+#define TM_MAX_PREDS 8 /* weight predicates beyond pred_edge/pred_op/pred_theta */
 
 typedef struct tm_ctx tm_ctx;
 typedef struct tm_graph tm_graph;
@@ -124,6 +125,10 @@ void tm_destroy(tm_ctx *ctx);
  *                          candidates (default 512) whose count has a closed form is
  *                          counted with binary searches instead of a scan (see
  *                          tm_work_stats); 0 = always scan; else 32..2^24
+ *   TM_PARAM_ROOT_HANDOFF  1 (default) = with splitting on, once the root chunks are
+ *                          gone, a wavefront whose chunk still holds 16 or more unstarted
+ *                          roots hands the last half of them, one per work item, to
+ *                          waiting wavefronts (tail redistribution, Sec. 5.2.2); 0 = never
  *   TM_PARAM_TRACE_US      0 (default) = off; 10..100000 = while each mining kernel
  *                          runs, sample its control words every this many
  *                          microseconds from a side stream (the kernel is not
@@ -142,11 +147,12 @@ enum {
     TM_PARAM_WORK_BUDGET = 10,
     TM_PARAM_MIN_WAVES = 11,
     TM_PARAM_LEAF_MIN = 12,
-    TM_PARAM_TRACE_US = 13
+    TM_PARAM_TRACE_US = 13,
+    TM_PARAM_ROOT_HANDOFF = 14
 };
 tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t value);
 
-/* Samples of the last mining launch taken with TM_PARAM_TRACE_US > 0, 7 int64
+/* Samples of the last mining launch taken with TM_PARAM_TRACE_US > 0, 8 int64
  * per sample in time order (the load balance over time, Sec. 5.2.2):
  *   0 host nanoseconds since the launch was queued
  *   1 root chunks taken from the queue (>= column 2 once the queue is empty;
@@ -156,7 +162,8 @@ tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t value);
  *   4 wavefronts waiting for donated work
  *   5 donated work items waiting in the queues
  *   6 1 on the last sample, taken after the kernel ended
- * out: host int64[cap][7], may be NULL when cap is 0; *n_out (host) receives
+ *   7 unstarted roots handed to waiting wavefronts so far (TM_PARAM_ROOT_HANDOFF)
+ * out: host int64[cap][8], may be NULL when cap is 0; *n_out (host) receives
  * the number of samples (at most cap rows are written). */
 tm_status tm_last_trace(tm_ctx *ctx, int64_t *out, int64_t cap, int64_t *n_out);
 tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
@@ -225,6 +232,7 @@ typedef struct {
     int64_t device_bytes;    /* HBM held by the graph */
     int32_t was_sorted;      /* 1 if the input was already in non-decreasing time order */
     int32_t has_labels;      /* 1 once vertex labels are attached */
+    int32_t has_edge_labels; /* 1 once edge labels are attached */
 } tm_graph_info;
 tm_status tm_graph_get_info(const tm_graph *g, tm_graph_info *info);
 
@@ -235,6 +243,17 @@ tm_status tm_graph_get_info(const tm_graph *g, tm_graph_info *info);
  * queries on this graph are running. Blocking. Errors: TM_E_INVALID (null
  * argument, a negative label), TM_E_OOM, TM_E_DEVICE. */
 tm_status tm_graph_set_node_labels(tm_graph *g, const int32_t *labels);
+
+/* Attach edge labels (Sec. 2.1: edges may carry discrete attributes; Sec.
+ * 5.4.1: an edge's label is checked when the edge is matched; Sec. 6: random
+ * edge features): labels is a host int32[n_edges] array of values >= 0 in the
+ * input order of tm_load_graph (the library moves them to edge-id order when
+ * it re-sorted the input). Copied to device memory twice, in edge-id and in
+ * adjacency order (12 bytes per edge); a second call replaces them. Motifs
+ * with edge label ranges run only on a graph that has them. Not while
+ * queries on this graph are running. Blocking. Errors: TM_E_INVALID (null
+ * argument, a negative label), TM_E_OOM, TM_E_DEVICE. */
+tm_status tm_graph_set_edge_labels(tm_graph *g, const int32_t *labels);
 
 /* perm_out: host int64[n_edges]; perm_out[id] = input position of edge id. */
 tm_status tm_graph_edge_order(const tm_graph *g, int64_t *perm_out);
@@ -254,7 +273,8 @@ tm_status tm_graph_copy_csr(const tm_graph *g, int32_t dir, uint32_t *off, int32
 
 /* -------------------------------------------------------------------- motif
  * A motif query (Sec. 4.3, user-defined query: pattern plus the coarse delta
- * and fine-grained delta_i constraints and an attribute constraint).
+ * and fine-grained delta_i constraints and attribute constraints on nodes and
+ * edges).
  *
  *   n_nodes     k, 2..8; every node 0..k-1 must appear on some edge
  *   n_edges     l, 1..8
@@ -277,6 +297,20 @@ tm_status tm_graph_copy_csr(const tm_graph *g, int32_t dir, uint32_t *off, int32
  *               requires (Sec. 5.4.1), -1 = any; checked when the node is
  *               first matched. Label values are launch arguments; which nodes
  *               carry one is part of the structure.
+ *   n_pred      0..TM_MAX_PREDS further weight predicates (Sec. 2.1 attribute
+ *               constraints), all of which must hold besides pred_edge's; several
+ *               may test one motif edge (an interval of weights)
+ *   preds       host tm_edge_pred[n_pred] or NULL when n_pred is 0: motif edge,
+ *               TM_PRED_* operator and float32 threshold of each
+ *   node_label_hi  host int32[n_nodes] or NULL: with node_label, node v's label
+ *               must lie in [node_label[v], node_label_hi[v]] (inclusive,
+ *               node_label_hi[v] >= node_label[v] where node_label[v] >= 0);
+ *               NULL means node_label_hi = node_label (one value)
+ *   edge_label  host int32[2*n_edges] or NULL: (lo, hi) per motif edge; the
+ *               graph edge matched to motif edge i must carry an edge label in
+ *               [lo, hi] (lo = -1: any; else hi >= lo >= 0); checked when the
+ *               edge is matched. Which edges carry a range is structure, the
+ *               bounds are launch arguments.
  *
  * An anti-edge is checked when the candidate of level max(i, first level
  * binding a, first level binding b) is accepted, and a hit ends that branch of
@@ -292,6 +326,13 @@ tm_status tm_graph_copy_csr(const tm_graph *g, int32_t dir, uint32_t *off, int32
  * level scans the whole edge list (Algorithm 1, GetCandidateEdgeList, case
  * neither endpoint mapped). Errors: TM_E_INVALID, TM_E_UNSUPPORTED,
  * TM_E_COMPILE. */
+/* One weight predicate: w(e_edge) op theta, as a float32 comparison. */
+typedef struct {
+    int32_t edge;
+    int32_t op;  /* TM_PRED_* */
+    float theta;
+} tm_edge_pred;
+
 typedef struct {
     int32_t n_nodes;
     int32_t n_edges;
@@ -305,6 +346,10 @@ typedef struct {
     const int32_t *anti;
     const int64_t *anti_delta;
     const int32_t *node_label;
+    int32_t n_pred;
+    const tm_edge_pred *preds;
+    const int32_t *node_label_hi;
+    const int32_t *edge_label;
 } tm_motif_desc;
 
 tm_status tm_compile_motif(tm_ctx *ctx, const tm_motif_desc *desc, tm_motif **out);
@@ -399,6 +444,7 @@ tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const
  * the call returns TM_E_CANCELLED; the other counts are exact. */
 tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
                          const tm_root_range *ranges, hipStream_t stream, uint64_t *counts_out);
+
 
 /* ----------------------------------------------------------------- serving
  * A request loop over one resident graph with continuous batching. Queries

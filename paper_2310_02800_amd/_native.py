@@ -19,13 +19,14 @@ STATUS_NAMES = {0: "TM_OK", 1: "TM_E_INVALID", 2: "TM_E_OOM", 3: "TM_E_COMPILE",
 TM_PARAM_BLOCK, TM_PARAM_ROOT_CHUNK, TM_PARAM_GRID = 1, 2, 3
 TM_PARAM_PROFILE, TM_PARAM_SPLIT, TM_PARAM_SPLIT_MIN, TM_PARAM_TIER, TM_PARAM_AUTOTUNE = 5, 6, 7, 8, 9
 TM_PARAM_WORK_BUDGET, TM_PARAM_MIN_WAVES, TM_PARAM_LEAF_MIN, TM_PARAM_TRACE_US = 10, 11, 12, 13
+TM_PARAM_ROOT_HANDOFF = 14
 
 # Every function the header declares, for the export check.
 EXPORTED = [
     "tm_last_error", "tm_version", "tm_create", "tm_destroy", "tm_set_param", "tm_get_param", "tm_last_kernel_ms",
     "tm_last_launch", "tm_last_trace", "tm_tune_save", "tm_tune_load", "tm_tune_clear",
     "tm_load_graph", "tm_free_graph", "tm_graph_get_info", "tm_graph_edge_order", "tm_graph_copy_csr",
-    "tm_graph_set_node_labels",
+    "tm_graph_set_node_labels", "tm_graph_set_edge_labels",
     "tm_compile_motif", "tm_free_motif", "tm_motif_source", "tm_motif_compile_check", "tm_batch_compile_check",
     "tm_generic_compile_check",
     "tm_count", "tm_enumerate",
@@ -34,11 +35,17 @@ EXPORTED = [
 ]
 
 
+class EdgePred(ctypes.Structure):
+    _fields_ = [("edge", ctypes.c_int32), ("op", ctypes.c_int32), ("theta", ctypes.c_float)]
+
+
 class MotifDesc(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int32), ("n_edges", ctypes.c_int32), ("edges", ctypes.c_void_p),
                 ("delta", ctypes.c_int64), ("gap_max", ctypes.c_void_p), ("pred_edge", ctypes.c_int32),
                 ("pred_op", ctypes.c_int32), ("pred_theta", ctypes.c_float), ("n_anti", ctypes.c_int32),
-                ("anti", ctypes.c_void_p), ("anti_delta", ctypes.c_void_p), ("node_label", ctypes.c_void_p)]
+                ("anti", ctypes.c_void_p), ("anti_delta", ctypes.c_void_p), ("node_label", ctypes.c_void_p),
+                ("n_pred", ctypes.c_int32), ("preds", ctypes.c_void_p), ("node_label_hi", ctypes.c_void_p),
+                ("edge_label", ctypes.c_void_p)]
 
 
 class RootRange(ctypes.Structure):
@@ -66,7 +73,8 @@ class Result(ctypes.Structure):
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64), ("n_edges", ctypes.c_int64), ("t_min", ctypes.c_int64),
                 ("t_max", ctypes.c_int64), ("key_bytes", ctypes.c_int32), ("has_weights", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64), ("was_sorted", ctypes.c_int32), ("has_labels", ctypes.c_int32)]
+                ("device_bytes", ctypes.c_int64), ("was_sorted", ctypes.c_int32), ("has_labels", ctypes.c_int32),
+                ("has_edge_labels", ctypes.c_int32)]
 
 
 _lib = None
@@ -113,6 +121,7 @@ def lib():
         "tm_graph_edge_order": (i32, [P, P]),
         "tm_graph_copy_csr": (i32, [P, i32, P, P, P, P]),
         "tm_graph_set_node_labels": (i32, [P, P]),
+        "tm_graph_set_edge_labels": (i32, [P, P]),
         "tm_compile_motif": (i32, [P, P, pp]),
         "tm_free_motif": (None, [P]),
         "tm_motif_source": (i32, [P, i32, P, i64, P]),

@@ -72,6 +72,14 @@ class Graph:
             raise ValueError("one label per node")
         N.check(N.lib().tm_graph_set_node_labels(self._h, _ptr(lab)))
 
+    def set_edge_labels(self, labels) -> None:
+        """Attach edge labels (int32 >= 0, one per edge, in the input order
+        given to load_graph)."""
+        lab = _np(labels, np.int32)
+        if lab.shape != (self.info()["n_edges"],):
+            raise ValueError("one label per edge")
+        N.check(N.lib().tm_graph_set_edge_labels(self._h, _ptr(lab)))
+
     def edge_order(self) -> np.ndarray:
         m = self.info()["n_edges"]
         out = np.zeros(m, np.int64)
@@ -125,10 +133,12 @@ class Motif:
 
 
 def make_desc(edges, delta, gap=None, pred_edge=-1, pred_op=0, pred_theta=0.0, n_nodes=None, anti=None,
-              node_labels=None):
+              node_labels=None, node_label_hi=None, preds=None, edge_labels=None):
     """Motif descriptor. ``anti``: temporal anti-edges as (a, b, attach edge,
     window) tuples; ``node_labels``: required vertex label per motif node
-    (-1 = any)."""
+    (-1 = any), with ``node_label_hi`` the upper ends of label ranges;
+    ``preds``: further weight predicates as (edge, op, theta); ``edge_labels``:
+    a (lo, hi) label range per motif edge (lo = -1: any)."""
     e = np.ascontiguousarray(np.array(edges, dtype=np.int32).reshape(-1))
     l = e.size // 2
     k = int(n_nodes) if n_nodes is not None else (int(e.max()) + 1 if e.size else 0)
@@ -143,18 +153,33 @@ def make_desc(edges, delta, gap=None, pred_edge=-1, pred_op=0, pred_theta=0.0, n
         nl = np.ascontiguousarray(np.array(node_labels, dtype=np.int32))
         if nl.shape != (k,):
             raise ValueError("one label (or -1) per motif node")
-    d = N.MotifDesc(k, l, ctypes.c_void_p(e.ctypes.data), int(delta),
-                    None if g is None else ctypes.c_void_p(g.ctypes.data), int(pred_edge), int(pred_op),
-                    float(pred_theta), na, None if an is None else ctypes.c_void_p(an.ctypes.data),
-                    None if ad is None else ctypes.c_void_p(ad.ctypes.data),
-                    None if nl is None else ctypes.c_void_p(nl.ctypes.data))
-    return d, (e, g, an, ad, nl)  # keep arrays alive with the descriptor
+    nh = None
+    if node_label_hi is not None:
+        nh = np.ascontiguousarray(np.array(node_label_hi, dtype=np.int32))
+        if nh.shape != (k,):
+            raise ValueError("one upper label (or -1) per motif node")
+    np_ = 0 if not preds else len(preds)
+    pa = None
+    if np_:
+        pa = (N.EdgePred * np_)(*[N.EdgePred(int(x[0]), int(x[1]), float(x[2])) for x in preds])
+    el = None
+    if edge_labels is not None:
+        el = np.ascontiguousarray(np.array(edge_labels, dtype=np.int32).reshape(-1))
+        if el.shape != (2 * l,):
+            raise ValueError("one (lo, hi) label range per motif edge")
+    ptr = lambda a: None if a is None else ctypes.c_void_p(a.ctypes.data)
+    d = N.MotifDesc(k, l, ctypes.c_void_p(e.ctypes.data), int(delta), ptr(g), int(pred_edge), int(pred_op),
+                    float(pred_theta), na, ptr(an), ptr(ad), ptr(nl), np_,
+                    None if pa is None else ctypes.cast(pa, ctypes.c_void_p), ptr(nh), ptr(el))
+    return d, (e, g, an, ad, nl, nh, pa, el)  # keep arrays alive with the descriptor
 
 
 def motif_desc_of(m):
     """Descriptor of a synth.Motif-like object."""
     return make_desc(m.edges, m.delta, None if m.gap is None else m.gaps(), m.pred_edge, m.pred_op, m.pred_theta,
-                     anti=getattr(m, "anti", None), node_labels=getattr(m, "node_labels", None))
+                     anti=getattr(m, "anti", None), node_labels=getattr(m, "node_labels", None),
+                     node_label_hi=getattr(m, "node_label_hi", None), preds=getattr(m, "preds", None),
+                     edge_labels=getattr(m, "edge_labels", None))
 
 
 def motif_source(edges, delta=0, key_bytes=4, **kw) -> str:
@@ -237,11 +262,12 @@ class Context:
 
     def last_trace(self) -> np.ndarray:
         """Samples of the last mining launch taken with TM_PARAM_TRACE_US > 0:
-        int64[n, 7] rows of (ns since queued, chunks taken, chunks, busy
-        wavefronts, waiting wavefronts, donated items waiting, done)."""
+        int64[n, 8] rows of (ns since queued, chunks taken, chunks, busy
+        wavefronts, waiting wavefronts, donated items waiting, done, roots
+        handed to waiting wavefronts)."""
         n = ctypes.c_int64(0)
         N.check(N.lib().tm_last_trace(self._h, None, 0, ctypes.byref(n)))
-        out = np.zeros((n.value, 7), np.int64)
+        out = np.zeros((n.value, 8), np.int64)
         N.check(N.lib().tm_last_trace(self._h, _ptr(out), n.value, ctypes.byref(n)))
         return out[:n.value]
 
@@ -279,11 +305,15 @@ class Context:
         dg = self.load_graph(g.n, g.src, g.dst, g.t, g.w)
         if getattr(g, "labels", None) is not None:
             dg.set_node_labels(g.labels)
+        if getattr(g, "edge_labels", None) is not None:
+            dg.set_edge_labels(g.edge_labels)
         return dg
 
     def compile_motif(self, edges, delta, gap=None, pred_edge=-1, pred_op=0, pred_theta=0.0,
-                      n_nodes=None, anti=None, node_labels=None) -> Motif:
-        d, keep = make_desc(edges, delta, gap, pred_edge, pred_op, pred_theta, n_nodes, anti, node_labels)
+                      n_nodes=None, anti=None, node_labels=None, node_label_hi=None, preds=None,
+                      edge_labels=None) -> Motif:
+        d, keep = make_desc(edges, delta, gap, pred_edge, pred_op, pred_theta, n_nodes, anti, node_labels,
+                            node_label_hi, preds, edge_labels)
         h = ctypes.c_void_p()
         N.check(N.lib().tm_compile_motif(self._h, ctypes.byref(d), ctypes.byref(h)))
         return Motif(self, h, d.n_edges)
@@ -292,7 +322,9 @@ class Context:
         """Compile a synth.Motif-like object."""
         return self.compile_motif(m.edges, m.delta, None if m.gap is None else m.gaps(), m.pred_edge, m.pred_op,
                                   m.pred_theta, anti=getattr(m, "anti", None),
-                                  node_labels=getattr(m, "node_labels", None))
+                                  node_labels=getattr(m, "node_labels", None),
+                                  node_label_hi=getattr(m, "node_label_hi", None), preds=getattr(m, "preds", None),
+                                  edge_labels=getattr(m, "edge_labels", None))
 
     # ---- mining
     def count(self, g: Graph, m: Motif, t_lo=None, t_hi=None, stream=None) -> int:
@@ -453,7 +485,12 @@ def tail_summary(samples) -> dict:
     t_drain = int(s[drained[0], 0]) if drained.size else t_end
     tail = s[(s[:, 0] >= t_drain) & (s[:, 6] == 0)]
     span = max(t_end - t_start, 1)
+    busy_after = float(tail[:, 3].mean()) if tail.shape[0] else 0.0
+    peak = int(s[:, 3].max())
+    tail_frac = (t_end - t_drain) / span
     return {"samples": int(s.shape[0]), "run_ms": span / 1e6, "drain_ms": (t_drain - t_start) / 1e6,
-            "tail_ms": (t_end - t_drain) / 1e6, "tail_frac": (t_end - t_drain) / span,
-            "busy_after_drain_mean": float(tail[:, 3].mean()) if tail.shape[0] else 0.0,
-            "busy_peak": int(s[:, 3].max())}
+            "tail_ms": (t_end - t_drain) / 1e6, "tail_frac": tail_frac,
+            "busy_after_drain_mean": busy_after, "busy_peak": peak,
+            # share of the launch's wavefront time spent idle after the queue drained
+            "idle_share": tail_frac * (1.0 - busy_after / peak) if peak else 0.0,
+            "roots_handed": int(s[-1, 7]) if s.shape[1] > 7 else 0}

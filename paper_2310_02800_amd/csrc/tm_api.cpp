@@ -47,7 +47,7 @@ struct DeviceGuard {
 void free_graph_buffers(tm_graph *g) {
     void *ptrs[] = {g->d_src, g->d_dst, g->d_tk, g->d_w, g->d_adj_t, g->d_adj_nbr, g->d_adj_eid, g->d_adj_w,
                     g->d_off_out, g->d_off_in, g->d_pos_out, g->d_pos_in, g->d_pr_nbr, g->d_pr_t, g->d_pr_pos,
-                    g->d_nlab};
+                    g->d_nlab, g->d_el, g->d_adj_el};
     for (void *p : ptrs)
         if (p) hipFree(p);
 }
@@ -167,15 +167,29 @@ void fill_qargs(const tm_graph *g, const tm_motif *m, int64_t r0, int64_t r1, in
     for (int j = 0; j < m->plan.n_anti; j++) q->gap[tmo::anti_slot(j)] = std::min<int64_t>(m->plan.anti_delta[j], span);
     q->c0 = c0;
     q->nchunks = (r1 - r0 + rch - 1) / rch;
-    q->theta = m->theta;
-    q->pred_op = m->pred_op;
     q->fn = fn;
     q->budget = budget;
     q->split = split;
     q->split_min = (int32_t)std::min<int64_t>(split_min, INT32_MAX);
-    q->lab_mask = m->plan.lab_mask;
-    for (int v = 0; v < 8; v++) q->nlab[v] = m->plan.lab_val[v];
-    tmo::fill_plan_tables(m->plan, q);
+    const tmo::Plan &p = m->plan;
+    q->lab_mask = p.lab_mask;
+    for (int v = 0; v < 8; v++) {
+        q->nlab[v] = p.lab_val[v];
+        q->nlab_hi[v] = p.lab_hi[v];
+    }
+    q->elab_mask = p.elab_mask;
+    for (int i = 0; i < 8; i++) {
+        q->elo[i] = p.elab_lo[i];
+        q->ehi[i] = p.elab_hi[i];
+    }
+    q->npred = p.np;
+    q->pred_mask = (int32_t)p.pred_mask();
+    for (int j = 0; j < p.np; j++) {
+        q->pth[j] = p.pred_th[j];
+        q->pop[j] = (uint8_t)p.pred_op[j];
+        q->plev[j] = (uint8_t)p.pred_lvl[j];
+    }
+    tmo::fill_plan_tables(p, q);
 }
 
 GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w, const tmo::LaunchCfg &c) {
@@ -197,6 +211,8 @@ GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w, const tmo::LaunchCfg &c
     a.pr_t = g->d_pr_t;
     a.pr_pos = g->d_pr_pos;
     a.nlab = g->d_nlab;
+    a.el = g->d_el;
+    a.adj_el = g->d_adj_el;
     a.qa = (const QArgs *)w->qa;
     a.ctl = w->ctl;
     a.counts = w->counts;
@@ -237,7 +253,8 @@ tm_status sample_launch(tm_ctx *ctx, tm_ctx::Workspace *w, int64_t chunks, hipSt
                               std::chrono::steady_clock::now() - t0).count();
         const uint64_t *c = w->h_tr;
         const int64_t row[tmo::kTraceCols] = {t, (int64_t)c[tmo::CTL_CURSOR], chunks, (int64_t)c[tmo::CTL_BUSY],
-                                              (int64_t)c[tmo::CTL_HUNGRY], (int64_t)c[tmo::CTL_AVAIL], done ? 1 : 0};
+                                              (int64_t)c[tmo::CTL_HUNGRY], (int64_t)c[tmo::CTL_AVAIL], done ? 1 : 0,
+                                              (int64_t)c[tmo::CTL_HANDED]};
         rows.insert(rows.end(), row, row + tmo::kTraceCols);
         if (done) break;
         std::this_thread::sleep_for(std::chrono::microseconds(ctx->trace_us));
@@ -255,6 +272,8 @@ tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int 
     HIP_TRY(tmo::dev_fill_u64(w->ctl, 0, tmo::CTL_WORDS, stream), "reset counters");
     // cross-wavefront work donation: a zeroed item buffer, fresh queue
     // heads/tails and a new epoch so items of earlier launches never look ready
+    // bit 1 of the split word: hand unstarted roots to waiting wavefronts
+    if (a->split) a->split = 1 | (ctx->root_handoff ? 2 : 0);
     if (a->split && mode != tmo::MODE_STATS && a->nq > 0) {
         if (!w->items) {
             const size_t bytes = tmo::kItemsTotal * tmo::kItemWords * sizeof(uint32_t);
@@ -296,7 +315,9 @@ tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int 
 tm_status check_pair(tm_ctx *ctx, const tm_graph *g, const tm_motif *m) {
     if (!ctx || !g || !m) return fail(TM_E_INVALID, "null context, graph or motif");
     if (g->ctx != ctx || m->ctx != ctx) return fail(TM_E_INVALID, "graph or motif belongs to another context");
-    if (m->plan.pred_level >= 0 && !g->has_w) return fail(TM_E_INVALID, "motif has a weight predicate but the graph has no weights");
+    if (m->plan.np > 0 && !g->has_w) return fail(TM_E_INVALID, "motif has a weight predicate but the graph has no weights");
+    if (m->plan.elab_mask && !g->has_edge_labels)
+        return fail(TM_E_INVALID, "motif requires edge labels but the graph has none");
     if (m->plan.lab_mask && !g->has_labels)
         return fail(TM_E_INVALID, "motif requires vertex labels but the graph has none");
     return TM_OK;
@@ -658,6 +679,10 @@ tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t v) {
         if (v != 0 && (v < 10 || v > 100000)) return fail(TM_E_INVALID, "sampling period must be 0 or 10..100000 us");
         ctx->trace_us = v;
         return TM_OK;
+    case TM_PARAM_ROOT_HANDOFF:
+        if (v != 0 && v != 1) return fail(TM_E_INVALID, "root handoff must be 0 or 1");
+        ctx->root_handoff = (int)v;
+        return TM_OK;
     default:
         return fail(TM_E_INVALID, "unknown parameter");
     }
@@ -678,6 +703,7 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *v) {
     case TM_PARAM_MIN_WAVES: *v = ctx->min_waves; return TM_OK;
     case TM_PARAM_LEAF_MIN: *v = ctx->leaf_min; return TM_OK;
     case TM_PARAM_TRACE_US: *v = ctx->trace_us; return TM_OK;
+    case TM_PARAM_ROOT_HANDOFF: *v = ctx->root_handoff; return TM_OK;
     default: return fail(TM_E_INVALID, "unknown parameter");
     }
 }
@@ -929,6 +955,7 @@ tm_status tm_graph_get_info(const tm_graph *g, tm_graph_info *info) {
     info->device_bytes = g->device_bytes;
     info->was_sorted = g->was_sorted ? 1 : 0;
     info->has_labels = g->has_labels ? 1 : 0;
+    info->has_edge_labels = g->has_edge_labels ? 1 : 0;
     return TM_OK;
 }
 
@@ -945,6 +972,32 @@ tm_status tm_graph_set_node_labels(tm_graph *g, const int32_t *labels) {
         HIP_TRY(hipDeviceSynchronize(), "upload labels");
     }
     g->has_labels = true;
+    return TM_OK;
+}
+
+tm_status tm_graph_set_edge_labels(tm_graph *g, const int32_t *labels) {
+    if (!g || (!labels && g->m > 0)) return fail(TM_E_INVALID, "null argument");
+    for (int64_t e = 0; e < g->m; e++)
+        if (labels[e] < 0) return fail(TM_E_INVALID, "edge labels must be >= 0");
+    DeviceGuard dg(g->device);
+    // input order -> edge-id order (ids are positions after the time sort)
+    std::vector<int32_t> by_id;
+    const int32_t *src = labels;
+    if (!g->perm.empty()) {
+        by_id.resize(g->m);
+        for (int64_t e = 0; e < g->m; e++) by_id[e] = labels[g->perm[e]];
+        src = by_id.data();
+    }
+    if (!g->d_el) HIP_TRY(dmalloc(&g->d_el, std::max<int64_t>(g->m, 1), &g->device_bytes), "hipMalloc edge labels");
+    if (!g->d_adj_el)
+        HIP_TRY(dmalloc(&g->d_adj_el, std::max<int64_t>(2 * g->m, 1), &g->device_bytes), "hipMalloc edge labels");
+    if (g->m > 0) {
+        HIP_TRY(hipMemcpy(g->d_el, src, (size_t)g->m * sizeof(int32_t), hipMemcpyHostToDevice), "upload edge labels");
+        HIP_TRY(hipDeviceSynchronize(), "upload edge labels");
+        HIP_TRY(tmo::dev_gather_i32(2 * g->m, g->d_adj_eid, g->d_el, g->d_adj_el, nullptr), "edge labels by list");
+        HIP_TRY(hipDeviceSynchronize(), "edge labels by list");
+    }
+    g->has_edge_labels = true;
     return TM_OK;
 }
 
@@ -1011,8 +1064,6 @@ tm_status tm_compile_motif(tm_ctx *ctx, const tm_motif_desc *desc, tm_motif **ou
     }
     m->ctx = ctx;
     m->delta = desc->delta;
-    m->pred_op = desc->pred_op;
-    m->theta = desc->pred_theta;
     DeviceGuard dg(ctx->device);
     // compile eagerly for 32-bit time keys (the common case) so errors surface
     // here; with the generic tier this is the shared module of the motif length

@@ -47,14 +47,12 @@ Plan generic_plan(int l) {
     p.l = l;
     p.k = TM_MAX_NODES;
     p.generic = true;
-    p.pred_level = -1;
     p.a[0] = 0;
     p.b[0] = 1;
     return p;
 }
 
 void fill_plan_tables(const Plan &p, QArgs *q) {
-    q->pred_level = p.pred_level;
     q->glob_mask = 0;
     for (int i = 0; i < 8; i++) q->pk[i] = q->pa[i] = q->pb[i] = q->pm[i] = q->pj[i] = 0;
     for (int i = 1; i < p.l; i++) {
@@ -76,9 +74,13 @@ void fill_plan_tables(const Plan &p, QArgs *q) {
 std::string Plan::key() const {
     if (generic) return "G" + std::to_string(l);
     std::ostringstream o;
-    o << "l" << l << "k" << k << "p" << pred_level << ":";
+    o << "l" << l << "k" << k << "p";
+    if (np == 0) o << "-1";  // no predicate (the key of motifs without one is unchanged)
+    for (int j = 0; j < np; j++) o << (j ? "." : "") << pred_lvl[j];
+    o << ":";
     for (int i = 0; i < l; i++) o << a[i] << b[i] << ",";
     if (lab_mask) o << "L" << lab_mask;
+    if (elab_mask) o << "E" << elab_mask;
     if (n_anti > 0) {
         o << "n";
         for (int j = 0; j < n_anti; j++) o << anti_a[j] << anti_b[j] << anti_at[j] << ",";
@@ -122,7 +124,41 @@ bool build_plan(const tm_motif_desc *d, Plan *p, int64_t *gaps, std::string *err
         *err = "unknown predicate operator";
         return false;
     }
-    p->pred_level = d->pred_edge;
+    // weight predicates: the single one and the list, sorted by motif edge
+    // (stable, so a launch's thresholds follow the caller's order per edge)
+    if (d->n_pred < 0 || d->n_pred > TM_MAX_PREDS) { *err = "at most 8 further weight predicates"; return false; }
+    if (d->n_pred > 0 && !d->preds) { *err = "predicate array is null"; return false; }
+    {
+        struct P { int lvl, op; float th; };
+        std::vector<P> ps;
+        if (d->pred_edge >= 0) ps.push_back({d->pred_edge, d->pred_op, d->pred_theta});
+        for (int j = 0; j < d->n_pred; j++) {
+            const tm_edge_pred &x = d->preds[j];
+            if (x.edge < 0 || x.edge >= l) { *err = "predicate edge out of range"; return false; }
+            if (x.op < TM_PRED_GE || x.op > TM_PRED_LT) { *err = "unknown predicate operator"; return false; }
+            ps.push_back({x.edge, x.op, x.theta});
+        }
+        std::stable_sort(ps.begin(), ps.end(), [](const P &x, const P &y) { return x.lvl < y.lvl; });
+        p->np = (int)ps.size();
+        for (int j = 0; j < p->np; j++) {
+            p->pred_lvl[j] = ps[j].lvl;
+            p->pred_op[j] = ps[j].op;
+            p->pred_th[j] = ps[j].th;
+        }
+    }
+    // edge labels (Sec. 5.4.1): an inclusive range per motif edge
+    p->elab_mask = 0;
+    for (int i = 0; i < TM_MAX_EDGES; i++) p->elab_lo[i] = p->elab_hi[i] = 0;
+    if (d->edge_label)
+        for (int i = 0; i < l; i++) {
+            const int32_t lo = d->edge_label[2 * i], hi = d->edge_label[2 * i + 1];
+            if (lo < -1 || (lo >= 0 && hi < lo)) { *err = "edge label ranges need -1 or 0 <= lo <= hi"; return false; }
+            if (lo >= 0) {
+                p->elab_mask |= 1 << i;
+                p->elab_lo[i] = lo;
+                p->elab_hi[i] = hi;
+            }
+        }
     bool bound[TM_MAX_NODES] = {};
     bound[p->a[0]] = bound[p->b[0]] = true;
     for (int i = 1; i < l; i++) {
@@ -135,14 +171,17 @@ bool build_plan(const tm_motif_desc *d, Plan *p, int64_t *gaps, std::string *err
     }
     // vertex labels (Sec. 5.4.1), in the relabelled node order
     p->lab_mask = 0;
-    for (int v = 0; v < TM_MAX_NODES; v++) p->lab_val[v] = 0;
+    for (int v = 0; v < TM_MAX_NODES; v++) p->lab_val[v] = p->lab_hi[v] = 0;
     if (d->node_label)
         for (int v = 0; v < k; v++) {
             const int32_t want = d->node_label[v];
+            const int32_t top = d->node_label_hi ? d->node_label_hi[v] : want;
             if (want < -1) { *err = "node labels must be -1 (any) or >= 0"; return false; }
+            if (want >= 0 && top < want) { *err = "node label ranges need node_label_hi >= node_label"; return false; }
             if (want >= 0) {
                 p->lab_mask |= 1 << relabel[v];
                 p->lab_val[relabel[v]] = want;
+                p->lab_hi[relabel[v]] = top;
             }
         }
     // temporal anti-edges (Sec. 2.1): each is checked at the first level where
@@ -182,18 +221,14 @@ struct QArgs {
   i64 r0, r1, delta;
   i64 gap[8];
   i64 c0, nchunks;
-  float theta;
-  int pred_op;
-  int fn;
-  int split;
   i64 budget;
+  int fn, split, split_min, pred_mask;
   unsigned char pk[8], pa[8], pb[8], pm[8], pj[8];
-  int pred_level;
-  int glob_mask;
-  int split_min;
-  int lab_mask;
-  int nlab[8];
-  int pad[2];
+  int glob_mask, lab_mask, elab_mask, npred;
+  int nlab[8], nlab_hi[8];
+  int elo[8], ehi[8];
+  float pth[12];
+  unsigned char pop[12], plev[12];
 };
 
 struct GArgs {
@@ -211,14 +246,17 @@ struct GArgs {
   const int* pr_nbr; const tkey* pr_t;
   const int* nlab;
   const u32* pr_pos;
+  const int* el; const int* adj_el;
 };
-static_assert(sizeof(QArgs) == 224, "QArgs layout");
-static_assert(sizeof(GArgs) == 240, "GArgs layout");
+static_assert(sizeof(QArgs) == 384, "QArgs layout");
+static_assert(sizeof(GArgs) == 256, "GArgs layout");
 // generic matchers: motif node slot by run-time index, and the bound-node check
 #define mget(ix) ((ix) == 0 ? m0 : (ix) == 1 ? m1 : (ix) == 2 ? m2 : (ix) == 3 ? m3 : \
                   (ix) == 4 ? m4 : (ix) == 5 ? m5 : (ix) == 6 ? m6 : m7)
 #define lget(ix) ((ix) == 0 ? l0 : (ix) == 1 ? l1 : (ix) == 2 ? l2 : (ix) == 3 ? l3 : \
                   (ix) == 4 ? l4 : (ix) == 5 ? l5 : (ix) == 6 ? l6 : l7)
+#define hget(ix) ((ix) == 0 ? h0 : (ix) == 1 ? h1 : (ix) == 2 ? h2 : (ix) == 3 ? h3 : \
+                  (ix) == 4 ? h4 : (ix) == 5 ? h5 : (ix) == 6 ? h6 : h7)
 #define mset(ix, val) do { const int v_ = (val); const int i_ = (ix); \
     m0 = i_ == 0 ? v_ : m0; m1 = i_ == 1 ? v_ : m1; m2 = i_ == 2 ? v_ : m2; m3 = i_ == 3 ? v_ : m3; \
     m4 = i_ == 4 ? v_ : m4; m5 = i_ == 5 ? v_ : m5; m6 = i_ == 6 ? v_ : m6; m7 = i_ == 7 ? v_ : m7; } while (0)
@@ -255,6 +293,15 @@ __device__ __forceinline__ u64 wave_sum(u64 v, int lane) {
 __device__ __forceinline__ bool pred_ok(float w, int op, float th) {
   return op == 0 ? (w >= th) : op == 1 ? (w > th) : op == 2 ? (w <= th) : (w < th);
 }
+// every weight predicate of level lv holds (table-driven matchers)
+__device__ __forceinline__ bool preds_at(const QArgs* q, int lv, float w) {
+  bool ok = true;
+  for (int j = 0; j < q->npred; ++j)
+    if (q->plev[j] == lv) ok = ok && pred_ok(w, q->pop[j], q->pth[j]);
+  return ok;
+}
+// a label in the inclusive range [lo, hi]
+__device__ __forceinline__ bool in_range(int x, int lo, int hi) { return x >= lo && x <= hi; }
 __device__ __forceinline__ u32 bitlen(u32 x) { return x ? 32u - (u32)__builtin_clz(x) : 0u; }
 // Counting a last-level window without scanning it. `pr` counts the reads.
 // Entries of [c, e) (sorted by time) with time <= t, galloping from c.
@@ -408,8 +455,28 @@ struct Emitter {
     std::string I(int i) const { return std::to_string(i); }
 
     // Vertex labels (Sec. 5.4.1): a node newly bound by a candidate must carry
-    // the label its motif node requires (register nl<v>, a launch argument).
+    // a label in its motif node's range (registers nl<v>, nh<v>: launch
+    // arguments).
     bool labelled(int v) const { return !G && ((p.lab_mask >> v) & 1); }
+    std::string lab_cond(int v, const std::string &node) const {
+        return "in_range(g.nlab[" + node + "], nl" + I(v) + ", nh" + I(v) + ")";
+    }
+    // Weight predicates (attribute constraints, Sec. 2.1 / 5.4.1): every
+    // predicate on motif edge i holds for weight w (pop<j>, pth<j>: launch
+    // arguments of predicate slot j).
+    bool has_pred(int i) const { return !G && ((p.pred_mask() >> i) & 1u); }
+    std::string preds_cond(int i, const std::string &w) const {
+        std::string c;
+        for (int j = 0; j < p.np; j++)
+            if (p.pred_lvl[j] == i) c += (c.empty() ? "" : " && ") + std::string("pred_ok(") + w + ", pop" + I(j) + ", pth" + I(j) + ")";
+        return c.empty() ? "true" : c;
+    }
+    // Edge labels: the graph edge matched to motif edge i carries a label in
+    // [elo<i>, ehi<i>] (launch arguments).
+    bool has_elab(int i) const { return !G && ((p.elab_mask >> i) & 1); }
+    std::string elab_cond(int i, const std::string &el) const {
+        return "in_range(" + el + ", elo" + I(i) + ", ehi" + I(i) + ")";
+    }
     // The motif node a level's candidate binds, for list kinds OUT and IN.
     int new_node(int i) const { return p.kind[i] == LIST_OUT ? p.b[i] : p.a[i]; }
 
@@ -598,6 +665,29 @@ struct Emitter {
         const int L = p.l, K = p.k;
         o << "    if (q_split && drained && MODE != 1) {\n";
         o << "      iter++;\n";
+        // Tail redistribution of unstarted roots (Sec. 5.2.2 redistributes
+        // the tail's work): once the root queue is empty, a wavefront whose
+        // pool still holds 16 or more roots of its chunk hands the last half
+        // of them, one root per item, to the query's queue while some
+        // wavefronts wait for work
+        o << "      if ((g.split & 2) && g.items != 0 && ghungry > 0 && (iter & 31u) == 8u && pend - pnext >= 16) {\n";
+        o << "        const i64 give = (pend - pnext) >> 1;\n";
+        o << "        i64 s0 = 0;\n";
+        o << "        if (lane == 0) s0 = (i64)atomicAdd(&g.qctl[2 * qi + 1], (u64)give);\n";
+        o << "        s0 = bcast64(s0);\n";
+        o << "        const i64 room = (i64)g.item_cap - s0;\n";
+        o << "        const i64 fit = room <= 0 ? 0 : (room < give ? room : give);\n";
+        o << "        for (i64 t = lane; t < fit; t += 64) {\n";
+        o << "          const i64 k = pend - fit + t;\n";
+        o << "          u32* it = item_at(g, qi, (u64)(s0 + t));\n";
+        o << "          st_ag(it + 1, 0u); st_ag(it + 7, (u32)(q_r0 + (pchunk - q_c0) + k * q_nch)); st_ag64(it + 8, pchunk);\n";
+        o << "          mem_order();\n";
+        o << "          st_ag(it, g.epoch);\n";
+        o << "        }\n";
+        // items waiting in all queues; roots handed so far
+        o << "        if (lane == 0 && fit > 0) { atomicAdd(&g.ctl[13], (u64)fit); atomicAdd(&g.ctl[14], (u64)fit); }\n";
+        o << "        pend -= fit;\n";
+        o << "      }\n";
         o << "      if ((iter & 31u) == 0u && g.items != 0) {\n";
         o << "        i64 hv = 0; if (lane == 0) hv = (i64)ld_rlx64(&g.ctl[9]); ghungry = bcast64(hv);\n";
         o << "      }\n";
@@ -732,6 +822,9 @@ struct Emitter {
         o << ind << "const u32* it = item_at(g, qi, " << slot << ");\n";
         o << ind << "if (item_ready(g, it)) {\n";
         o << ind << "  const int j = (int)ld_ag(it + 1);\n";
+        // level 0: a handed root, which the lane fetches at its next refill
+        o << ind << "  if (j == 0) { proot = (int)ld_ag(it + 7); pmy = ld_ag64(it + 8); lvl = 0; ph = 0; base = 1; exact = 0u; }\n";
+        o << ind << "  else {\n";
         o << ind << "  lvl = j; base = j; ph = 0; exact = 1u << j;\n";
         if (leaf_cache()) o << ind << "  lq = false;\n";
         o << ind << "  root = (int)ld_ag(it + 7); mych = ld_ag64(it + 8); tmaxk = (tkey)ld_ag64(it + 10);\n";
@@ -748,6 +841,7 @@ struct Emitter {
         }
         o << ind << "    default: break;\n";
         o << ind << "  }\n";
+        o << ind << "  }\n";
         o << ind << "}\n";
     }
 
@@ -763,7 +857,7 @@ struct Emitter {
     // at run time.
     bool leaf_countable() const {
         const int i = p.l - 1;
-        return G || (p.l > 1 && p.kind[i] != LIST_GLOBAL && p.pred_level != i && !anti_on(i) &&
+        return G || (p.l > 1 && p.kind[i] != LIST_GLOBAL && !has_pred(i) && !has_elab(i) && !anti_on(i) &&
                      !(p.kind[i] != LIST_BOTH && labelled(new_node(i))));
     }
 
@@ -885,10 +979,10 @@ struct Emitter {
         if (!leaf_countable()) return;
         const std::string s = I(i);
         const char *ind = "            ";
-        const std::string gc = G ? " && gpl != " + s + " && !glabl" : std::string();
+        const std::string gc = G ? " && gcf" : std::string();
         o << ind << "if ((MODE == 0 || MODE == 2) && wide && g.leaf_min > 0 && sb + (u32)g.leaf_min - 1u < end" << s
           << " && g.adj_t[sb + (u32)g.leaf_min - 1u] <= hi" << s << gc << ") park = true;\n";
-        const std::string gcond = G ? " && !((gglob >> " + s + ") & 1u) && gpl != " + s + " && !glabl" : std::string();
+        const std::string gcond = G ? " && !((gglob >> " + s + ") & 1u) && gcf" : std::string();
         o << ind << "if (MODE == 1 && g.leaf_min > 0" << gcond << ") {\n";
         o << ind << "  const u32 pk = sb + (u32)g.leaf_min - 1u;\n";
         o << ind << "  if (pk < end" << s << " && g.adj_t[pk] <= hi" << s << ") {\n";
@@ -940,8 +1034,8 @@ struct Emitter {
             o << "        const int w_ = rl(want" << i << ", j);\n";
             for (int v = 0; v < 8; v++) o << "        const int x" << v << " = rl(m" << v << ", j);\n";
             ok << "(gk" << i << " == 2 ? nb == w_ : notin(gm" << i << ", nb, x0, x1, x2, x3, x4, x5, x6, x7))";
-            ok << " && (gk" << i << " == 2 || ((glm >> gn" << i << ") & 1u) == 0u || g.nlab[nb] == lget(gn" << i
-               << "))";
+            ok << " && (gk" << i << " == 2 || ((glm >> gn" << i << ") & 1u) == 0u || in_range(g.nlab[nb], lget(gn"
+               << i << "), hget(gn" << i << ")))";
         } else if (p.kind[i] == LIST_BOTH) {
             o << "        const int w_ = rl(want" << i << ", j);\n";
             ok << "nb == w_";
@@ -951,7 +1045,7 @@ struct Emitter {
                 o << "        const int x" << v << " = rl(m" << v << ", j);\n";
                 ok << " && nb != x" << v;
             }
-            if (labelled(new_node(i))) ok << " && g.nlab[nb] == nl" << new_node(i);
+            if (labelled(new_node(i))) ok << " && " << lab_cond(new_node(i), "nb");
         }
         o << "        int o_root = 0; i64 o_ch = 0;\n";
         o << "        if (MODE == 3) { o_root = rl(root, j); o_ch = rl(mych, j); }\n";
@@ -964,10 +1058,14 @@ struct Emitter {
         o << "          if (v) { t = g.adj_t[idx]; nb = g.adj_nbr[idx]; }\n";
         o << "          v = v && t <= h;\n";
         o << "          bool ok = v && " << ok.str() << ";\n";
-        if (G)
-            o << "          if (ok && gpl == " << i << ") ok = pred_ok(g.adj_w[idx], pop, theta);\n";
-        else if (p.pred_level == i)
-            o << "          if (ok) ok = pred_ok(g.adj_w[idx], pop, theta);\n";
+        if (G) {
+            o << "          if (ok && ((gpm >> " << i << ") & 1u)) ok = preds_at(q, " << i << ", g.adj_w[idx]);\n";
+            o << "          if (ok && ((gelm >> " << i << ") & 1u)) ok = in_range(g.adj_el[idx], q->elo[" << i << "], q->ehi["
+              << i << "]);\n";
+        } else {
+            if (has_pred(i)) o << "          if (ok) ok = " << preds_cond(i, "g.adj_w[idx]") << ";\n";
+            if (has_elab(i)) o << "          if (ok) ok = " << elab_cond(i, "g.adj_el[idx]") << ";\n";
+        }
         o << "          const u64 okm = ballot(ok);\n";
         o << "          tot += (u64)__builtin_popcountll(okm);\n";
         o << "          if (MODE == 3 && okm != 0ull) {\n";
@@ -1048,11 +1146,15 @@ struct Emitter {
         o << "  const bool q_split = g.split && q->split; const u32 q_smin = (u32)q->split_min;\n";
         for (int i = 0; i + 1 < L; i++) o << "  const i64 gap" << i << " = q->gap[" << i << "];\n";
         for (int j = 0; j < p.n_anti; j++) o << "  const i64 adl" << j << " = q->gap[" << anti_slot(j) << "];\n";
-        if (G || p.pred_level >= 0) o << "  const float theta = q->theta; const int pop = q->pred_op;\n";
+        if (!G)
+            for (int j = 0; j < p.np; j++)
+                o << "  const int pop" << j << " = q->pop[" << j << "]; const float pth" << j << " = q->pth[" << j << "];\n";
         for (int v = 0; v < K; v++)
-            if (labelled(v)) o << "  const int nl" << v << " = q->nlab[" << v << "];\n";
+            if (labelled(v)) o << "  const int nl" << v << " = q->nlab[" << v << "], nh" << v << " = q->nlab_hi[" << v << "];\n";
+        for (int i = 0; i < L; i++)
+            if (has_elab(i)) o << "  const int elo" << i << " = q->elo[" << i << "], ehi" << i << " = q->ehi[" << i << "];\n";
         if (G) {
-            o << "  const int gpl = q->pred_level; const u32 gglob = (u32)q->glob_mask;\n";
+            o << "  const u32 gpm = (u32)q->pred_mask, gelm = (u32)q->elab_mask; const u32 gglob = (u32)q->glob_mask;\n";
             for (int i = 1; i < L; i++)
                 o << "  const int gk" << i << " = q->pk[" << i << "], ga" << i << " = q->pa[" << i << "], gb" << i
                   << " = q->pb[" << i << "], gj" << i << " = q->pj[" << i << "]; const u32 gm" << i << " = q->pm["
@@ -1060,10 +1162,17 @@ struct Emitter {
             o << "  const u32 glm = (u32)q->lab_mask;\n";
             o << "  const int l0 = q->nlab[0], l1 = q->nlab[1], l2 = q->nlab[2], l3 = q->nlab[3], l4 = q->nlab[4], "
                  "l5 = q->nlab[5], l6 = q->nlab[6], l7 = q->nlab[7];\n";
+            o << "  const int h0 = q->nlab_hi[0], h1 = q->nlab_hi[1], h2 = q->nlab_hi[2], h3 = q->nlab_hi[3], "
+                 "h4 = q->nlab_hi[4], h5 = q->nlab_hi[5], h6 = q->nlab_hi[6], h7 = q->nlab_hi[7];\n";
             for (int i = 1; i < L; i++)
                 o << "  const int gn" << i << " = gk" << i << " == 0 ? gb" << i << " : ga" << i << ";\n";
             if (L > 1)
                 o << "  const bool glabl = gk" << L - 1 << " != 2 && ((glm >> gn" << L - 1 << ") & 1u) != 0u;\n";
+            // the last level's count has a closed form (no predicate, edge
+            // label or label on its new node there)
+            if (L > 1)
+                o << "  const bool gcf = !glabl && !((gpm >> " << L - 1 << ") & 1u) && !((gelm >> " << L - 1
+                  << ") & 1u);\n";
         }
         o << "  int lvl = 0, ph = 0, root = 0, base = 1, cool = 0;\n";
         o << "  u32 exact = 0u;  // bit i: end of level i's window is its exact extent\n";
@@ -1088,6 +1197,8 @@ struct Emitter {
                 if (fixed_at_leaf(v)) o << "  u32 ls" << v << " = 0u, le" << v << " = 0u;\n";
         }
         o << "  u32 iter = 0u, steps = 0u; i64 ghungry = 0;\n";
+        o << "  int proot = -1; i64 pmy = 0;  // a root handed to this lane (tail redistribution)\n";
+        o << "  u32 dchk = 0u;\n";
         o << "  i64 pnext = 0, pend = 0, pchunk = chunk, pending = -1;\n";
         o << "  bool drained = chunk < 0;\n";
         o << "  if (chunk >= 0) {\n";
@@ -1103,13 +1214,15 @@ struct Emitter {
         o << "  }\n";
         o << "  for (;;) {\n";
         // ---------------- refill
-        o << "    const u64 need = ballot(lvl == 0);\n";
-        o << "    if (need) {\n";
+        // lanes holding a handed root (proot) take it instead of a pool root
+        o << "    const bool wantp = lvl == 0 && proot < 0;\n";
+        o << "    const u64 need = ballot(wantp);\n";
+        o << "    if (need || ballot(lvl == 0) != 0ull) {\n";
         o << "      const i64 nneed = (i64)__builtin_popcountll(need);\n";
         o << "      const i64 rk = (i64)rank_in(need);\n";
         o << "      const i64 avail = pend - pnext;\n";
         o << "      i64 myr = -1, myc = pchunk;\n";
-        o << "      if (lvl == 0 && rk < avail) myr = q_r0 + (pchunk - q_c0) + (pnext + rk) * q_nch;\n";
+        o << "      if (wantp && rk < avail) myr = q_r0 + (pchunk - q_c0) + (pnext + rk) * q_nch;\n";
         o << "      if (avail >= nneed) { pnext += nneed; }\n";
         o << "      else {\n";
         o << "        pnext = pend;\n";
@@ -1122,29 +1235,32 @@ struct Emitter {
         o << "            pchunk = c;\n";
         o << "            pnext = 0; pend = (q_n - (c - q_c0) + q_nch - 1) / q_nch;\n";
         o << "            const i64 k2 = rk - avail;\n";
-        o << "            if (lvl == 0 && myr < 0 && k2 < pend) { myr = q_r0 + (c - q_c0) + k2 * q_nch; myc = c; }\n";
+        o << "            if (wantp && myr < 0 && k2 < pend) { myr = q_r0 + (c - q_c0) + k2 * q_nch; myc = c; }\n";
         o << "            const i64 take = nneed - avail < pend - pnext ? nneed - avail : pend - pnext;\n";
         o << "            pnext += take;\n";
         o << "          }\n";
         o << "        }\n";
         o << "      }\n";
+        o << "      if (lvl == 0 && proot >= 0) { myr = proot; myc = pmy; proot = -1; }\n";
         o << "      if (lvl == 0) {\n";
         o << "        if (myr >= 0) {\n";
         o << "          const int r = (int)myr;\n";
         o << "          const int s = g.src[r], d = g.dst[r];\n";
         o << "          const tkey tr = g.tk[r];\n";
         if (G) {
-            o << "          if (MODE == 1) { st_root++; if (gpl == 0) st_pv++; }\n";
+            o << "          if (MODE == 1) { st_root++; if (gpm & 1u) st_pv++; }\n";
             o << "          bool ok = s != d;\n";
-            o << "          if (gpl == 0) ok = ok && pred_ok(g.w[r], pop, theta);\n";
-            o << "          if (glm & 1u) ok = ok && g.nlab[s] == l0;\n";
-            o << "          if (glm & 2u) ok = ok && g.nlab[d] == l1;\n";
+            o << "          if (gpm & 1u) ok = ok && preds_at(q, 0, g.w[r]);\n";
+            o << "          if (gelm & 1u) ok = ok && in_range(g.el[r], q->elo[0], q->ehi[0]);\n";
+            o << "          if (glm & 1u) ok = ok && in_range(g.nlab[s], l0, h0);\n";
+            o << "          if (glm & 2u) ok = ok && in_range(g.nlab[d], l1, h1);\n";
         } else {
-            o << "          if (MODE == 1) { st_root++;" << (p.pred_level == 0 ? " st_pv++;" : "") << " }\n";
+            o << "          if (MODE == 1) { st_root++;" << (has_pred(0) ? " st_pv++;" : "") << " }\n";
             o << "          bool ok = s != d;\n";
-            if (p.pred_level == 0) o << "          ok = ok && pred_ok(g.w[r], pop, theta);\n";
-            if (labelled(p.a[0])) o << "          ok = ok && g.nlab[s] == nl" << p.a[0] << ";\n";
-            if (labelled(p.b[0])) o << "          ok = ok && g.nlab[d] == nl" << p.b[0] << ";\n";
+            if (has_pred(0)) o << "          ok = ok && " << preds_cond(0, "g.w[r]") << ";\n";
+            if (has_elab(0)) o << "          ok = ok && " << elab_cond(0, "g.el[r]") << ";\n";
+            if (labelled(p.a[0])) o << "          ok = ok && " << lab_cond(p.a[0], "s") << ";\n";
+            if (labelled(p.b[0])) o << "          ok = ok && " << lab_cond(p.b[0], "d") << ";\n";
             if (anti_on(0)) o << "          ok = ok && " << anti_cond(0) << ";\n";
         }
         o << "          if (ok) {\n";
@@ -1181,7 +1297,19 @@ struct Emitter {
         o << "        break;\n";
         o << "      }\n";
         o << "    }\n";
-        if (L > 1) steal();
+        // A wavefront still working through its chunk learns that the whole
+        // root queue is empty (it only fetches again once its pool is used
+        // up): a relaxed look at the queue cursor every 64 steps. From then
+        // on it splits pending work and hands out unstarted roots.
+        if (L > 1) {
+            o << "    if (q_split && !drained && g.items != 0 && ((++dchk & 63u) == 0u)) {\n";
+            o << "      i64 cc = 0;\n";
+            o << "      if (lane == 0) cc = (i64)ld_rlx64(&g.ctl[0]);\n";
+            o << "      cc = bcast64(cc);\n";
+            o << "      if (cc >= g.total_chunks) drained = true;  // no chunk of any query is left\n";
+            o << "    }\n";
+            steal();
+        }
         if (L > 1 && coop_ok()) coop();
         if (L > 1 && coop_ok()) park_flush();
         if (L > 1) {
@@ -1197,10 +1325,24 @@ struct Emitter {
             } else {
                 o << "      const tkey* sarr = g.adj_t;\n";
             }
-            // ph 2: first probe at the window start (tie skip after a jump)
-            o << "      const u32 half = ph == 2 ? 0u : (sn >> 1); const u32 mid = sb + half;\n";
-            o << "      const tkey v = sarr[mid];\n";
-            o << "      if (v <= sx) { sb = mid + 1u; sn = sn - half - 1u; } else { sn = half; }\n";
+            // ph 2: first probe at the window start (tie skip after a jump).
+            // A search of 3 or more unknown entries reads three pivots at
+            // once and keeps one of the four ranges between them: half as
+            // many dependent steps as a binary search, the three reads in
+            // flight together.
+            o << "      if (ph == 1 && sn >= 3u) {\n";
+            o << "        const u32 o1 = ((sn + 1u) >> 2) - 1u, o2 = ((2u * (sn + 1u)) >> 2) - 1u, "
+                 "o3 = ((3u * (sn + 1u)) >> 2) - 1u;\n";
+            o << "        const tkey v1 = sarr[sb + o1], v2 = sarr[sb + o2], v3 = sarr[sb + o3];\n";
+            o << "        if (v3 <= sx) { sb += o3 + 1u; sn -= o3 + 1u; }\n";
+            o << "        else if (v2 <= sx) { sb += o2 + 1u; sn = o3 - o2 - 1u; }\n";
+            o << "        else if (v1 <= sx) { sb += o1 + 1u; sn = o2 - o1 - 1u; }\n";
+            o << "        else { sn = o1; }\n";
+            o << "      } else {\n";
+            o << "        const u32 half = ph == 2 ? 0u : (sn >> 1); const u32 mid = sb + half;\n";
+            o << "        const tkey v = sarr[mid];\n";
+            o << "        if (v <= sx) { sb = mid + 1u; sn = sn - half - 1u; } else { sn = half; }\n";
+            o << "      }\n";
             o << "      ph = 1;\n";
             o << "      if (sn == 0u) {\n";
             o << "        bool park = false;\n";
@@ -1231,15 +1373,22 @@ struct Emitter {
                 o << "        case " << i << ": c = cur" << i << "; e = end" << i << "; h = hi" << i << "; break;\n";
             o << "        default: break;\n";
             o << "      }\n";
+            bool any_pred = false, any_elab = false;
+            for (int i = 1; i < L; i++) {
+                any_pred |= has_pred(i);
+                any_elab |= has_elab(i);
+            }
             o << "      bool inwin = false; tkey tt = 0; int nb = 0;";
-            if (G || p.pred_level >= 1) o << " float wv = 0.0f;";
+            if (G || any_pred) o << " float wv = 0.0f;";
+            if (G || any_elab) o << " int ev = 0;";
             o << "\n";
             o << "      if (c < e) {\n";
             if (G) {
                 o << "        const bool gl = ((gglob >> lvl) & 1u) != 0u;\n";
                 o << "        tt = gl ? g.tk[c] : g.adj_t[c];\n";
                 o << "        if (!gl) nb = g.adj_nbr[c];\n";
-                o << "        if (lvl == gpl) wv = gl ? g.w[c] : g.adj_w[c];\n";
+                o << "        if ((gpm >> lvl) & 1u) wv = gl ? g.w[c] : g.adj_w[c];\n";
+                o << "        if ((gelm >> lvl) & 1u) ev = gl ? g.el[c] : g.adj_el[c];\n";
             } else if (glob) {
                 o << "        bool gl = false;\n";
                 for (int i = 1; i < L; i++)
@@ -1250,18 +1399,20 @@ struct Emitter {
                 o << "        tt = g.adj_t[c];\n";
                 o << "        nb = g.adj_nbr[c];\n";
             }
-            if (p.pred_level >= 1) {
-                if (p.kind[p.pred_level] == LIST_GLOBAL)
-                    o << "        if (lvl == " << p.pred_level << ") wv = g.w[c];\n";
-                else
-                    o << "        if (lvl == " << p.pred_level << ") wv = g.adj_w[c];\n";
+            for (int i = 1; i < L; i++) {
+                if (has_pred(i))
+                    o << "        if (lvl == " << i << ") wv = " << (p.kind[i] == LIST_GLOBAL ? "g.w[c]" : "g.adj_w[c]")
+                      << ";\n";
+                if (has_elab(i))
+                    o << "        if (lvl == " << i << ") ev = " << (p.kind[i] == LIST_GLOBAL ? "g.el[c]" : "g.adj_el[c]")
+                      << ";\n";
             }
             o << "        inwin = tt <= h;\n";
             if (G)
-                o << "        if (MODE == 1) { st_visit++; if (lvl == gpl) st_pv++; }\n";
+                o << "        if (MODE == 1) { st_visit++; if ((gpm >> lvl) & 1u) st_pv++; }\n";
             else
                 o << "        if (MODE == 1) { st_visit++;"
-                  << (p.pred_level >= 1 ? " if (lvl == " + std::to_string(p.pred_level) + ") st_pv++;" : std::string())
+                  << (any_pred ? " if ((" + std::to_string(p.pred_mask()) + "u >> lvl) & 1u) st_pv++;" : std::string())
                   << " }\n";
             o << "      }\n";
             o << "      if (!inwin) {\n";
@@ -1288,13 +1439,17 @@ struct Emitter {
                     o << "          else ok = notin(gm" << s << ", nb, " << ms << ");\n";
                     o << "          if (glm != 0u) {\n";
                     o << "            if (gk" << s << " == 3) {\n";
-                    o << "              if ((glm >> ga" << s << ") & 1u) ok = ok && g.nlab[cs] == lget(ga" << s << ");\n";
-                    o << "              if ((glm >> gb" << s << ") & 1u) ok = ok && g.nlab[cd] == lget(gb" << s << ");\n";
+                    o << "              if ((glm >> ga" << s << ") & 1u) ok = ok && in_range(g.nlab[cs], lget(ga" << s
+                      << "), hget(ga" << s << "));\n";
+                    o << "              if ((glm >> gb" << s << ") & 1u) ok = ok && in_range(g.nlab[cd], lget(gb" << s
+                      << "), hget(gb" << s << "));\n";
                     o << "            } else if (gk" << s << " != 2 && ((glm >> gn" << s << ") & 1u)) {\n";
-                    o << "              ok = ok && g.nlab[nb] == lget(gn" << s << ");\n";
+                    o << "              ok = ok && in_range(g.nlab[nb], lget(gn" << s << "), hget(gn" << s << "));\n";
                     o << "            }\n";
                     o << "          }\n";
-                    o << "          if (gpl == " << i << ") ok = ok && pred_ok(wv, pop, theta);\n";
+                    o << "          if ((gpm >> " << i << ") & 1u) ok = ok && preds_at(q, " << i << ", wv);\n";
+                    o << "          if ((gelm >> " << i << ") & 1u) ok = ok && in_range(ev, q->elo[" << i << "], q->ehi[" << i
+                      << "]);\n";
                     o << "          if (ok) {\n";
                     if (i == L - 1) {
                         leaf("            ", eidx.c_str());
@@ -1318,7 +1473,7 @@ struct Emitter {
                 case LIST_IN: {
                     ok << "true";
                     for (int v : p.mapped[i]) ok << " && nb != m" << v;
-                    if (labelled(new_node(i))) ok << " && g.nlab[nb] == nl" << new_node(i);
+                    if (labelled(new_node(i))) ok << " && " << lab_cond(new_node(i), "nb");
                     bind = "m" + std::to_string(p.kind[i] == LIST_OUT ? B : A) + " = nb;";
                     eid = "g.adj_eid[c]";
                     break;
@@ -1331,14 +1486,15 @@ struct Emitter {
                     o << "          const int cs = g.src[c], cd = g.dst[c];\n";
                     ok << "cs != cd";
                     for (int v : p.mapped[i]) ok << " && cs != m" << v << " && cd != m" << v;
-                    if (labelled(A)) ok << " && g.nlab[cs] == nl" << A;
-                    if (labelled(B)) ok << " && g.nlab[cd] == nl" << B;
+                    if (labelled(A)) ok << " && " << lab_cond(A, "cs");
+                    if (labelled(B)) ok << " && " << lab_cond(B, "cd");
                     bind = "m" + std::to_string(A) + " = cs; m" + std::to_string(B) + " = cd;";
                     eid = "(int)c";
                 }
                 }
                 o << "          bool ok = " << ok.str() << ";\n";
-                if (p.pred_level == i) o << "          ok = ok && pred_ok(wv, pop, theta);\n";
+                if (has_pred(i)) o << "          ok = ok && " << preds_cond(i, "wv") << ";\n";
+                if (has_elab(i)) o << "          ok = ok && " << elab_cond(i, "ev") << ";\n";
                 if (anti_on(i)) o << "          ok = ok && " << anti_cond(i) << ";\n";
                 o << "          if (ok) {\n";
                 if (i == L - 1) {

@@ -159,6 +159,18 @@ hipError_t dev_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+__global__ void k_gather_i32(int64_t n, const int32_t *idx, const int32_t *vals, int32_t *out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = vals[idx[i]];
+}
+
+hipError_t dev_gather_i32(int64_t n, const int32_t *eid, const int32_t *el, int32_t *out, hipStream_t s) {
+    clear_stale_error();
+    if (n <= 0) return hipSuccess;
+    k_gather_i32<<<blocks_for(n), kThreads, 0, s>>>(n, eid, el, out);
+    return hipGetLastError();
+}
+
 hipError_t dev_check_ids(int64_t m, int64_t n, const int32_t *d_src, const int32_t *d_dst, uint32_t *d_bad,
                          hipStream_t s) {
     clear_stale_error();

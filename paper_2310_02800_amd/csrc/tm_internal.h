@@ -25,25 +25,27 @@ struct QArgs {
     int64_t delta;      // clamped to the graph's time span
     int64_t gap[8];     // fine-grained limits, clamped to delta
     int64_t c0, nchunks;  // this query's slice of the launch's root-chunk queue
-    float theta;
-    int32_t pred_op;
+    int64_t budget;     // wavefront loop steps this query may use (0 = no limit)
     int32_t fn;         // which specialised matcher of the module runs it
     int32_t split;      // 1: busy lanes of this query hand pending windows to idle ones
-    int64_t budget;     // wavefront loop steps this query may use (0 = no limit)
+    int32_t split_min;  // smallest pending window this query splits
+    int32_t pred_mask;  // bit i: motif edge i has at least one weight predicate
     // plan tables read by the generic (table-driven) matchers, per level:
     // list kind, source and destination motif node, mask of motif nodes bound
     // before the level, window-start rule (0 search, 1 after the root in its
     // source's out-list, 2 after the root in its destination's in-list, 3 after
     // the previous level's candidate)
     uint8_t pk[8], pa[8], pb[8], pm[8], pj[8];
-    int32_t pred_level;
     int32_t glob_mask;  // bit i: level i scans the whole edge list
-    int32_t split_min;  // smallest pending window this query splits
-    int32_t lab_mask;   // bit v: motif node v requires the vertex label nlab[v]
-    int32_t nlab[8];
-    int32_t pad[2];
+    int32_t lab_mask;   // bit v: motif node v requires a vertex label in [nlab[v], nlab_hi[v]]
+    int32_t elab_mask;  // bit i: motif edge i requires an edge label in [elo[i], ehi[i]]
+    int32_t npred;      // weight predicates: pth, pop, plev [0, npred), sorted by edge
+    int32_t nlab[8], nlab_hi[8];
+    int32_t elo[8], ehi[8];
+    float pth[12];
+    uint8_t pop[12], plev[12];
 };
-static_assert(sizeof(QArgs) == 224, "QArgs layout");
+static_assert(sizeof(QArgs) == 384, "QArgs layout");
 
 struct GArgs {
     const int32_t *src;
@@ -67,7 +69,7 @@ struct GArgs {
     int64_t total_chunks;
     int32_t rch;              // roots per chunk
     int32_t nq;
-    int32_t split;            // 1 = idle lanes take pending candidates from busy lanes
+    int32_t split;            // bit 0: idle lanes take pending candidates from busy lanes; bit 1: and unstarted roots
     int32_t leaf_min;         // smallest last-level window counted in closed form (0 = never)
     uint32_t *items;          // donated work items, item_cap per query, 32 words each
     uint64_t *qctl;           // per query: (head, tail) of its item queue
@@ -79,16 +81,18 @@ struct GArgs {
     const void *pr_t;
     const int32_t *nlab;      // vertex labels (n entries) or null
     const uint32_t *pr_pos;   // per adjacency entry: its position in the pair-sorted lists
+    const int32_t *el;        // edge labels in edge-id order (m entries) or null
+    const int32_t *adj_el;    // edge labels in adjacency order (2m entries) or null
 };
-static_assert(sizeof(GArgs) == 240, "GArgs layout");
+static_assert(sizeof(GArgs) == 256, "GArgs layout");
 
 // ctl words: [10..12] work counters of the windows counted without a scan,
 // [13] donated items waiting in all queues
 enum { CTL_CURSOR = 0, CTL_OVERFLOW = 1, CTL_STATS = 2, CTL_ERROR = 7, CTL_BUSY = 8, CTL_HUNGRY = 9,
-       CTL_LEAF = 10, CTL_AVAIL = 13, CTL_WORDS = 16 };
+       CTL_LEAF = 10, CTL_AVAIL = 13, CTL_HANDED = 14, CTL_WORDS = 16 };
 constexpr uint32_t kItemWords = 32;
 constexpr uint64_t kItemsTotal = uint64_t(1) << 20;  // donated work items per launch (128 MiB)
-constexpr int kTraceCols = 7;            // t_ns, cursor, chunks, busy, waiting, items, done
+constexpr int kTraceCols = 8;            // t_ns, cursor, chunks, busy, waiting, items, done, handed
 constexpr int64_t kTraceMaxSamples = 1 << 20;
 enum Mode { MODE_COUNT = 0, MODE_STATS = 1, MODE_ENUM_COUNT = 2, MODE_ENUM_WRITE = 3, MODE_COUNT_ = 4 };
 
@@ -100,7 +104,12 @@ struct Plan {
     int a[TM_MAX_EDGES] = {}, b[TM_MAX_EDGES] = {};
     int kind[TM_MAX_EDGES] = {};            // per level >= 1
     std::vector<int> mapped[TM_MAX_EDGES];  // motif nodes bound before level i
-    int pred_level = -1;
+    // weight predicates (Sec. 2.1 attribute constraints), sorted by motif
+    // edge: which edge each tests (structure) and its operator and threshold
+    // (launch arguments)
+    int np = 0;
+    int pred_lvl[TM_MAX_PREDS + 1] = {}, pred_op[TM_MAX_PREDS + 1] = {};
+    float pred_th[TM_MAX_PREDS + 1] = {};
     bool generic = false;  // table-driven matcher for every motif with l edges
     // temporal anti-edges: motif nodes, attach edge, and the level at which
     // each is checked (its attach edge matched and both nodes bound)
@@ -109,10 +118,20 @@ struct Plan {
     // anti-edge windows: launch values (in the gap slots the motif leaves
     // free), not part of the structure key
     int64_t anti_delta[TM_MAX_ANTI] = {};
-    // vertex labels: bit v of lab_mask = motif node v requires lab_val[v]
-    // (the mask is structure, the values are launch arguments)
+    // vertex labels: bit v of lab_mask = motif node v requires a label in
+    // [lab_val[v], lab_hi[v]]; edge labels: bit i of elab_mask = motif edge i
+    // requires a label in [elab_lo[i], elab_hi[i]] (masks are structure,
+    // values launch arguments)
     int lab_mask = 0;
-    int32_t lab_val[TM_MAX_NODES] = {};
+    int32_t lab_val[TM_MAX_NODES] = {}, lab_hi[TM_MAX_NODES] = {};
+    int elab_mask = 0;
+    int32_t elab_lo[TM_MAX_EDGES] = {}, elab_hi[TM_MAX_EDGES] = {};
+    // bit i: motif edge i has at least one weight predicate
+    uint32_t pred_mask() const {
+        uint32_t m = 0;
+        for (int j = 0; j < np; j++) m |= 1u << pred_lvl[j];
+        return m;
+    }
     std::string key() const;
 };
 
@@ -182,6 +201,8 @@ hipError_t dev_make_keys(int64_t m, const int64_t *d_t, int64_t t_min, int key_b
 hipError_t dev_check_ids(int64_t m, int64_t n, const int32_t *d_src, const int32_t *d_dst, uint32_t *d_bad,
                          hipStream_t s);
 hipError_t dev_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+// out[p] = el[eid[p]] for p < n (edge labels into adjacency order)
+hipError_t dev_gather_i32(int64_t n, const int32_t *eid, const int32_t *el, int32_t *out, hipStream_t s);
 // own scan and radix sort (tm_sort.hip). Scans: exclusive, in == out allowed,
 // `tmp` holds scan_tmp_elems(n) elements. Radix sort: stable, keys below
 // 2^end_bit, ping-pong between (keys, vals) and the *_alt buffers (*in_alt
@@ -268,6 +289,7 @@ struct tm_ctx {
     tmo::LaunchCfg last_cfg;  // setting of the last mining launch
     int last_tuned = 0;       // 1: it came from the tune table
     int64_t trace_us = 0;     // launch sampling period (0 = off)
+    int root_handoff = 1;     // hand unstarted roots to waiting wavefronts once the queue is empty
     std::vector<int64_t> trace;  // samples of the last sampled launch, kTraceCols each
 };
 
@@ -292,6 +314,9 @@ struct tm_graph {
     uint32_t *d_pr_pos = nullptr;  // per adjacency entry: its position in the pair-sorted lists
     int32_t *d_nlab = nullptr;    // vertex labels (n entries), once attached
     bool has_labels = false;
+    int32_t *d_el = nullptr;      // edge labels (m entries, id order), once attached
+    int32_t *d_adj_el = nullptr;  // the same in adjacency order (2m entries)
+    bool has_edge_labels = false;
     std::vector<int64_t> h_t;     // sorted absolute times (root-range lookup)
     std::vector<int64_t> perm;    // empty when the input was sorted
     int64_t device_bytes = 0;
@@ -302,8 +327,6 @@ struct tm_motif {
     tmo::Plan plan;
     int64_t delta = 0;
     int64_t gaps[TM_MAX_EDGES] = {};
-    int32_t pred_op = 0;
-    float theta = 0.0f;
 };
 
 namespace tmo {

@@ -286,8 +286,6 @@ tm_status tm_submit_query(tm_server *s, const tm_query *q, uint64_t *ticket) {
     }
     p->motif.ctx = s->ctx;
     p->motif.delta = q->motif.delta;
-    p->motif.pred_op = q->motif.pred_op;
-    p->motif.theta = q->motif.pred_theta;
     tm_status st = tmo::check_query(s->ctx, s->g, &p->motif);
     if (st != TM_OK) {
         delete p;

@@ -29,8 +29,9 @@ def ctx():
 
 
 def check_samples(s):
-    assert s.shape[0] >= 1 and s.shape[1] == 7
+    assert s.shape[0] >= 1 and s.shape[1] == 8
     assert s[-1, 6] == 1 and (s[:-1, 6] == 0).all()
+    assert (np.diff(s[:, 7]) >= 0).all() and (s[:, 7] >= 0).all()  # roots handed only grow
     assert (np.diff(s[:, 0]) >= 0).all()
     assert (np.diff(s[:, 1]) >= 0).all()  # chunks taken only grow
     assert (s[:, 2] == s[0, 2]).all()

@@ -15,8 +15,8 @@ from paper_2310_02800_amd import api, synth
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def sample(t, taken, chunks, busy, waiting=0, items=0, done=0):
-    return [t, taken, chunks, busy, waiting, items, done]
+def sample(t, taken, chunks, busy, waiting=0, items=0, done=0, handed=0):
+    return [t, taken, chunks, busy, waiting, items, done, handed]
 
 
 def test_tail_summary_of_a_hand_made_trace():
@@ -37,10 +37,17 @@ def test_tail_summary_of_a_hand_made_trace():
     assert r["tail_frac"] == pytest.approx(3.0 / 9.0)
     assert r["busy_after_drain_mean"] == pytest.approx((40 + 10) / 2)
     assert r["busy_peak"] == 64
+    # idle share of the launch: the tail's fraction times the idle share of the peak wavefronts in it
+    assert r["idle_share"] == pytest.approx(3.0 / 9.0 * (1 - 25 / 64))
+    assert r["roots_handed"] == 0
 
 
 def test_tail_summary_edge_cases():
-    assert api.tail_summary(np.zeros((0, 7), np.int64)) == {}
+    assert api.tail_summary(np.zeros((0, 8), np.int64)) == {}
+    # the last sample's handed-roots column is the launch's total
+    s = np.array([sample(0, 1, 10, 5), sample(5, 10, 10, 5, handed=7), sample(9, 10, 10, 0, done=1, handed=9)],
+                 np.int64)
+    assert api.tail_summary(s)["roots_handed"] == 9
     # never drained before the end: the tail is empty
     s = np.array([sample(0, 1, 10, 5), sample(5, 3, 10, 5), sample(9, 10, 10, 0, done=1)], np.int64)
     r = api.tail_summary(s)
