@@ -445,6 +445,32 @@ tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const
 tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
                          const tm_root_range *ranges, hipStream_t stream, uint64_t *counts_out);
 
+/* tm_count_batch for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc. It
+ * allocates no device memory, event or stream (its host-side argument copies
+ * are ordinary pageable memory). Its control words, per-query counts, launch
+ * arguments and donated-work items live in one device array of 16 MiB
+ * (TM_NOALLOC_SCRATCH_BYTES) that each GPU the library runs on holds until
+ * the process ends, shared by every call on that GPU: each call resets what
+ * must start at zero and keeps nothing from earlier calls. Calls on one GPU
+ * are serialised by the library (a second one waits for the first); calls
+ * from other processes or overlapping with the same scratch by any other
+ * route race. Arguments and results as tm_count_batch, except:
+ *   - q <= TM_NOALLOC_MAX_QUERIES (256), else TM_E_INVALID;
+ *   - the batched kernel of exactly these motifs (same structures, tier and
+ *     graph timestamp width) must already be compiled and loaded by an
+ *     earlier tm_count_batch on ctx, else TM_E_INVALID (nothing is compiled or
+ *     loaded here);
+ *   - the launch uses the batch key's tuned setting when TM_PARAM_AUTOTUNE
+ *     has one, else the context's defaults, with no tuning trials and no
+ *     timing or sampling (TM_PARAM_PROFILE and TM_PARAM_TRACE_US are ignored);
+ *   - at most about 130,000 pending windows can be donated between
+ *     wavefronts per launch (a donor keeps work it cannot hand over), which
+ *     changes speed, never a count. */
+#define TM_NOALLOC_SCRATCH_BYTES (16 << 20)
+#define TM_NOALLOC_MAX_QUERIES 256
+tm_status tm_count_batch_noalloc(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
+                                 const tm_root_range *ranges, hipStream_t stream, uint64_t *counts_out);
 
 /* ----------------------------------------------------------------- serving
  * A request loop over one resident graph with continuous batching. Queries

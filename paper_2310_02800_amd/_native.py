@@ -30,7 +30,7 @@ EXPORTED = [
     "tm_compile_motif", "tm_free_motif", "tm_motif_source", "tm_motif_compile_check", "tm_batch_compile_check",
     "tm_generic_compile_check",
     "tm_count", "tm_enumerate",
-    "tm_work_stats", "tm_count_batch", "tm_server_start", "tm_submit_query", "tm_poll", "tm_release",
+    "tm_work_stats", "tm_count_batch", "tm_count_batch_noalloc", "tm_server_start", "tm_submit_query", "tm_poll", "tm_release",
     "tm_server_stats", "tm_server_stop",
 ]
 
@@ -132,6 +132,7 @@ def lib():
         "tm_enumerate": (i32, [P, P, P, P, P, P, ctypes.c_uint64, P]),
         "tm_work_stats": (i32, [P, P, P, P, P, P]),
         "tm_count_batch": (i32, [P, P, i32, P, P, P, P]),
+        "tm_count_batch_noalloc": (i32, [P, P, i32, P, P, P, P]),
         "tm_server_start": (i32, [P, P, P, pp]),
         "tm_submit_query": (i32, [P, P, P]),
         "tm_poll": (i32, [P, P, i32, P, i32]),

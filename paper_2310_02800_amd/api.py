@@ -387,6 +387,20 @@ class Context:
         N.check(st)
         return [int(x) for x in out[:q]]
 
+    def count_batch_noalloc(self, g: Graph, motifs: Sequence[Motif], ranges=None, stream=None):
+        """count_batch on the library's device scratch (no device allocation);
+        the batched kernel of these motifs must be loaded already."""
+        q = len(motifs)
+        arr = (ctypes.c_void_p * max(q, 1))(*[mm.handle.value if hasattr(mm.handle, "value") else mm.handle
+                                              for mm in motifs])
+        rr = None
+        if ranges is not None:
+            rr = (N.RootRange * q)(*[N.RootRange(I64_MIN if a is None else int(a), I64_MAX if b is None else int(b))
+                                     for a, b in ranges])
+        out = np.zeros(max(q, 1), np.uint64)
+        N.check(N.lib().tm_count_batch_noalloc(self._h, g.handle, q, arr, rr, _stream_handle(stream), _ptr(out)))
+        return [int(x) for x in out[:q]]
+
 
 class _DeviceRows:
     """Device memory the server owns, exposed to torch without a copy."""

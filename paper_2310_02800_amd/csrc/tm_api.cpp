@@ -276,6 +276,7 @@ tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int 
     if (a->split) a->split = 1 | (ctx->root_handoff ? 2 : 0);
     if (a->split && mode != tmo::MODE_STATS && a->nq > 0) {
         if (!w->items) {
+            if (w->no_alloc) return fail(TM_E_DEVICE, "scratch view without an item region");
             const size_t bytes = tmo::kItemsTotal * tmo::kItemWords * sizeof(uint32_t);
             HIP_TRY(hipMalloc(&w->items, bytes), "work item buffer");
             // zeroed on the launch stream: a memset on the null stream is not
@@ -287,8 +288,15 @@ tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int 
         HIP_TRY(tmo::dev_fill_u64(w->qctl, 0, 2 * (int64_t)a->nq, stream), "reset queues");
         a->items = w->items;
         a->qctl = w->qctl;
-        a->item_cap = (uint32_t)(tmo::kItemsTotal / (uint64_t)a->nq);
-        a->epoch = ++w->epoch;
+        a->item_cap = (uint32_t)(w->items_total / (uint64_t)a->nq);
+        // launch number: a ready word of an earlier launch never equals it
+        if (w->shared_epoch) {
+            uint32_t ep = w->shared_epoch->fetch_add(1) + 1;
+            if (ep == 0) ep = w->shared_epoch->fetch_add(1) + 1;  // 0 is a zeroed item's word
+            a->epoch = ep;
+        } else {
+            a->epoch = ++w->epoch;
+        }
     } else {
         a->items = nullptr;
         a->qctl = w->qctl;
@@ -296,7 +304,8 @@ tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int 
         a->epoch = 0;
     }
     void *params[] = {a};
-    const bool sampled = ctx->trace_us > 0;
+    const bool sampled = ctx->trace_us > 0 && !w->no_alloc;
+    if (w->no_alloc) timed = false;
     if (sampled) {
         if (!w->tr_stream) HIP_TRY(hipStreamCreateWithFlags(&w->tr_stream, hipStreamNonBlocking), "sampler stream");
         if (!w->tr_go) HIP_TRY(hipEventCreateWithFlags(&w->tr_go, hipEventDisableTiming), "sampler event");
@@ -599,6 +608,13 @@ tm_status tm_create(int32_t device, tm_ctx **out) {
     ctx->device = device;
     ctx->num_cus = prop.multiProcessorCount;
     ctx->compiler.device = device;
+    // the device's no-allocation scratch: its address on this device, looked
+    // up once per device with the device current
+    const hipError_t se = tmo::scratch_for_device(device, &ctx->scratch);
+    if (se != hipSuccess) {
+        delete ctx;
+        return hip_fail(se, "hipGetSymbolAddress(scratch)");
+    }
     *out = ctx;
     return TM_OK;
 }
@@ -1342,7 +1358,7 @@ tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, cons
 
 tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
                            const tm_root_range *ranges, const int64_t *budgets, int tier, hipStream_t stream,
-                           tm_ctx::Workspace *w, uint64_t *counts_out, uint8_t *cancelled) {
+                           tm_ctx::Workspace *w, uint64_t *counts_out, uint8_t *cancelled, bool no_alloc) {
     DeviceGuard dg(ctx->device);
     std::vector<const tmo::Plan *> qp(q), plans;
     for (int i = 0; i < q; i++) qp[i] = &motifs[i]->plan;
@@ -1350,9 +1366,17 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
     std::vector<tmo::Plan> gplans;
     batch_plans(qp, tier, &gplans, &plans, &fn);
     std::string err;
-    auto mod = ctx->compiler.get_batch(plans, g->key_bytes, ctx->block, &err, ctx->min_waves);
-    if (!mod) return fail(TM_E_COMPILE, err);
-    HIP_TRY(ws_prepare(w, 0, q), "workspace");
+    std::shared_ptr<tmo::Module> mod;
+    if (no_alloc) {
+        mod = ctx->compiler.find_batch(plans, g->key_bytes, ctx->block, ctx->min_waves);
+        if (!mod)
+            return fail(TM_E_INVALID, "the batched kernel of these motifs is not loaded: run tm_count_batch with "
+                                      "them once first");
+    } else {
+        mod = ctx->compiler.get_batch(plans, g->key_bytes, ctx->block, &err, ctx->min_waves);
+        if (!mod) return fail(TM_E_COMPILE, err);
+        HIP_TRY(ws_prepare(w, 0, q), "workspace");
+    }
     std::vector<int64_t> rlo(q), rhi(q);
     int64_t roots = 0, dmax = 0;
     const int64_t span = g->m ? g->t_max - g->t_min : 0;
@@ -1429,7 +1453,17 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
     tmo::LaunchCfg used;
     bool tuned = false;
     double ms = 0;
-    tm_status st = run_tuned(ctx, key, roots, once, &res, &used, &tuned, &ms);
+    tm_status st;
+    if (no_alloc) {
+        // no tuning trials (they need timing events): the tuned setting of
+        // the key if there is one, else the defaults; untimed
+        used = default_cfg(ctx);
+        tuned = ctx->autotune && roots > 0 && tune_lookup(ctx, key, &used);
+        used.timed = false;
+        st = once(used, &ms, &res);
+    } else {
+        st = run_tuned(ctx, key, roots, once, &res, &used, &tuned, &ms);
+    }
     if (st != TM_OK) return st;
     note_launch(ctx, used, tuned, ms, c0 > 0 ? 1 : 0);
     for (int i = 0; i < q; i++) {
@@ -1499,6 +1533,61 @@ tm_status tm_count_batch(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_mot
     std::vector<uint8_t> cancelled(q, 0);
     tm_status st = tmo::count_batch_impl(ctx, g, q, motifs, ranges, budgets.data(), ctx->tier, stream, lease.w,
                                          counts_out, cancelled.data());
+    if (st != TM_OK) return st;
+    const int64_t n_cancelled = std::count(cancelled.begin(), cancelled.end(), 1);
+    if (n_cancelled)
+        return fail(TM_E_CANCELLED, std::to_string(n_cancelled) + " of the queries exceeded the work budget");
+    return TM_OK;
+}
+
+// tm_count_batch on the device scratch array: no device memory, event or
+// stream is allocated. Scratch layout (256-byte aligned parts): control words,
+// per-query counts and step tallies, per-query item queue heads and tails,
+// the queries' launch arguments, then the donated-work items.
+tm_status tm_count_batch_noalloc(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
+                                 const tm_root_range *ranges, hipStream_t stream, uint64_t *counts_out) {
+    if (!ctx || !g || q < 0 || (q > 0 && (!motifs || !counts_out))) return fail(TM_E_INVALID, "bad argument");
+    if (q > tmo::kScratchMaxQueries)
+        return fail(TM_E_INVALID, "at most " + std::to_string(tmo::kScratchMaxQueries) +
+                                      " queries fit the no-allocation scratch");
+    if (q == 0) return TM_OK;
+    if (!ctx->scratch) return fail(TM_E_DEVICE, "no scratch address for this device");
+    for (int i = 0; i < q; i++) {
+        tm_status st = check_pair(ctx, g, motifs[i]);
+        if (st != TM_OK) return st;
+    }
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t o_counts = up(tmo::CTL_WORDS * sizeof(uint64_t));
+    const size_t o_qctl = o_counts + up(2 * tmo::kScratchMaxQueries * sizeof(uint64_t));
+    const size_t o_qa = o_qctl + up(2 * tmo::kScratchMaxQueries * sizeof(uint64_t));
+    const size_t o_items = o_qa + up(tmo::kScratchMaxQueries * sizeof(QArgs));
+    static_assert(tmo::kScratchBytes > (size_t(1) << 20), "scratch too small for its item region");
+    char *base = (char *)ctx->scratch;
+    // host mirrors (pageable; every copy is waited for before they go)
+    std::vector<QArgs> h_qa(q);
+    std::vector<uint64_t> h_counts(2 * (size_t)q), h_ctl(tmo::CTL_WORDS + 65);
+    tm_ctx::Workspace w;
+    w.no_alloc = true;
+    w.ctl = (uint64_t *)base;
+    w.counts = (uint64_t *)(base + o_counts);
+    w.qctl = (uint64_t *)(base + o_qctl);
+    w.qa = base + o_qa;
+    w.items = (uint32_t *)(base + o_items);
+    w.items_total = (tmo::kScratchBytes - o_items) / (tmo::kItemWords * sizeof(uint32_t));
+    w.q_cap = tmo::kScratchMaxQueries;
+    w.h_qa = h_qa.data();
+    w.h_counts = h_counts.data();
+    w.h_ctl = h_ctl.data();
+    w.shared_epoch = tmo::scratch_epoch(ctx->device);
+    std::vector<int64_t> budgets(q, ctx->work_budget);
+    std::vector<uint8_t> cancelled(q, 0);
+    tm_status st;
+    {
+        // one call at a time uses a device's scratch
+        std::lock_guard<std::mutex> lk(*tmo::scratch_mutex(ctx->device));
+        st = tmo::count_batch_impl(ctx, g, q, motifs, ranges, budgets.data(), ctx->tier, stream, &w, counts_out,
+                                   cancelled.data(), true);
+    }
     if (st != TM_OK) return st;
     const int64_t n_cancelled = std::count(cancelled.begin(), cancelled.end(), 1);
     if (n_cancelled)

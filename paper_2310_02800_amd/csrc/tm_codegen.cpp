@@ -1841,13 +1841,24 @@ std::shared_ptr<Module> Compiler::get(const Plan &p, int key_bytes, int block, s
                            [&] { return generate_source(p, key_bytes, block, min_waves, modes); }, err);
 }
 
-std::shared_ptr<Module> Compiler::get_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
-                                            std::string *err, int min_waves) {
+static std::string batch_key(const std::vector<const Plan *> &plans, int key_bytes, int block, int min_waves) {
     std::string key = "B" + std::to_string(key_bytes) + "b" + std::to_string(block) +
                       (min_waves ? "w" + std::to_string(min_waves) : std::string()) + ":";
     for (auto *p : plans) key += p->key() + "|";
-    return lookup_or_build(key, block, 0u,
+    return key;
+}
+
+std::shared_ptr<Module> Compiler::get_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
+                                            std::string *err, int min_waves) {
+    return lookup_or_build(batch_key(plans, key_bytes, block, min_waves), block, 0u,
                            [&] { return generate_batch_source(plans, key_bytes, block, min_waves); }, err);
+}
+
+std::shared_ptr<Module> Compiler::find_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
+                                             int min_waves) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(batch_key(plans, key_bytes, block, min_waves));
+    return it == cache.end() ? nullptr : it->second;
 }
 
 }  // namespace tmo

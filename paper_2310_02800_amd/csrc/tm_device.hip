@@ -17,6 +17,9 @@
 // motif level uses.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "tm_internal.h"
 
 namespace tmo {
@@ -170,6 +173,38 @@ hipError_t dev_gather_i32(int64_t n, const int32_t *eid, const int32_t *el, int3
     k_gather_i32<<<blocks_for(n), kThreads, 0, s>>>(n, eid, el, out);
     return hipGetLastError();
 }
+
+// Device scratch of tm_count_batch_noalloc, for callers that cannot allocate
+// device memory: control words, per-query counts, queue heads and launch
+// arguments, and the donated-work items, in one statically sized array each
+// device holds until the process ends. Host code uses the address
+// hipGetSymbolAddress returns for the current device, never the array's name.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+std::atomic<uint32_t> g_scratch_epoch[kMaxDevices];
+std::mutex g_scratch_use[kMaxDevices];
+}  // namespace
+
+hipError_t scratch_for_device(int device, void **out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+std::atomic<uint32_t> *scratch_epoch(int device) { return &g_scratch_epoch[device]; }
+std::mutex *scratch_mutex(int device) { return &g_scratch_use[device]; }
 
 hipError_t dev_check_ids(int64_t m, int64_t n, const int32_t *d_src, const int32_t *d_dst, uint32_t *d_bad,
                          hipStream_t s) {

@@ -9,6 +9,7 @@
 #include <memory>
 #include <mutex>
 #include <set>
+#include <atomic>
 #include <condition_variable>
 #include <string>
 #include <vector>
@@ -165,6 +166,10 @@ struct Compiler {
                                 unsigned modes);
     std::shared_ptr<Module> get_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
                                       std::string *err, int min_waves = 0);
+    // the batched module if it is already built and loaded, else null
+    // (never compiles or loads)
+    std::shared_ptr<Module> find_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
+                                       int min_waves = 0);
     // the cached module for `key`, else one built by `make` (holding the
     // kernels of `modes`, 0 = the batched kernel); concurrent callers of one
     // key share a single compile
@@ -201,6 +206,14 @@ hipError_t dev_make_keys(int64_t m, const int64_t *d_t, int64_t t_min, int key_b
 hipError_t dev_check_ids(int64_t m, int64_t n, const int32_t *d_src, const int32_t *d_dst, uint32_t *d_bad,
                          hipStream_t s);
 hipError_t dev_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+// The device scratch array of tm_count_batch_noalloc: its address on the
+// current device (looked up once per device), its launch counter and the lock
+// that serialises its users.
+constexpr size_t kScratchBytes = TM_NOALLOC_SCRATCH_BYTES;
+constexpr int kScratchMaxQueries = TM_NOALLOC_MAX_QUERIES;
+hipError_t scratch_for_device(int device, void **out);
+std::atomic<uint32_t> *scratch_epoch(int device);
+std::mutex *scratch_mutex(int device);
 // out[p] = el[eid[p]] for p < n (edge labels into adjacency order)
 hipError_t dev_gather_i32(int64_t n, const int32_t *eid, const int32_t *el, int32_t *out, hipStream_t s);
 // own scan and radix sort (tm_sort.hip). Scans: exclusive, in == out allowed,
@@ -273,8 +286,15 @@ struct tm_ctx {
         uint64_t *h_counts = nullptr;
         int q_cap = 0;
         uint64_t *qctl = nullptr;    // 2 words per query
-        uint32_t *items = nullptr;   // kItemsTotal * kItemWords, zeroed once
+        uint32_t *items = nullptr;   // items_total * kItemWords, zeroed once
+        uint64_t items_total = tmo::kItemsTotal;
         uint32_t epoch = 0;
+        // set for a view of the device scratch (tm_count_batch_noalloc): no
+        // buffer, event or stream is ever created for it, launches are never
+        // timed or sampled, and launch numbers come from one counter per
+        // device (the scratch's items outlive any one call)
+        bool no_alloc = false;
+        std::atomic<uint32_t> *shared_epoch = nullptr;
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
         // launch sampler (TM_PARAM_TRACE_US): side stream, events, pinned mirror
         hipStream_t tr_stream = nullptr;
@@ -291,6 +311,7 @@ struct tm_ctx {
     int64_t trace_us = 0;     // launch sampling period (0 = off)
     int root_handoff = 1;     // hand unstarted roots to waiting wavefronts once the queue is empty
     std::vector<int64_t> trace;  // samples of the last sampled launch, kTraceCols each
+    void *scratch = nullptr;     // this device's no-allocation scratch (tm_count_batch_noalloc)
 };
 
 struct tm_graph {
@@ -344,9 +365,12 @@ using RowAlloc = std::function<int64_t *(uint64_t rows, uint64_t *capacity, tm_s
 tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range, int tier,
                          int64_t budget, hipStream_t stream, tm_ctx::Workspace *w, const RowAlloc &alloc,
                          uint64_t *n_out, int64_t **rows_out);
+// no_alloc: the workspace is a view of the device scratch; the batched module
+// must already be loaded (TM_E_INVALID otherwise) and the launch uses the
+// key's tuned setting or the defaults, untimed, with no tuning trials.
 tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_motif *const *motifs,
                            const tm_root_range *ranges, const int64_t *budgets, int tier, hipStream_t stream,
-                           tm_ctx::Workspace *w, uint64_t *counts_out, uint8_t *cancelled);
+                           tm_ctx::Workspace *w, uint64_t *counts_out, uint8_t *cancelled, bool no_alloc = false);
 tm_ctx::Workspace *ws_acquire(tm_ctx *ctx);
 void ws_release(tm_ctx *ctx, tm_ctx::Workspace *w);
 tm_status set_error(tm_status st, const std::string &msg);
