@@ -585,8 +585,10 @@ def main():
                     help="skip the 4-cycle with added constraints (gaps, anti-edge)")
     ap.add_argument("--serve-queries", type=int, default=10_000,
                     help="queries of the served stream to run (0 = skip; the full stream has 10,000)")
-    ap.add_argument("--serve-rate-queries", type=int, default=0,
-                    help="queries of the stream served at the Poisson rate for latency (0 = all of them)")
+    ap.add_argument("--serve-rate-queries", type=int, default=2000,
+                    help="queries of the stream served at the Poisson rate for latency (0 = all of them); the "
+                         "default keeps that pass to about a minute, the capacity and plain passes run the whole "
+                         "stream")
     ap.add_argument("--serve-only", action="store_true", help="run only the served stream and print its JSON")
     ap.add_argument("--query-only", type=int, default=None,
                     help="time only headline query i (0..5: 3-cycle, 4-cycle, out-star at 3600 s, then at 86400 s) "

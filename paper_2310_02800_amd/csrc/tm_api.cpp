@@ -1147,10 +1147,9 @@ tm_status tm_batch_compile_check(const tm_motif_desc *descs, int32_t q, int32_t 
     std::vector<int> fn;
     std::vector<tmo::Plan> gplans;
     batch_plans(qp, tier, &gplans, &mods, &fn);
-    const std::string src = tmo::generate_batch_source(mods, key_bytes, 256);
     std::vector<char> code;
     std::string err;
-    if (!tmo::cached_code(src, &code, &err)) return fail(TM_E_COMPILE, err);
+    if (!tmo::batch_code(mods, key_bytes, tmo::kDefaultBlock, 0, &code, &err)) return fail(TM_E_COMPILE, err);
     if (code_bytes) *code_bytes = (int64_t)code.size();
     return TM_OK;
 }
@@ -1171,19 +1170,14 @@ tm_status tm_motif_compile_check(const tm_motif_desc *descs, int32_t q, int32_t 
 tm_status tm_generic_compile_check(int32_t l, int32_t key_bytes, int64_t *code_bytes) {
     if (l < 0 || l > TM_MAX_EDGES) return fail(TM_E_INVALID, "motif length out of range");
     if (key_bytes != 4 && key_bytes != 8) return fail(TM_E_INVALID, "key_bytes must be 4 or 8");
-    std::string src;
-    if (l > 0) {
-        return compile_groups(tmo::generic_plan(l), key_bytes, code_bytes);
-    } else {
-        std::vector<tmo::Plan> gplans;
-        for (int k = 1; k <= TM_MAX_EDGES; k++) gplans.push_back(tmo::generic_plan(k));
-        std::vector<const tmo::Plan *> ptrs;
-        for (auto &gp : gplans) ptrs.push_back(&gp);
-        src = tmo::generate_batch_source(ptrs, key_bytes, 256);
-    }
+    if (l > 0) return compile_groups(tmo::generic_plan(l), key_bytes, code_bytes);
+    std::vector<tmo::Plan> gplans;
+    for (int k = 1; k <= TM_MAX_EDGES; k++) gplans.push_back(tmo::generic_plan(k));
+    std::vector<const tmo::Plan *> ptrs;
+    for (auto &gp : gplans) ptrs.push_back(&gp);
     std::vector<char> code;
     std::string err;
-    if (!tmo::cached_code(src, &code, &err)) return fail(TM_E_COMPILE, err);
+    if (!tmo::batch_code(ptrs, key_bytes, tmo::kDefaultBlock, 0, &code, &err)) return fail(TM_E_COMPILE, err);
     if (code_bytes) *code_bytes = (int64_t)code.size();
     return TM_OK;
 }

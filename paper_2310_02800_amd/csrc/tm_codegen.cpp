@@ -231,6 +231,10 @@ struct QArgs {
   unsigned char pop[12], plev[12];
 };
 
+// Query arguments are read-only during a launch and uniform per wavefront; in the
+// constant address space the compiler reads them with scalar loads.
+typedef const __attribute__((address_space(4))) QArgs* qptr;
+
 struct GArgs {
   const int* src; const int* dst; const tkey* tk; const float* w;
   const tkey* adj_t; const int* adj_nbr; const int* adj_eid; const float* adj_w;
@@ -294,7 +298,7 @@ __device__ __forceinline__ bool pred_ok(float w, int op, float th) {
   return op == 0 ? (w >= th) : op == 1 ? (w > th) : op == 2 ? (w <= th) : (w < th);
 }
 // every weight predicate of level lv holds (table-driven matchers)
-__device__ __forceinline__ bool preds_at(const QArgs* q, int lv, float w) {
+__device__ __forceinline__ bool preds_at(qptr q, int lv, float w) {
   bool ok = true;
   for (int j = 0; j < q->npred; ++j)
     if (q->plev[j] == lv) ok = ok && pred_ok(w, q->pop[j], q->pth[j]);
@@ -497,6 +501,13 @@ struct Emitter {
         return false;
     }
     std::string e_cond(int j) const { return keep_e(j) ? "true" : "MODE == 3"; }
+    // The root edge id: written with each instance, and read by an anti-edge
+    // attached to the root edge that is checked at a deeper level.
+    std::string root_cond() const {
+        for (int x = 0; x < p.n_anti; x++)
+            if (p.anti_at[x] == 0 && p.anti_lvl[x] > 0) return "true";
+        return "MODE == 3";
+    }
     // Graph node of motif node v while level i's candidate is checked.
     std::string node_at(int i, int v) const {
         if (i == 0) return v == p.a[0] ? "s" : "d";
@@ -744,7 +755,8 @@ struct Emitter {
         o << "            const int srcl = thief ? nth_bit(donors, rt) : lane;\n";
         o << "            const int t_dj = shf(dj, srcl); const u32 t_ds = shf(ds, srcl), t_de = shf(de, srcl);\n";
         o << "            const tkey t_dh = shf(dh, srcl); const int t_dw = shf(dw, srcl);\n";
-        o << "            const int t_root = shf(root, srcl); const i64 t_mych = shf(mych, srcl);\n";
+        o << "            const int t_root = " << root_cond() << " ? shf(root, srcl) : 0;\n";
+        o << "            const i64 t_mych = MODE >= 2 ? shf(mych, srcl) : 0;\n";
         o << "            const tkey t_tmax = shf(tmaxk, srcl);\n";
         for (int v = 0; v < K; v++) o << "            const int t_m" << v << " = shf(m" << v << ", srcl);\n";
         for (int j = 1; j + 1 < L; j++)
@@ -823,11 +835,13 @@ struct Emitter {
         o << ind << "if (item_ready(g, it)) {\n";
         o << ind << "  const int j = (int)ld_ag(it + 1);\n";
         // level 0: a handed root, which the lane fetches at its next refill
-        o << ind << "  if (j == 0) { proot = (int)ld_ag(it + 7); pmy = ld_ag64(it + 8); lvl = 0; ph = 0; base = 1; exact = 0u; }\n";
+        o << ind << "  if (j == 0) { proot = (int)ld_ag(it + 7); if (MODE >= 2) pmy = ld_ag64(it + 8); lvl = 0; ph = 0; base = 1; exact = 0u; }\n";
         o << ind << "  else {\n";
         o << ind << "  lvl = j; base = j; ph = 0; exact = 1u << j;\n";
         if (leaf_cache()) o << ind << "  lq = false;\n";
-        o << ind << "  root = (int)ld_ag(it + 7); mych = ld_ag64(it + 8); tmaxk = (tkey)ld_ag64(it + 10);\n";
+        o << ind << "  if (" << root_cond() << ") root = (int)ld_ag(it + 7);\n";
+        o << ind << "  if (MODE >= 2) mych = ld_ag64(it + 8);\n";
+        o << ind << "  tmaxk = (tkey)ld_ag64(it + 10);\n";
         for (int v = 0; v < K; v++) o << ind << "  m" << v << " = (int)ld_ag(it + " << 12 + v << ");\n";
         for (int j = 1; j + 1 < L; j++)
             o << ind << "  if (" << e_cond(j) << ") e" << j << " = (int)ld_ag(it + " << 19 + j << ");\n";
@@ -1138,7 +1152,7 @@ struct Emitter {
               << "(const GArgs& g, int qi, i64 chunk, i64 ih, int in) {\n";
         }
         o << "  const int lane = lane_id();\n";
-        o << "  const QArgs* q = g.qa + qi;\n";
+        o << "  const qptr q = (qptr)(g.qa + qi);  // uniform: scalar loads\n";
         o << "  const i64 q_r0 = q->r0, q_delta = q->delta, q_c0 = q->c0, q_c1 = q->c0 + q->nchunks;\n";
         o << "  // chunk j of a query holds its roots j, j + nchunks, j + 2 nchunks, ...: a burst of\n";
         o << "  // consecutive heavy roots spreads over many wavefronts\n";
@@ -1198,7 +1212,7 @@ struct Emitter {
         }
         o << "  u32 iter = 0u, steps = 0u; i64 ghungry = 0;\n";
         o << "  int proot = -1; i64 pmy = 0;  // a root handed to this lane (tail redistribution)\n";
-        o << "  u32 dchk = 0u;\n";
+        o << "  u32 dchk = 0u, dcur = 0u;  // queue-cursor look: step counter, value read (lane 0)\n";
         o << "  i64 pnext = 0, pend = 0, pchunk = chunk, pending = -1;\n";
         o << "  bool drained = chunk < 0;\n";
         o << "  if (chunk >= 0) {\n";
@@ -1264,7 +1278,9 @@ struct Emitter {
             if (anti_on(0)) o << "          ok = ok && " << anti_cond(0) << ";\n";
         }
         o << "          if (ok) {\n";
-        o << "            root = r; mych = myc; base = 1;\n";
+        o << "            base = 1;\n";
+        o << "            if (" << root_cond() << ") root = r;\n";
+        o << "            if (MODE >= 2) mych = myc;  // its chunk orders the instances\n";
         if (L == 1) {
             leaf("            ", "0");
             o << "            if (MODE == 2 && rcnt) { atomicAdd(&g.chunk_cnt[mych], rcnt); cnt += rcnt; rcnt = 0; }\n";
@@ -1299,14 +1315,15 @@ struct Emitter {
         o << "    }\n";
         // A wavefront still working through its chunk learns that the whole
         // root queue is empty (it only fetches again once its pool is used
-        // up): a relaxed look at the queue cursor every 64 steps. From then
-        // on it splits pending work and hands out unstarted roots.
+        // up): a relaxed look at the queue cursor every 256 steps, read one
+        // step after it is issued so that the wavefront does not wait on the
+        // contended line. From then on it splits pending work and hands out
+        // unstarted roots.
         if (L > 1) {
-            o << "    if (q_split && !drained && g.items != 0 && ((++dchk & 63u) == 0u)) {\n";
-            o << "      i64 cc = 0;\n";
-            o << "      if (lane == 0) cc = (i64)ld_rlx64(&g.ctl[0]);\n";
-            o << "      cc = bcast64(cc);\n";
-            o << "      if (cc >= g.total_chunks) drained = true;  // no chunk of any query is left\n";
+            o << "    if (q_split && !drained && g.items != 0) {\n";
+            o << "      const u32 dk = ++dchk & 255u;\n";
+            o << "      if (dk == 0u) { if (lane == 0) { const u64 v = ld_rlx64(&g.ctl[0]); dcur = v < 0xffffffffull ? (u32)v : 0xffffffffu; } }\n";
+            o << "      else if (dk == 1u && (i64)(u32)__builtin_amdgcn_readfirstlane((int)dcur) >= g.total_chunks) drained = true;  // no chunk of any query is left\n";
             o << "    }\n";
             steal();
         }
@@ -1780,13 +1797,64 @@ bool cached_code(const std::string &src, std::vector<char> *code, std::string *e
 }
 
 // `modes` as for emit_kernels: the kernels the module holds.
-static bool compile_module(const std::string &src, int block, unsigned modes, Module *out, std::string *err) {
+// An unsigned field of the first kernel's metadata in a code object: the
+// metadata note is MessagePack, where the field name is a short string (one
+// prefix byte 0xa0 | length) followed by the value as a positive fixint or a
+// uint8/16/32. -1 when absent.
+static long meta_uint(const std::vector<char> &code, const char *field) {
+    const size_t n = std::strlen(field);
+    std::string pat(1, (char)(0xa0u | (unsigned)n));
+    pat += field;
+    auto it = std::search(code.begin(), code.end(), pat.begin(), pat.end());
+    if (it == code.end()) return -1;
+    const size_t i = (size_t)(it - code.begin()) + pat.size();
+    if (i >= code.size()) return -1;
+    const unsigned char b = (unsigned char)code[i];
+    auto be = [&](int k) {
+        if (i + (size_t)k >= code.size()) return -1L;
+        long v = 0;
+        for (int j = 1; j <= k; j++) v = (v << 8) | (unsigned char)code[i + j];
+        return v;
+    };
+    if (b < 0x80) return b;
+    if (b == 0xcc) return be(1);
+    if (b == 0xcd) return be(2);
+    if (b == 0xce) return be(4);
+    return -1;
+}
+
+// Waves per SIMD that `vgprs` registers per lane leave room for on gfx950
+// (512 registers per lane across the SIMD's waves, allocated in granules of 8).
+static int waves_for(long vgprs) {
+    const long a = (vgprs + 7) / 8 * 8;
+    return a <= 0 ? 8 : (int)std::min(8L, 512 / a);
+}
+
+bool batch_code(const std::vector<const Plan *> &plans, int key_bytes, int block, int min_waves,
+                std::vector<char> *code, std::string *err) {
+    if (!cached_code(generate_batch_source(plans, key_bytes, block, min_waves), code, err)) return false;
+    if (min_waves != 0) return true;
+    // A batched kernel a few registers above a wave boundary runs one wave
+    // more per SIMD when compiled to fit it (the persistent kernel hides its
+    // dependent loads with waves); kept if the squeeze spills little.
+    const long v = meta_uint(*code, ".vgpr_count");
+    const int w = waves_for(v);
+    if (v < 0 || w >= 8) return true;
+    const long fit = (512 / (w + 1)) / 8 * 8;
+    if (v - fit > kSqueezeRegs) return true;
+    std::vector<char> c2;
+    std::string e2;
+    if (!cached_code(generate_batch_source(plans, key_bytes, block, w + 1), &c2, &e2)) return true;
+    const long spill = meta_uint(c2, ".vgpr_spill_count");
+    if (spill < 0 || spill > kSqueezeSpills) return true;
+    code->swap(c2);
+    return true;
+}
+
+static bool compile_module(const std::vector<char> &code, int block, unsigned modes, Module *out, std::string *err) {
     const bool batch = modes == 0;
     const char *const *names = batch ? &kBatchName : kSingleNames;
     const int nmodes = batch ? 1 : 4;
-    auto t0 = std::chrono::steady_clock::now();
-    std::vector<char> code;
-    if (!cached_code(src, &code, err)) return false;
     hipError_t he = hipModuleLoadData(&out->mod, code.data());
     if (he != hipSuccess) {
         *err = std::string("hipModuleLoadData: ") + hipGetErrorString(he);
@@ -1807,12 +1875,11 @@ static bool compile_module(const std::string &src, int block, unsigned modes, Mo
     for (int mode = 0; mode < MODE_COUNT_ && !any; mode++) any = out->fn[mode];
     if (any && hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, any, block, 0) == hipSuccess)
         out->max_blocks_per_cu = nb;
-    out->compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return true;
 }
 
 std::shared_ptr<Module> Compiler::lookup_or_build(const std::string &key, int block, unsigned modes,
-                                                  const std::function<std::string()> &make, std::string *err) {
+                                                  const CodeFn &make, std::string *err) {
     {
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
@@ -1824,7 +1891,10 @@ std::shared_ptr<Module> Compiler::lookup_or_build(const std::string &key, int bl
         inflight.insert(key);
     }
     auto m = std::make_shared<Module>();
-    const bool ok = compile_module(make(), block, modes, m.get(), err);
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<char> code;
+    const bool ok = make(&code, err) && compile_module(code, block, modes, m.get(), err);
+    m->compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     std::lock_guard<std::mutex> lk(mu);
     inflight.erase(key);
     if (ok) cache[key] = m;
@@ -1837,8 +1907,9 @@ std::shared_ptr<Module> Compiler::get(const Plan &p, int key_bytes, int block, s
     const std::string key = "S" + std::to_string(key_bytes) + "b" + std::to_string(block) +
                             (min_waves ? "w" + std::to_string(min_waves) : std::string()) + "m" +
                             std::to_string(modes) + ":" + p.key();
-    return lookup_or_build(key, block, modes,
-                           [&] { return generate_source(p, key_bytes, block, min_waves, modes); }, err);
+    return lookup_or_build(key, block, modes, [&](std::vector<char> *code, std::string *e) {
+        return cached_code(generate_source(p, key_bytes, block, min_waves, modes), code, e);
+    }, err);
 }
 
 static std::string batch_key(const std::vector<const Plan *> &plans, int key_bytes, int block, int min_waves) {
@@ -1851,7 +1922,9 @@ static std::string batch_key(const std::vector<const Plan *> &plans, int key_byt
 std::shared_ptr<Module> Compiler::get_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
                                             std::string *err, int min_waves) {
     return lookup_or_build(batch_key(plans, key_bytes, block, min_waves), block, 0u,
-                           [&] { return generate_batch_source(plans, key_bytes, block, min_waves); }, err);
+                           [&](std::vector<char> *code, std::string *e) {
+                               return batch_code(plans, key_bytes, block, min_waves, code, e);
+                           }, err);
 }
 
 std::shared_ptr<Module> Compiler::find_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,

@@ -173,8 +173,10 @@ struct Compiler {
     // the cached module for `key`, else one built by `make` (holding the
     // kernels of `modes`, 0 = the batched kernel); concurrent callers of one
     // key share a single compile
-    std::shared_ptr<Module> lookup_or_build(const std::string &key, int block, unsigned modes,
-                                            const std::function<std::string()> &make, std::string *err);
+    // produces a module's code object (from the on-disk cache or by compiling)
+    using CodeFn = std::function<bool(std::vector<char> *code, std::string *err)>;
+    std::shared_ptr<Module> lookup_or_build(const std::string &key, int block, unsigned modes, const CodeFn &make,
+                                            std::string *err);
 };
 
 constexpr int kDefaultBlock = 256;  // threads per workgroup of the mining kernels
@@ -191,6 +193,12 @@ std::string generate_batch_source(const std::vector<const Plan *> &plans, int ke
 bool build_plan(const tm_motif_desc *d, Plan *p, int64_t *gaps, std::string *err);
 bool compile_to_code(const std::string &src, std::vector<char> *code, std::string *err);
 bool cached_code(const std::string &src, std::vector<char> *code, std::string *err);
+// Code of a batched module. min_waves 0: compiled as is, then again to fit one
+// more wave per SIMD when that needs at most kSqueezeRegs fewer registers and
+// spills at most kSqueezeSpills (the second build is used then).
+constexpr int kSqueezeRegs = 8, kSqueezeSpills = 8;
+bool batch_code(const std::vector<const Plan *> &plans, int key_bytes, int block, int min_waves,
+                std::vector<char> *code, std::string *err);
 
 // device helpers (tm_device.hip)
 hipError_t dev_build_pairs(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
