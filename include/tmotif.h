@@ -129,6 +129,23 @@ void tm_destroy(tm_ctx *ctx);
  *                          gone, a wavefront whose chunk still holds 16 or more unstarted
  *                          roots hands the last half of them, one per work item, to
  *                          waiting wavefronts (tail redistribution, Sec. 5.2.2); 0 = never
+ *   TM_PARAM_HUB_LDS       0 (default) = off; 1 = every workgroup of a mining kernel
+ *                          first copies the graph's hub table into LDS: for the
+ *                          longest adjacency lists (up to 64, chosen longest first
+ *                          at load time while the table fits 28 KiB), time keys
+ *                          sampled every 2^k positions (k >= 5, at most 512 per
+ *                          list). A window opened over such a list is first located
+ *                          among its samples in LDS, and the search in HBM then
+ *                          covers one stride (candidate caching, Sec. 5.1.1).
+ *                          Results are identical either way; see
+ *                          tm_graph_info.hub_lists
+ *   TM_PARAM_STEP_FORM     loop step of the generated kernels (results are the same):
+ *                          0 = the search probe and the candidate scan are separate
+ *                          branches, each waiting for its own reads, and binding a
+ *                          candidate opens the next level's window at once; 1 = each
+ *                          step issues the reads of all lanes (search pivots,
+ *                          candidate key and neighbour, list offsets of a level to
+ *                          open) before using any, one wait per step
  *   TM_PARAM_TRACE_US      0 (default) = off; 10..100000 = while each mining kernel
  *                          runs, sample its control words every this many
  *                          microseconds from a side stream (the kernel is not
@@ -148,7 +165,9 @@ enum {
     TM_PARAM_MIN_WAVES = 11,
     TM_PARAM_LEAF_MIN = 12,
     TM_PARAM_TRACE_US = 13,
-    TM_PARAM_ROOT_HANDOFF = 14
+    TM_PARAM_ROOT_HANDOFF = 14,
+    TM_PARAM_HUB_LDS = 15,
+    TM_PARAM_STEP_FORM = 16
 };
 tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t value);
 
@@ -233,6 +252,8 @@ typedef struct {
     int32_t was_sorted;      /* 1 if the input was already in non-decreasing time order */
     int32_t has_labels;      /* 1 once vertex labels are attached */
     int32_t has_edge_labels; /* 1 once edge labels are attached */
+    int32_t hub_lists;       /* adjacency lists in the hub table (TM_PARAM_HUB_LDS) */
+    int32_t hub_bytes;       /* the table's size: the LDS each workgroup stages */
 } tm_graph_info;
 tm_status tm_graph_get_info(const tm_graph *g, tm_graph_info *info);
 

@@ -20,6 +20,8 @@ TM_PARAM_BLOCK, TM_PARAM_ROOT_CHUNK, TM_PARAM_GRID = 1, 2, 3
 TM_PARAM_PROFILE, TM_PARAM_SPLIT, TM_PARAM_SPLIT_MIN, TM_PARAM_TIER, TM_PARAM_AUTOTUNE = 5, 6, 7, 8, 9
 TM_PARAM_WORK_BUDGET, TM_PARAM_MIN_WAVES, TM_PARAM_LEAF_MIN, TM_PARAM_TRACE_US = 10, 11, 12, 13
 TM_PARAM_ROOT_HANDOFF = 14
+TM_PARAM_HUB_LDS = 15
+TM_PARAM_STEP_FORM = 16
 
 # Every function the header declares, for the export check.
 EXPORTED = [
@@ -74,7 +76,7 @@ class GraphInfo(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64), ("n_edges", ctypes.c_int64), ("t_min", ctypes.c_int64),
                 ("t_max", ctypes.c_int64), ("key_bytes", ctypes.c_int32), ("has_weights", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64), ("was_sorted", ctypes.c_int32), ("has_labels", ctypes.c_int32),
-                ("has_edge_labels", ctypes.c_int32)]
+                ("has_edge_labels", ctypes.c_int32), ("hub_lists", ctypes.c_int32), ("hub_bytes", ctypes.c_int32)]
 
 
 _lib = None

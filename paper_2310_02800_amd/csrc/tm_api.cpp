@@ -47,7 +47,7 @@ struct DeviceGuard {
 void free_graph_buffers(tm_graph *g) {
     void *ptrs[] = {g->d_src, g->d_dst, g->d_tk, g->d_w, g->d_adj_t, g->d_adj_nbr, g->d_adj_eid, g->d_adj_w,
                     g->d_off_out, g->d_off_in, g->d_pos_out, g->d_pos_in, g->d_pr_nbr, g->d_pr_t, g->d_pr_pos,
-                    g->d_nlab, g->d_el, g->d_adj_el};
+                    g->d_nlab, g->d_el, g->d_adj_el, g->d_hub};
     for (void *p : ptrs)
         if (p) hipFree(p);
 }
@@ -192,7 +192,7 @@ void fill_qargs(const tm_graph *g, const tm_motif *m, int64_t r0, int64_t r1, in
     tmo::fill_plan_tables(p, q);
 }
 
-GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w, const tmo::LaunchCfg &c) {
+GArgs base_args(const tm_ctx *ctx, const tm_graph *g, tm_ctx::Workspace *w, const tmo::LaunchCfg &c) {
     GArgs a;
     std::memset(&a, 0, sizeof(a));
     a.src = g->d_src;
@@ -221,12 +221,18 @@ GArgs base_args(const tm_graph *g, tm_ctx::Workspace *w, const tmo::LaunchCfg &c
     a.m_edges = g->m;
     a.split = c.split;
     a.leaf_min = (int32_t)c.leaf_min;
+    if (ctx->hub_lds && g->d_hub) {
+        a.hub = g->d_hub;
+        a.hub_words = g->hub_words;
+        a.hub_dmin = g->hub_dmin;
+    }
     return a;
 }
 
-int grid_for(tm_ctx *ctx, const tmo::Module *mod) {
+int grid_for(tm_ctx *ctx, const tmo::Module *mod, uint32_t lds_bytes) {
     if (ctx->grid > 0) return (int)ctx->grid;
     int per_cu = mod->max_blocks_per_cu > 0 ? mod->max_blocks_per_cu : 1;
+    if (lds_bytes > 0) per_cu = std::max(1, std::min(per_cu, (int)(tmo::kLdsPerCu / lds_bytes)));
     return std::max(1, per_cu * std::max(ctx->num_cus, 1));
 }
 
@@ -303,6 +309,9 @@ tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int 
         a->item_cap = 0;
         a->epoch = 0;
     }
+    // the work-counter mode follows the byte model (full searches): no staging
+    if (mode == tmo::MODE_STATS) { a->hub = nullptr; a->hub_words = 0; a->hub_dmin = 0; }
+    const uint32_t lds = a->hub_words * 4u;
     void *params[] = {a};
     const bool sampled = ctx->trace_us > 0 && !w->no_alloc;
     if (w->no_alloc) timed = false;
@@ -314,7 +323,7 @@ tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int 
         HIP_TRY(hipEventRecord(w->tr_go, stream), "hipEventRecord");  // after the control words are reset
     }
     if (timed) HIP_TRY(hipEventRecord(w->ev0, stream), "hipEventRecord");
-    HIP_TRY(hipModuleLaunchKernel(fn, grid_for(ctx, mod), 1, 1, ctx->block, 1, 1, 0, stream, params, nullptr),
+    HIP_TRY(hipModuleLaunchKernel(fn, grid_for(ctx, mod, lds), 1, 1, ctx->block, 1, 1, lds, stream, params, nullptr),
             "hipModuleLaunchKernel");
     if (timed) HIP_TRY(hipEventRecord(w->ev1, stream), "hipEventRecord");
     if (sampled) return sample_launch(ctx, w, a->total_chunks, stream);
@@ -373,7 +382,7 @@ tm_status get_module(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, int tier
     std::string err;
     const tmo::Plan gp = tmo::generic_plan(m->plan.l);
     auto mod = ctx->compiler.get(use_generic(tier, m) ? gp : m->plan, g->key_bytes, ctx->block, &err,
-                                 ctx->min_waves, tmo::mode_group(mode));
+                                 ctx->min_waves, tmo::mode_group(mode), ctx->step_form);
     if (!mod) return fail(TM_E_COMPILE, err);
     *out = mod;
     return TM_OK;
@@ -394,7 +403,7 @@ tm_status run_single(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm
     *chunks_out = chunks;
     *r0_out = r0;
     if (chunks == 0) return TM_OK;
-    GArgs a = base_args(g, w, cfg);
+    GArgs a = base_args(ctx, g, w, cfg);
     a.total_chunks = chunks;
     a.rch = (int32_t)rch;
     a.nq = 1;
@@ -699,6 +708,14 @@ tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t v) {
         if (v != 0 && v != 1) return fail(TM_E_INVALID, "root handoff must be 0 or 1");
         ctx->root_handoff = (int)v;
         return TM_OK;
+    case TM_PARAM_HUB_LDS:
+        if (v != 0 && v != 1) return fail(TM_E_INVALID, "hub staging must be 0 or 1");
+        ctx->hub_lds = (int)v;
+        return TM_OK;
+    case TM_PARAM_STEP_FORM:
+        if (v != 0 && v != 1) return fail(TM_E_INVALID, "step form must be 0 or 1");
+        ctx->step_form = (int)v;
+        return TM_OK;
     default:
         return fail(TM_E_INVALID, "unknown parameter");
     }
@@ -720,6 +737,8 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *v) {
     case TM_PARAM_LEAF_MIN: *v = ctx->leaf_min; return TM_OK;
     case TM_PARAM_TRACE_US: *v = ctx->trace_us; return TM_OK;
     case TM_PARAM_ROOT_HANDOFF: *v = ctx->root_handoff; return TM_OK;
+    case TM_PARAM_HUB_LDS: *v = ctx->hub_lds; return TM_OK;
+    case TM_PARAM_STEP_FORM: *v = ctx->step_form; return TM_OK;
     default: return fail(TM_E_INVALID, "unknown parameter");
     }
 }
@@ -823,6 +842,76 @@ tm_status tm_last_kernel_ms(tm_ctx *ctx, double *ms, int32_t *launches) {
 }
 
 // ------------------------------------------------------------------- graph
+
+// Hub-list sample table, staged in LDS by every workgroup of a mining kernel
+// when TM_PARAM_HUB_LDS is on (a search index for the windows over the longest
+// adjacency lists, Sec. 5.1.1). Words: [0] hub count H; [1, 1+H) list starts
+// (positions in the unified adjacency, ascending); [1+H, 2+2H) sample offsets;
+// [2+2H, 2+3H) log2 strides; samples (time keys) from word 2+3H rounded up to
+// even. The lists are chosen longest first while the table fits kHubMaxWords.
+static hipError_t build_hub_table(tm_graph *g, hipStream_t s, int64_t *acc) {
+    const int64_t n = g->n;
+    if (g->m < (int64_t)tmo::kHubMinLen) return hipSuccess;
+    std::vector<uint32_t> oo(n + 1), oi(n + 1);
+    hipError_t e = hipMemcpyAsync(oo.data(), g->d_off_out, (n + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(oi.data(), g->d_off_in, (n + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    struct L { uint32_t len, start; };
+    std::vector<L> cand;
+    for (int64_t v = 0; v < n; v++) {
+        if (oo[v + 1] - oo[v] >= tmo::kHubMinLen) cand.push_back({oo[v + 1] - oo[v], oo[v]});
+        if (oi[v + 1] - oi[v] >= tmo::kHubMinLen) cand.push_back({oi[v + 1] - oi[v], oi[v]});
+    }
+    std::sort(cand.begin(), cand.end(), [](const L &a, const L &b) { return a.len != b.len ? a.len > b.len : a.start < b.start; });
+    const uint32_t kw = (uint32_t)g->key_bytes / 4u;  // words per key
+    std::vector<L> hubs;
+    std::vector<uint32_t> lgs, cnts;
+    uint32_t total = 0;
+    for (const L &c : cand) {
+        if (hubs.size() == tmo::kHubMaxLists) break;
+        uint32_t lg = 5;
+        while (((c.len + (1u << lg) - 1) >> lg) > tmo::kHubSamplesPerList) lg++;
+        const uint32_t k = (c.len + (1u << lg) - 1) >> lg;
+        const uint32_t H = (uint32_t)hubs.size() + 1;
+        const uint32_t words = ((2 + 3 * H + 1) & ~1u) + (total + k) * kw;
+        if (words > tmo::kHubMaxWords) break;
+        hubs.push_back(c);
+        lgs.push_back(lg);
+        cnts.push_back(k);
+        total += k;
+    }
+    if (hubs.empty()) return hipSuccess;
+    const uint32_t H = (uint32_t)hubs.size();
+    uint32_t dmin = hubs.back().len;
+    // sort by start for the lookup; offsets follow that order
+    std::vector<uint32_t> ord(H);
+    for (uint32_t h = 0; h < H; h++) ord[h] = h;
+    std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return hubs[a].start < hubs[b].start; });
+    const uint32_t base = (2 + 3 * H + 1) & ~1u;
+    const uint32_t words = base + total * kw;
+    std::vector<uint32_t> tab(base, 0u);
+    tab[0] = H;
+    uint32_t off = 0;
+    for (uint32_t j = 0; j < H; j++) {
+        const uint32_t h = ord[j];
+        tab[1 + j] = hubs[h].start;
+        tab[1 + H + j] = off;
+        tab[2 + 2 * H + j] = lgs[h];
+        off += cnts[h];
+    }
+    tab[1 + 2 * H] = off;
+    e = dmalloc(&g->d_hub, words, acc);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->d_hub, tab.data(), base * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = tmo::dev_hub_samples(g->d_hub, base, total, g->d_adj_t, g->key_bytes, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host table is freed on return
+    if (e != hipSuccess) return e;
+    g->hub_words = words;
+    g->hub_dmin = dmin;
+    g->hub_lists = (int32_t)H;
+    return hipSuccess;
+}
 
 tm_status tm_load_graph(tm_ctx *ctx, int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const int64_t *t,
                         const float *w, uint32_t flags, tm_graph **out) {
@@ -946,6 +1035,8 @@ tm_status tm_load_graph(tm_ctx *ctx, int64_t n, int64_t m, const int32_t *src, c
         e = tmo::dev_build_pairs(n, m, g->d_dst, g->d_src, g->d_tk, g->key_bytes, g->d_pr_nbr + m,
                                  (char *)g->d_pr_t + m * g->key_bytes, g->d_pos_in, (uint32_t)m, g->d_pr_pos, s);
     if (e != hipSuccess) return cleanup(hip_fail(e, "pair list build"));
+    e = build_hub_table(g, s, &acc);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hub table build"));
     g->device_bytes = acc;
     hipStreamDestroy(s);
     *out = g;
@@ -972,6 +1063,8 @@ tm_status tm_graph_get_info(const tm_graph *g, tm_graph_info *info) {
     info->was_sorted = g->was_sorted ? 1 : 0;
     info->has_labels = g->has_labels ? 1 : 0;
     info->has_edge_labels = g->has_edge_labels ? 1 : 0;
+    info->hub_lists = g->hub_lists;
+    info->hub_bytes = (int32_t)(g->hub_words * 4u);
     return TM_OK;
 }
 
@@ -1085,7 +1178,7 @@ tm_status tm_compile_motif(tm_ctx *ctx, const tm_motif_desc *desc, tm_motif **ou
     // here; with the generic tier this is the shared module of the motif length
     const tmo::Plan gp = tmo::generic_plan(m->plan.l);
     if (!ctx->compiler.get(use_generic(ctx->tier, m) ? gp : m->plan, 4, ctx->block, &err, ctx->min_waves,
-                           tmo::mode_group(tmo::MODE_COUNT))) {
+                           tmo::mode_group(tmo::MODE_COUNT), ctx->step_form)) {
         delete m;
         return fail(TM_E_COMPILE, err);
     }
@@ -1326,7 +1419,7 @@ tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, cons
     HIP_TRY(tmo::dev_fill_u64(w->chunk_cnt, 0, chunks, stream), "reset cursors");
     HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload query");
     HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 2, stream), "reset count");
-    GArgs a = base_args(g, w, cfg);
+    GArgs a = base_args(ctx, g, w, cfg);
     a.total_chunks = chunks;
     a.rch = (int32_t)rch;
     a.nq = 1;
@@ -1362,12 +1455,12 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
     std::string err;
     std::shared_ptr<tmo::Module> mod;
     if (no_alloc) {
-        mod = ctx->compiler.find_batch(plans, g->key_bytes, ctx->block, ctx->min_waves);
+        mod = ctx->compiler.find_batch(plans, g->key_bytes, ctx->block, ctx->min_waves, ctx->step_form);
         if (!mod)
             return fail(TM_E_INVALID, "the batched kernel of these motifs is not loaded: run tm_count_batch with "
                                       "them once first");
     } else {
-        mod = ctx->compiler.get_batch(plans, g->key_bytes, ctx->block, &err, ctx->min_waves);
+        mod = ctx->compiler.get_batch(plans, g->key_bytes, ctx->block, &err, ctx->min_waves, ctx->step_form);
         if (!mod) return fail(TM_E_COMPILE, err);
         HIP_TRY(ws_prepare(w, 0, q), "workspace");
     }
@@ -1409,7 +1502,7 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
         HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, q * sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload queries");
         HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 2 * (int64_t)q, stream), "reset counts and step tallies");
         if (c0 > 0) {
-            GArgs a = base_args(g, w, c);
+            GArgs a = base_args(ctx, g, w, c);
             a.split = any_split;
             a.total_chunks = c0;
             a.rch = (int32_t)rch;

@@ -251,9 +251,31 @@ struct GArgs {
   const int* nlab;
   const u32* pr_pos;
   const int* el; const int* adj_el;
+  const u32* hub; u32 hub_words; u32 hub_dmin;
 };
 static_assert(sizeof(QArgs) == 384, "QArgs layout");
-static_assert(sizeof(GArgs) == 256, "GArgs layout");
+static_assert(sizeof(GArgs) == 272, "GArgs layout");
+// Hub-list samples staged by the workgroup (launches with hub_words > 0):
+// [0] H, [1, 1+H) list starts (ascending), [1+H, 2+2H) sample offsets,
+// [2+2H, 2+3H) log2 strides, time keys from word 2+3H rounded up to even.
+extern __shared__ u32 lds_hub[];
+// A window over the hub list that starts at adjacency position lo: locate the
+// first key > x among the list's samples in LDS and leave [sb, sb+sn) to the
+// search in HBM, one stride at most; lists not in the table are left as they are.
+__device__ __forceinline__ void hub_narrow(u32 lo, tkey x, u32& sb, u32& sn) {
+  const u32 H = lds_hub[0];
+  u32 a = 0u, n = H;
+  while (n > 0u) { const u32 h2 = n >> 1; if (lds_hub[1u + a + h2] < lo) { a += h2 + 1u; n -= h2 + 1u; } else { n = h2; } }
+  if (a >= H || lds_hub[1u + a] != lo) return;
+  const u32 s0 = lds_hub[1u + H + a], s1 = lds_hub[2u + H + a], lg = lds_hub[2u + 2u * H + a];
+  const tkey* smp = (const tkey*)(lds_hub + ((2u + 3u * H + 1u) & ~1u));
+  u32 b = s0, k = s1 - s0;
+  while (k > 0u) { const u32 h2 = k >> 1; if (smp[b + h2] <= x) { b += h2 + 1u; k -= h2 + 1u; } else { k = h2; } }
+  const u32 c = b - s0;  // samples <= x: sample c (if any) is the first key > x among them
+  if (c == 0u) { sn = 0u; return; }  // the list's first key already exceeds x
+  const u32 end = sb + sn, nb = lo + ((c - 1u) << lg) + 1u, nx = lo + (c << lg);
+  sb = nb; sn = (nx < end ? nx : end) - nb;
+}
 // generic matchers: motif node slot by run-time index, and the bound-node check
 #define mget(ix) ((ix) == 0 ? m0 : (ix) == 1 ? m1 : (ix) == 2 ? m2 : (ix) == 3 ? m3 : \
                   (ix) == 4 ? m4 : (ix) == 5 ? m5 : (ix) == 6 ? m6 : m7)
@@ -454,7 +476,15 @@ struct Emitter {
     std::ostringstream o;
     const Plan &p;
     const bool G;
-    explicit Emitter(const Plan &pl, bool generic = false) : p(pl), G(generic) {}
+    // Step form. false: a loop step runs the search probe and the candidate
+    // scan as separate branches, each waiting for its own reads, and a
+    // candidate that binds opens the next level (reads its offsets) at once.
+    // true: a step first issues the reads of every lane (search pivots,
+    // candidate key and neighbour, or the offsets of a level to open) and
+    // then consumes them, so that a wavefront waits once per step; a binding
+    // candidate leaves the next level's open to the following step (phase 4).
+    bool F = false;
+    explicit Emitter(const Plan &pl, bool generic = false, bool fused = false) : p(pl), G(generic), F(fused) {}
 
     std::string I(int i) const { return std::to_string(i); }
 
@@ -565,6 +595,21 @@ struct Emitter {
     // which follows the byte model's one search per window).
     void open(int i, const char *tp, const char *ind) {
         if (leaf_cache() && i == p.l - 2) o << ind << "lq = false;\n";
+        if (F) {
+            // the next step reads the list offsets; a known window start (see
+            // jump_of) is kept in sb until then, the bound edge's time in sx
+            if (G) {
+                if (i == 1)
+                    o << ind << "if (MODE != 1 && gj1 != 0) sb = (gj1 == 1 ? g.pos_out[r] : g.pos_in[r]) + 1u;\n";
+                else
+                    o << ind << "if (MODE != 1 && gj" << i << " != 0) sb = c + 1u;\n";
+            } else {
+                const std::string jump = jump_of(i);
+                if (!jump.empty()) o << ind << "if (MODE != 1) sb = " << jump << ";\n";
+            }
+            o << ind << "sx = (" << tp << "); lvl = " << i << "; ph = 4;\n";
+            return;
+        }
         if (G) {
             const std::string in2 = std::string(ind) + "  ";
             o << ind << "if (MODE != 1 && gj" << i << " != 0) {\n";
@@ -643,9 +688,339 @@ struct Emitter {
         o << ind << "  { i64 h_ = (i64)(" << tp << ") + gap" << (i - 1) << "; hi" << i
           << " = (tkey)(h_ < (i64)tmaxk ? h_ : (i64)tmaxk); }\n";
         o << ind << "  sb = lo_; sn = hi_ - lo_; sx = (" << tp << "); lvl = " << i << ";\n";
-        o << ind << "  if (sn == 0u) { cur" << i << " = lo_; ph = 0; } else { ph = 1; }\n";
         o << ind << "  if (MODE == 1) { st_win++; st_probe += bitlen(sn); }\n";
+        if (G)
+            o << ind << "  if (MODE != 1 && g.hub_words != 0u && gk" << i << " != 3 && sn >= g.hub_dmin) hub_narrow(lo_, sx, sb, sn);\n";
+        else if (p.kind[i] != LIST_GLOBAL)
+            o << ind << "  if (MODE != 1 && g.hub_words != 0u && sn >= g.hub_dmin) hub_narrow(lo_, sx, sb, sn);\n";
+        o << ind << "  if (sn == 0u) { cur" << i << " = sb; ph = 0; } else { ph = 1; }\n";
         o << ind << "}\n";
+    }
+
+    // Phase 4 reads: the offsets of the list level i opens.
+    void open_reads(int i, const char *ind) {
+        if (G) {
+            const std::string s = I(i);
+            o << ind << "if (gk" << s << " == 0 || gk" << s << " == 2) { const int x_ = mget(ga" << s
+              << "); f1 = g.off_out[x_]; f2 = g.off_out[x_ + 1]; }\n";
+            o << ind << "else if (gk" << s << " == 1) { const int y_ = mget(gb" << s
+              << "); f1 = g.off_in[y_]; f2 = g.off_in[y_ + 1]; }\n";
+            o << ind << "if (gk" << s << " == 2) { const int y_ = mget(gb" << s
+              << "); f3 = g.off_in[y_]; f4 = g.off_in[y_ + 1]; }\n";
+            return;
+        }
+        const int A = p.a[i], B = p.b[i];
+        switch (p.kind[i]) {
+        case LIST_OUT:
+            o << ind << "f1 = g.off_out[m" << A << "]; f2 = g.off_out[m" << A << " + 1];\n";
+            break;
+        case LIST_IN:
+            o << ind << "f1 = g.off_in[m" << B << "]; f2 = g.off_in[m" << B << " + 1];\n";
+            break;
+        case LIST_BOTH:
+            o << ind << "f1 = g.off_out[m" << A << "]; f2 = g.off_out[m" << A << " + 1];\n";
+            o << ind << "f3 = g.off_in[m" << B << "]; f4 = g.off_in[m" << B << " + 1];\n";
+            break;
+        default:
+            break;
+        }
+    }
+
+    // Level i's window once lo_, hi_ are known; `jump`: the start needs only
+    // the tie skip (phase 2), else a search (phase 1).
+    void open_tail(int i, bool jump, bool hub, const char *ind) {
+        o << ind << "end" << i << " = hi_; exact &= ~" << (1 << i) << "u;\n";
+        o << ind << "{ i64 h_ = (i64)sx + gap" << (i - 1) << "; hi" << i
+          << " = (tkey)(h_ < (i64)tmaxk ? h_ : (i64)tmaxk); }\n";
+        o << ind << "sb = lo_; sn = hi_ - lo_;\n";
+        if (jump) {
+            o << ind << "if (sn == 0u) { cur" << i << " = lo_; ph = 0; } else { ph = 2; }\n";
+            return;
+        }
+        o << ind << "if (MODE == 1) { st_win++; st_probe += bitlen(sn); }\n";
+        if (hub) o << ind << "if (MODE != 1 && g.hub_words != 0u && sn >= g.hub_dmin) hub_narrow(lo_, sx, sb, sn);\n";
+        o << ind << "if (sn == 0u) { cur" << i << " = sb; ph = 0; } else { ph = 1; }\n";
+    }
+
+    // Phase 4: open level i from the offsets read this step.
+    void open_use(int i, const char *ind) {
+        const std::string in2 = std::string(ind) + "  ";
+        o << ind << "u32 lo_ = 0u, hi_ = 0u;\n";
+        if (G) {
+            const std::string s = I(i);
+            o << ind << "if (MODE != 1 && gj" << s << " != 0) {\n";
+            o << in2 << "lo_ = sb; hi_ = f2;\n";
+            open_tail(i, true, false, in2.c_str());
+            o << ind << "} else {\n";
+            o << in2 << "if (gk" << s << " == 0 || gk" << s << " == 1) { lo_ = f1; hi_ = f2; }\n";
+            o << in2 << "else if (gk" << s << " == 2) { const bool uo = (f2 - f1) <= (f4 - f3);\n";
+            o << in2 << "  lo_ = uo ? f1 : f3; hi_ = uo ? f2 : f4; want" << s << " = uo ? mget(gb" << s << ") : mget(ga"
+              << s << "); }\n";
+            o << in2 << "else { lo_ = 0u; hi_ = (u32)g.m_edges; }\n";
+            o << in2 << "end" << i << " = hi_; exact &= ~" << (1 << i) << "u;\n";
+            o << in2 << "{ i64 h_ = (i64)sx + gap" << (i - 1) << "; hi" << i
+              << " = (tkey)(h_ < (i64)tmaxk ? h_ : (i64)tmaxk); }\n";
+            o << in2 << "sb = lo_; sn = hi_ - lo_;\n";
+            o << in2 << "if (MODE == 1) { st_win++; st_probe += bitlen(sn); }\n";
+            o << in2 << "if (MODE != 1 && g.hub_words != 0u && gk" << s
+              << " != 3 && sn >= g.hub_dmin) hub_narrow(lo_, sx, sb, sn);\n";
+            o << in2 << "if (sn == 0u) { cur" << i << " = sb; ph = 0; } else { ph = 1; }\n";
+            o << ind << "}\n";
+            return;
+        }
+        const bool jump = !jump_of(i).empty();
+        std::string in = ind;
+        if (jump) {
+            o << ind << "if (MODE != 1) {\n";
+            o << in2 << "lo_ = sb; hi_ = f2;\n";
+            open_tail(i, true, false, in2.c_str());
+            o << ind << "} else {\n";
+            in = in2;
+        }
+        const int A = p.a[i], B = p.b[i];
+        switch (p.kind[i]) {
+        case LIST_OUT:
+        case LIST_IN:
+            o << in << "lo_ = f1; hi_ = f2;\n";
+            break;
+        case LIST_BOTH:
+            o << in << "{ const bool uo = (f2 - f1) <= (f4 - f3);\n";
+            o << in << "  lo_ = uo ? f1 : f3; hi_ = uo ? f2 : f4; want" << i << " = uo ? m" << B << " : m" << A << "; }\n";
+            break;
+        default:
+            o << in << "lo_ = 0u; hi_ = (u32)g.m_edges;\n";
+        }
+        open_tail(i, false, p.kind[i] != LIST_GLOBAL, in.c_str());
+        if (jump) o << ind << "}\n";
+    }
+
+    // One loop step in the fused form (see F): the reads of every lane first,
+    // then their use. Phase 4 opens the level chosen in the previous step.
+    void step_fused() {
+        const int L = p.l;
+        const bool glob = has_global();
+        bool any_pred = false, any_elab = false;
+        for (int i = 1; i < L; i++) {
+            any_pred |= has_pred(i);
+            any_elab |= has_elab(i);
+        }
+        o << "    if (lvl > 0 && ph != 3) {\n";
+        if (G) {
+            o << "      const bool glv = ((gglob >> lvl) & 1u) != 0u;\n";
+        } else if (glob) {
+            o << "      bool glv = false;\n";
+            for (int i = 1; i < L; i++)
+                if (p.kind[i] == LIST_GLOBAL) o << "      glv = glv || lvl == " << i << ";\n";
+        }
+        o << "      const tkey* sarr = " << (G || glob ? "glv ? g.tk : g.adj_t" : "g.adj_t") << ";\n";
+        o << "      u32 c = 0u, e = 0u; tkey h = 0;\n";
+        o << "      if (ph == 0) {\n";
+        o << "        switch (lvl) {\n";
+        for (int i = 1; i < L; i++)
+            o << "          case " << i << ": c = cur" << i << "; e = end" << i << "; h = hi" << i << "; break;\n";
+        o << "          default: break;\n";
+        o << "        }\n";
+        o << "      }\n";
+        o << "      // the step's reads, issued together so that the wavefront waits once\n";
+        o << "      tkey v1 = 0, v2 = 0, v3 = 0; int nb = 0; u32 f1 = 0u, f2 = 0u, f3 = 0u, f4 = 0u;";
+        if (G || any_pred) o << " float wv = 0.0f;";
+        if (G || any_elab) o << " int ev = 0;";
+        o << "\n";
+        o << "      u32 o1 = 0u, o2 = 0u, o3 = 0u;\n";
+        o << "      const bool four = ph == 1 && sn >= 3u;  // three pivots, else one\n";
+        o << "      if (ph == 4) {\n";
+        o << "        switch (lvl) {\n";
+        for (int i = 1; i < L; i++) {
+            o << "          case " << i << ": {\n";
+            open_reads(i, "            ");
+            o << "          } break;\n";
+        }
+        o << "          default: break;\n";
+        o << "        }\n";
+        o << "      } else if (ph == 0) {\n";
+        o << "        if (c < e) {\n";
+        o << "          v1 = sarr[c];\n";
+        if (G) {
+            o << "          if (!glv) nb = g.adj_nbr[c];\n";
+            o << "          if ((gpm >> lvl) & 1u) wv = glv ? g.w[c] : g.adj_w[c];\n";
+            o << "          if ((gelm >> lvl) & 1u) ev = glv ? g.el[c] : g.adj_el[c];\n";
+        } else {
+            o << "          " << (glob ? "if (!glv) " : "") << "nb = g.adj_nbr[c];\n";
+            for (int i = 1; i < L; i++) {
+                if (has_pred(i))
+                    o << "          if (lvl == " << i << ") wv = " << (p.kind[i] == LIST_GLOBAL ? "g.w[c]" : "g.adj_w[c]")
+                      << ";\n";
+                if (has_elab(i))
+                    o << "          if (lvl == " << i << ") ev = " << (p.kind[i] == LIST_GLOBAL ? "g.el[c]" : "g.adj_el[c]")
+                      << ";\n";
+            }
+        }
+        o << "        }\n";
+        o << "      } else if (four) {\n";
+        o << "        o1 = ((sn + 1u) >> 2) - 1u; o2 = ((2u * (sn + 1u)) >> 2) - 1u; o3 = ((3u * (sn + 1u)) >> 2) - 1u;\n";
+        o << "        v1 = sarr[sb + o1]; v2 = sarr[sb + o2]; v3 = sarr[sb + o3];\n";
+        o << "      } else {\n";
+        o << "        o1 = ph == 2 ? 0u : (sn >> 1);\n";
+        o << "        v1 = sarr[sb + o1];\n";
+        o << "      }\n";
+        o << "      if (ph == 4) {\n";
+        o << "        switch (lvl) {\n";
+        for (int i = 1; i < L; i++) {
+            o << "          case " << i << ": {\n";
+            open_use(i, "            ");
+            o << "          } break;\n";
+        }
+        o << "          default: break;\n";
+        o << "        }\n";
+        o << "      } else if (ph == 0) {\n";
+        o << "      const tkey tt = v1; const bool inwin = c < e && tt <= h;\n";
+        if (G)
+            o << "      if (MODE == 1 && c < e) { st_visit++; if ((gpm >> lvl) & 1u) st_pv++; }\n";
+        else
+            o << "      if (MODE == 1 && c < e) { st_visit++;"
+              << (any_pred ? " if ((" + std::to_string(p.pred_mask()) + "u >> lvl) & 1u) st_pv++;" : std::string())
+              << " }\n";
+        visit_accept();
+        o << "      } else {\n";
+        o << "      if (four) {\n";
+        o << "        if (v3 <= sx) { sb += o3 + 1u; sn -= o3 + 1u; }\n";
+        o << "        else if (v2 <= sx) { sb += o2 + 1u; sn = o3 - o2 - 1u; }\n";
+        o << "        else if (v1 <= sx) { sb += o1 + 1u; sn = o2 - o1 - 1u; }\n";
+        o << "        else { sn = o1; }\n";
+        o << "      } else {\n";
+        o << "        if (v1 <= sx) { sb += o1 + 1u; sn = sn - o1 - 1u; } else { sn = o1; }\n";
+        o << "      }\n";
+        o << "      ph = 1;\n";
+        search_done();
+        o << "      }\n";
+        o << "    }\n";
+    }
+
+    // A search has ended (sn == 0): the window starts at sb.
+    void search_done() {
+        const int L = p.l;
+        o << "      if (sn == 0u) {\n";
+        o << "        bool park = false;\n";
+        o << "        switch (lvl) {\n";
+        for (int i = 1; i < L; i++) {
+            if (i == L - 1 && coop_ok()) {
+                // peek 32 candidates ahead: a window that reaches that far is
+                // scanned by the whole wavefront, or, when counting and the
+                // window's count has a closed form, counted without a scan
+                o << "          case " << i << ": cur" << i << " = sb;\n";
+                o << "            if (MODE != 1" << (G ? " && !((gglob >> " + I(i) + ") & 1u)" : std::string())
+                  << ") { const u32 pk = sb + 31u; wide = pk < end" << i << " && g.adj_t[pk] <= hi" << i << "; }\n";
+                leaf_count(i);
+                o << "            break;\n";
+            } else {
+                o << "          case " << i << ": cur" << i << " = sb; break;\n";
+            }
+        }
+        o << "          default: break;\n";
+        o << "        }\n";
+        o << "        ph = park ? 3 : 0;\n";
+        o << "      }\n";
+    }
+
+    // The candidate read at position c of level lvl (tt, nb, wv, ev): leave the
+    // level when it is past the window, else check it and bind or count it.
+    void visit_accept() {
+        const int L = p.l;
+        o << "      if (!inwin) {\n";
+        o << "        lvl -= 1;\n";
+        o << "        if (lvl < base) {\n";
+        o << "          lvl = 0;\n";
+        o << "          if (MODE == 2 && rcnt) { atomicAdd(&g.chunk_cnt[mych], rcnt); cnt += rcnt; rcnt = 0; }\n";
+        o << "        }\n";
+        o << "      } else {\n";
+        o << "        switch (lvl) {\n";
+        for (int i = 1; i < L; i++) {
+            const int A = p.a[i], B = p.b[i];
+            o << "        case " << i << ": {\n";
+            o << "          cur" << i << " = c + 1u;\n";
+            if (G) {
+                const std::string s = I(i);
+                const std::string ms = "m0, m1, m2, m3, m4, m5, m6, m7";
+                const std::string eidx = "(gk" + s + " == 3 ? (int)c : g.adj_eid[c])";
+                o << "          int cs = 0, cd = 0; bool ok;\n";
+                o << "          if (gk" << s << " == 2) ok = nb == want" << s << ";\n";
+                o << "          else if (gk" << s << " == 3) { cs = g.src[c]; cd = g.dst[c];\n";
+                o << "            ok = cs != cd && notin(gm" << s << ", cs, " << ms << ") && notin(gm" << s
+                  << ", cd, " << ms << "); }\n";
+                o << "          else ok = notin(gm" << s << ", nb, " << ms << ");\n";
+                o << "          if (glm != 0u) {\n";
+                o << "            if (gk" << s << " == 3) {\n";
+                o << "              if ((glm >> ga" << s << ") & 1u) ok = ok && in_range(g.nlab[cs], lget(ga" << s
+                  << "), hget(ga" << s << "));\n";
+                o << "              if ((glm >> gb" << s << ") & 1u) ok = ok && in_range(g.nlab[cd], lget(gb" << s
+                  << "), hget(gb" << s << "));\n";
+                o << "            } else if (gk" << s << " != 2 && ((glm >> gn" << s << ") & 1u)) {\n";
+                o << "              ok = ok && in_range(g.nlab[nb], lget(gn" << s << "), hget(gn" << s << "));\n";
+                o << "            }\n";
+                o << "          }\n";
+                o << "          if ((gpm >> " << i << ") & 1u) ok = ok && preds_at(q, " << i << ", wv);\n";
+                o << "          if ((gelm >> " << i << ") & 1u) ok = ok && in_range(ev, q->elo[" << i << "], q->ehi[" << i
+                  << "]);\n";
+                o << "          if (ok) {\n";
+                if (i == L - 1) {
+                    leaf("            ", eidx.c_str());
+                } else {
+                    o << "            if (gk" << s << " == 0) mset(gb" << s << ", nb);\n";
+                    o << "            else if (gk" << s << " == 1) mset(ga" << s << ", nb);\n";
+                    o << "            else if (gk" << s << " == 3) { mset(ga" << s << ", cs); mset(gb" << s
+                      << ", cd); }\n";
+                    o << "            if (MODE == 3) e" << i << " = " << eidx << ";\n";
+                    open(i + 1, "tt", "            ");
+                }
+                o << "          }\n";
+                o << "        } break;\n";
+                continue;
+            }
+            std::ostringstream ok;
+            std::string bind;
+            std::string eid;
+            switch (p.kind[i]) {
+            case LIST_OUT:
+            case LIST_IN: {
+                ok << "true";
+                for (int v : p.mapped[i]) ok << " && nb != m" << v;
+                if (labelled(new_node(i))) ok << " && " << lab_cond(new_node(i), "nb");
+                bind = "m" + std::to_string(p.kind[i] == LIST_OUT ? B : A) + " = nb;";
+                eid = "g.adj_eid[c]";
+                break;
+            }
+            case LIST_BOTH:
+                ok << "nb == want" << i;
+                eid = "g.adj_eid[c]";
+                break;
+            default: {
+                o << "          const int cs = g.src[c], cd = g.dst[c];\n";
+                ok << "cs != cd";
+                for (int v : p.mapped[i]) ok << " && cs != m" << v << " && cd != m" << v;
+                if (labelled(A)) ok << " && " << lab_cond(A, "cs");
+                if (labelled(B)) ok << " && " << lab_cond(B, "cd");
+                bind = "m" + std::to_string(A) + " = cs; m" + std::to_string(B) + " = cd;";
+                eid = "(int)c";
+            }
+            }
+            o << "          bool ok = " << ok.str() << ";\n";
+            if (has_pred(i)) o << "          ok = ok && " << preds_cond(i, "wv") << ";\n";
+            if (has_elab(i)) o << "          ok = ok && " << elab_cond(i, "ev") << ";\n";
+            if (anti_on(i)) o << "          ok = ok && " << anti_cond(i) << ";\n";
+            o << "          if (ok) {\n";
+            if (i == L - 1) {
+                leaf("            ", eid.c_str());
+            } else {
+                if (!bind.empty()) o << "            " << bind << "\n";
+                o << "            if (" << e_cond(i) << ") e" << i << " = " << eid << ";\n";
+                open(i + 1, "tt", "            ");
+            }
+            o << "          }\n";
+            o << "        } break;\n";
+        }
+        o << "        default: break;\n";
+        o << "        }\n";
+        o << "      }\n";
     }
 
     void leaf(const char *ind, const char *last_eid) {
@@ -1329,7 +1704,8 @@ struct Emitter {
         }
         if (L > 1 && coop_ok()) coop();
         if (L > 1 && coop_ok()) park_flush();
-        if (L > 1) {
+        if (L > 1 && F) step_fused();
+        if (L > 1 && !F) {
             // ---------------- search probe
             o << "    if (lvl > 0 && (ph == 1 || ph == 2)) {\n";
             if (G) {
@@ -1361,27 +1737,7 @@ struct Emitter {
             o << "        if (v <= sx) { sb = mid + 1u; sn = sn - half - 1u; } else { sn = half; }\n";
             o << "      }\n";
             o << "      ph = 1;\n";
-            o << "      if (sn == 0u) {\n";
-            o << "        bool park = false;\n";
-            o << "        switch (lvl) {\n";
-            for (int i = 1; i < L; i++) {
-                if (i == L - 1 && coop_ok()) {
-                    // peek 32 candidates ahead: a window that reaches that far is
-                    // scanned by the whole wavefront, or, when counting and the
-                    // window's count has a closed form, counted without a scan
-                    o << "          case " << i << ": cur" << i << " = sb;\n";
-                    o << "            if (MODE != 1" << (G ? " && !((gglob >> " + I(i) + ") & 1u)" : std::string())
-                      << ") { const u32 pk = sb + 31u; wide = pk < end" << i << " && g.adj_t[pk] <= hi" << i << "; }\n";
-                    leaf_count(i);
-                    o << "            break;\n";
-                } else {
-                    o << "          case " << i << ": cur" << i << " = sb; break;\n";
-                }
-            }
-            o << "          default: break;\n";
-            o << "        }\n";
-            o << "        ph = park ? 3 : 0;\n";
-            o << "      }\n";
+            search_done();
             o << "    } else if (lvl > 0 && ph == 0) {\n";
             // ---------------- candidate scan
             o << "      u32 c = 0u, e = 0u; tkey h = 0;\n";
@@ -1432,101 +1788,7 @@ struct Emitter {
                   << (any_pred ? " if ((" + std::to_string(p.pred_mask()) + "u >> lvl) & 1u) st_pv++;" : std::string())
                   << " }\n";
             o << "      }\n";
-            o << "      if (!inwin) {\n";
-            o << "        lvl -= 1;\n";
-            o << "        if (lvl < base) {\n";
-            o << "          lvl = 0;\n";
-            o << "          if (MODE == 2 && rcnt) { atomicAdd(&g.chunk_cnt[mych], rcnt); cnt += rcnt; rcnt = 0; }\n";
-            o << "        }\n";
-            o << "      } else {\n";
-            o << "        switch (lvl) {\n";
-            for (int i = 1; i < L; i++) {
-                const int A = p.a[i], B = p.b[i];
-                o << "        case " << i << ": {\n";
-                o << "          cur" << i << " = c + 1u;\n";
-                if (G) {
-                    const std::string s = I(i);
-                    const std::string ms = "m0, m1, m2, m3, m4, m5, m6, m7";
-                    const std::string eidx = "(gk" + s + " == 3 ? (int)c : g.adj_eid[c])";
-                    o << "          int cs = 0, cd = 0; bool ok;\n";
-                    o << "          if (gk" << s << " == 2) ok = nb == want" << s << ";\n";
-                    o << "          else if (gk" << s << " == 3) { cs = g.src[c]; cd = g.dst[c];\n";
-                    o << "            ok = cs != cd && notin(gm" << s << ", cs, " << ms << ") && notin(gm" << s
-                      << ", cd, " << ms << "); }\n";
-                    o << "          else ok = notin(gm" << s << ", nb, " << ms << ");\n";
-                    o << "          if (glm != 0u) {\n";
-                    o << "            if (gk" << s << " == 3) {\n";
-                    o << "              if ((glm >> ga" << s << ") & 1u) ok = ok && in_range(g.nlab[cs], lget(ga" << s
-                      << "), hget(ga" << s << "));\n";
-                    o << "              if ((glm >> gb" << s << ") & 1u) ok = ok && in_range(g.nlab[cd], lget(gb" << s
-                      << "), hget(gb" << s << "));\n";
-                    o << "            } else if (gk" << s << " != 2 && ((glm >> gn" << s << ") & 1u)) {\n";
-                    o << "              ok = ok && in_range(g.nlab[nb], lget(gn" << s << "), hget(gn" << s << "));\n";
-                    o << "            }\n";
-                    o << "          }\n";
-                    o << "          if ((gpm >> " << i << ") & 1u) ok = ok && preds_at(q, " << i << ", wv);\n";
-                    o << "          if ((gelm >> " << i << ") & 1u) ok = ok && in_range(ev, q->elo[" << i << "], q->ehi[" << i
-                      << "]);\n";
-                    o << "          if (ok) {\n";
-                    if (i == L - 1) {
-                        leaf("            ", eidx.c_str());
-                    } else {
-                        o << "            if (gk" << s << " == 0) mset(gb" << s << ", nb);\n";
-                        o << "            else if (gk" << s << " == 1) mset(ga" << s << ", nb);\n";
-                        o << "            else if (gk" << s << " == 3) { mset(ga" << s << ", cs); mset(gb" << s
-                          << ", cd); }\n";
-                        o << "            if (MODE == 3) e" << i << " = " << eidx << ";\n";
-                        open(i + 1, "tt", "            ");
-                    }
-                    o << "          }\n";
-                    o << "        } break;\n";
-                    continue;
-                }
-                std::ostringstream ok;
-                std::string bind;
-                std::string eid;
-                switch (p.kind[i]) {
-                case LIST_OUT:
-                case LIST_IN: {
-                    ok << "true";
-                    for (int v : p.mapped[i]) ok << " && nb != m" << v;
-                    if (labelled(new_node(i))) ok << " && " << lab_cond(new_node(i), "nb");
-                    bind = "m" + std::to_string(p.kind[i] == LIST_OUT ? B : A) + " = nb;";
-                    eid = "g.adj_eid[c]";
-                    break;
-                }
-                case LIST_BOTH:
-                    ok << "nb == want" << i;
-                    eid = "g.adj_eid[c]";
-                    break;
-                default: {
-                    o << "          const int cs = g.src[c], cd = g.dst[c];\n";
-                    ok << "cs != cd";
-                    for (int v : p.mapped[i]) ok << " && cs != m" << v << " && cd != m" << v;
-                    if (labelled(A)) ok << " && " << lab_cond(A, "cs");
-                    if (labelled(B)) ok << " && " << lab_cond(B, "cd");
-                    bind = "m" + std::to_string(A) + " = cs; m" + std::to_string(B) + " = cd;";
-                    eid = "(int)c";
-                }
-                }
-                o << "          bool ok = " << ok.str() << ";\n";
-                if (has_pred(i)) o << "          ok = ok && " << preds_cond(i, "wv") << ";\n";
-                if (has_elab(i)) o << "          ok = ok && " << elab_cond(i, "ev") << ";\n";
-                if (anti_on(i)) o << "          ok = ok && " << anti_cond(i) << ";\n";
-                o << "          if (ok) {\n";
-                if (i == L - 1) {
-                    leaf("            ", eid.c_str());
-                } else {
-                    if (!bind.empty()) o << "            " << bind << "\n";
-                    o << "            if (" << e_cond(i) << ") e" << i << " = " << eid << ";\n";
-                    open(i + 1, "tt", "            ");
-                }
-                o << "          }\n";
-                o << "        } break;\n";
-            }
-            o << "        default: break;\n";
-            o << "        }\n";
-            o << "      }\n";
+            visit_accept();
             o << "    }\n";
         }
         o << "  }\n";
@@ -1573,6 +1835,10 @@ void emit_kernels(std::ostringstream &o, int nfn, int block, unsigned modes, int
         if (min_waves > 0) o << ", " << min_waves;  // minimum waves per SIMD
         o << ") void " << names[mode] << "(GArgs g) {\n";
         o << "  const int lane = lane_id();\n";
+        o << "  if (g.hub_words != 0u) {  // stage the hub samples (the same for all workgroups)\n";
+        o << "    for (u32 i = threadIdx.x; i < g.hub_words; i += blockDim.x) lds_hub[i] = g.hub[i];\n";
+        o << "    __syncthreads();\n";
+        o << "  }\n";
         if (outlined) o << "  const u64 ga = (u64)__builtin_amdgcn_kernarg_segment_ptr();\n";
         o << "  i64 c = 0;\n";
         o << "  if (lane == 0) { atomicAdd(&g.ctl[8], 1ull); c = (i64)atomicAdd(&g.ctl[0], 1ull); }\n";
@@ -1653,8 +1919,8 @@ static std::string header(int key_bytes) {
     return o.str();
 }
 
-std::string generate_source(const Plan &p, int key_bytes, int block, int min_waves, unsigned modes) {
-    Emitter e(p, p.generic);
+std::string generate_source(const Plan &p, int key_bytes, int block, int min_waves, unsigned modes, int form) {
+    Emitter e(p, p.generic, form != 0);
     e.o << header(key_bytes);
     e.matcher(0);
     emit_kernels(e.o, 1, block, modes & kAllModes, min_waves, false);
@@ -1662,14 +1928,14 @@ std::string generate_source(const Plan &p, int key_bytes, int block, int min_wav
 }
 
 std::string generate_batch_source(const std::vector<const Plan *> &plans, int key_bytes, int block,
-                                  int min_waves) {
+                                  int min_waves, int form) {
     std::ostringstream all;
     all << header(key_bytes);
     int n_generic = 0;
     for (auto *pl : plans) n_generic += pl->generic ? 1 : 0;
     const bool outlined = (int)plans.size() > kMaxInlinedMatchers || n_generic > 1;
     for (size_t f = 0; f < plans.size(); f++) {
-        Emitter e(*plans[f], plans[f]->generic);
+        Emitter e(*plans[f], plans[f]->generic, form != 0);
         e.matcher((int)f, outlined);
         all << e.o.str();
     }
@@ -1831,8 +2097,8 @@ static int waves_for(long vgprs) {
 }
 
 bool batch_code(const std::vector<const Plan *> &plans, int key_bytes, int block, int min_waves,
-                std::vector<char> *code, std::string *err) {
-    if (!cached_code(generate_batch_source(plans, key_bytes, block, min_waves), code, err)) return false;
+                std::vector<char> *code, std::string *err, int form) {
+    if (!cached_code(generate_batch_source(plans, key_bytes, block, min_waves, form), code, err)) return false;
     if (min_waves != 0) return true;
     // A batched kernel a few registers above a wave boundary runs one wave
     // more per SIMD when compiled to fit it (the persistent kernel hides its
@@ -1844,7 +2110,7 @@ bool batch_code(const std::vector<const Plan *> &plans, int key_bytes, int block
     if (v - fit > kSqueezeRegs) return true;
     std::vector<char> c2;
     std::string e2;
-    if (!cached_code(generate_batch_source(plans, key_bytes, block, w + 1), &c2, &e2)) return true;
+    if (!cached_code(generate_batch_source(plans, key_bytes, block, w + 1, form), &c2, &e2)) return true;
     const long spill = meta_uint(c2, ".vgpr_spill_count");
     if (spill < 0 || spill > kSqueezeSpills) return true;
     code->swap(c2);
@@ -1903,34 +2169,37 @@ std::shared_ptr<Module> Compiler::lookup_or_build(const std::string &key, int bl
 }
 
 std::shared_ptr<Module> Compiler::get(const Plan &p, int key_bytes, int block, std::string *err, int min_waves,
-                                      unsigned modes) {
+                                      unsigned modes, int form) {
     const std::string key = "S" + std::to_string(key_bytes) + "b" + std::to_string(block) +
-                            (min_waves ? "w" + std::to_string(min_waves) : std::string()) + "m" +
-                            std::to_string(modes) + ":" + p.key();
+                            (min_waves ? "w" + std::to_string(min_waves) : std::string()) +
+                            (form ? "f" + std::to_string(form) : std::string()) + "m" + std::to_string(modes) + ":" +
+                            p.key();
     return lookup_or_build(key, block, modes, [&](std::vector<char> *code, std::string *e) {
-        return cached_code(generate_source(p, key_bytes, block, min_waves, modes), code, e);
+        return cached_code(generate_source(p, key_bytes, block, min_waves, modes, form), code, e);
     }, err);
 }
 
-static std::string batch_key(const std::vector<const Plan *> &plans, int key_bytes, int block, int min_waves) {
+static std::string batch_key(const std::vector<const Plan *> &plans, int key_bytes, int block, int min_waves,
+                             int form) {
     std::string key = "B" + std::to_string(key_bytes) + "b" + std::to_string(block) +
-                      (min_waves ? "w" + std::to_string(min_waves) : std::string()) + ":";
+                      (min_waves ? "w" + std::to_string(min_waves) : std::string()) +
+                      (form ? "f" + std::to_string(form) : std::string()) + ":";
     for (auto *p : plans) key += p->key() + "|";
     return key;
 }
 
 std::shared_ptr<Module> Compiler::get_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
-                                            std::string *err, int min_waves) {
-    return lookup_or_build(batch_key(plans, key_bytes, block, min_waves), block, 0u,
+                                            std::string *err, int min_waves, int form) {
+    return lookup_or_build(batch_key(plans, key_bytes, block, min_waves, form), block, 0u,
                            [&](std::vector<char> *code, std::string *e) {
-                               return batch_code(plans, key_bytes, block, min_waves, code, e);
+                               return batch_code(plans, key_bytes, block, min_waves, code, e, form);
                            }, err);
 }
 
 std::shared_ptr<Module> Compiler::find_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
-                                             int min_waves) {
+                                             int min_waves, int form) {
     std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find(batch_key(plans, key_bytes, block, min_waves));
+    auto it = cache.find(batch_key(plans, key_bytes, block, min_waves, form));
     return it == cache.end() ? nullptr : it->second;
 }
 

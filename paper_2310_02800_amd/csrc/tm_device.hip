@@ -17,6 +17,7 @@
 // motif level uses.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 
@@ -171,6 +172,38 @@ hipError_t dev_gather_i32(int64_t n, const int32_t *eid, const int32_t *el, int3
     clear_stale_error();
     if (n <= 0) return hipSuccess;
     k_gather_i32<<<blocks_for(n), kThreads, 0, s>>>(n, eid, el, out);
+    return hipGetLastError();
+}
+
+// Samples of the hub lists staged in LDS: sample i of hub h (slots
+// soff[h] .. soff[h+1]) is the time key at adjacency position
+// start[h] + (i - soff[h]) * 2^lg[h]. The table's header (hub count, starts,
+// sample offsets, strides) is already in place; samples follow at word `base`.
+template <typename K>
+__global__ void k_hub_samples(uint32_t *tab, uint32_t base, const K *adj_t) {
+    const uint32_t H = tab[0];
+    const uint32_t *start = tab + 1, *soff = tab + 1 + H, *lg = tab + 2 + 2 * H;
+    K *out = (K *)(tab + base);
+    const uint32_t total = soff[H];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        uint32_t lo = 0, n = H;  // hub h: the last with soff[h] <= i
+        while (n > 0) {
+            const uint32_t h2 = n >> 1;
+            if (soff[lo + h2 + 1] <= i) { lo += h2 + 1; n -= h2 + 1; } else { n = h2; }
+        }
+        out[i] = adj_t[start[lo] + ((i - soff[lo]) << lg[lo])];
+    }
+}
+
+hipError_t dev_hub_samples(uint32_t *d_tab, uint32_t base, uint32_t total, const void *adj_t, int key_bytes,
+                           hipStream_t s) {
+    clear_stale_error();
+    if (total == 0) return hipSuccess;
+    const int blocks = (int)std::min<uint32_t>((total + kThreads - 1) / kThreads, 1024u);
+    if (key_bytes == 4)
+        k_hub_samples<int32_t><<<blocks, kThreads, 0, s>>>(d_tab, base, (const int32_t *)adj_t);
+    else
+        k_hub_samples<int64_t><<<blocks, kThreads, 0, s>>>(d_tab, base, (const int64_t *)adj_t);
     return hipGetLastError();
 }
 

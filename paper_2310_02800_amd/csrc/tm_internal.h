@@ -84,8 +84,19 @@ struct GArgs {
     const uint32_t *pr_pos;   // per adjacency entry: its position in the pair-sorted lists
     const int32_t *el;        // edge labels in edge-id order (m entries) or null
     const int32_t *adj_el;    // edge labels in adjacency order (2m entries) or null
+    const uint32_t *hub;      // hub-list sample table staged in LDS by every workgroup, or null
+    uint32_t hub_words;       // its size in 32-bit words (0: no staging)
+    uint32_t hub_dmin;        // shortest hub list: only windows over lists this long look it up
 };
-static_assert(sizeof(GArgs) == 256, "GArgs layout");
+static_assert(sizeof(GArgs) == 272, "GArgs layout");
+
+// Hub-list staging (LDS): the longest adjacency lists each get up to
+// kHubSamplesPerList time keys sampled at a power-of-two stride (at least 32,
+// one cache line of keys), kHubMaxLists lists at most and kHubMaxWords words
+// of table in all, so that a workgroup's copy stays within its share of LDS
+// at full occupancy. Lists shorter than kHubMinLen are never staged.
+constexpr uint32_t kHubMaxWords = 7168, kHubMaxLists = 64, kHubSamplesPerList = 512, kHubMinLen = 512;
+constexpr uint32_t kLdsPerCu = 160u * 1024u;  // gfx950
 
 // ctl words: [10..12] work counters of the windows counted without a scan,
 // [13] donated items waiting in all queues
@@ -144,6 +155,10 @@ Plan generic_plan(int l);
 // Fill the plan tables a generic matcher reads (and that specialised ones ignore).
 void fill_plan_tables(const Plan &p, QArgs *q);
 
+// Loop step form of the generated matchers: 0 = search probe and candidate scan
+// as separate branches; 1 = one read round per step (TM_PARAM_STEP_FORM).
+constexpr int kDefaultStepForm = 0;
+
 struct Module {
     hipModule_t mod = nullptr;
     hipFunction_t fn[MODE_COUNT_] = {};
@@ -163,13 +178,13 @@ struct Compiler {
     // min_waves > 0 asks the compiler to fit that many waves per SIMD
     // `modes`: the kernels the module holds (bit i = Mode i; see mode_group)
     std::shared_ptr<Module> get(const Plan &p, int key_bytes, int block, std::string *err, int min_waves,
-                                unsigned modes);
+                                unsigned modes, int form = kDefaultStepForm);
     std::shared_ptr<Module> get_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
-                                      std::string *err, int min_waves = 0);
+                                      std::string *err, int min_waves = 0, int form = kDefaultStepForm);
     // the batched module if it is already built and loaded, else null
     // (never compiles or loads)
     std::shared_ptr<Module> find_batch(const std::vector<const Plan *> &plans, int key_bytes, int block,
-                                       int min_waves = 0);
+                                       int min_waves = 0, int form = kDefaultStepForm);
     // the cached module for `key`, else one built by `make` (holding the
     // kernels of `modes`, 0 = the batched kernel); concurrent callers of one
     // key share a single compile
@@ -187,9 +202,10 @@ inline unsigned mode_group(int mode) {
     return mode == MODE_ENUM_COUNT || mode == MODE_ENUM_WRITE ? (1u << MODE_ENUM_COUNT) | (1u << MODE_ENUM_WRITE)
                                                               : 1u << mode;
 }
-std::string generate_source(const Plan &p, int key_bytes, int block, int min_waves = 0, unsigned modes = kAllModes);
+std::string generate_source(const Plan &p, int key_bytes, int block, int min_waves = 0, unsigned modes = kAllModes,
+                            int form = kDefaultStepForm);
 std::string generate_batch_source(const std::vector<const Plan *> &plans, int key_bytes, int block,
-                                  int min_waves = 0);
+                                  int min_waves = 0, int form = kDefaultStepForm);
 bool build_plan(const tm_motif_desc *d, Plan *p, int64_t *gaps, std::string *err);
 bool compile_to_code(const std::string &src, std::vector<char> *code, std::string *err);
 bool cached_code(const std::string &src, std::vector<char> *code, std::string *err);
@@ -198,7 +214,7 @@ bool cached_code(const std::string &src, std::vector<char> *code, std::string *e
 // spills at most kSqueezeSpills (the second build is used then).
 constexpr int kSqueezeRegs = 8, kSqueezeSpills = 8;
 bool batch_code(const std::vector<const Plan *> &plans, int key_bytes, int block, int min_waves,
-                std::vector<char> *code, std::string *err);
+                std::vector<char> *code, std::string *err, int form = kDefaultStepForm);
 
 // device helpers (tm_device.hip)
 hipError_t dev_build_pairs(int64_t n, int64_t m, const int32_t *d_key, const int32_t *d_other, const void *d_tk,
@@ -224,6 +240,9 @@ std::atomic<uint32_t> *scratch_epoch(int device);
 std::mutex *scratch_mutex(int device);
 // out[p] = el[eid[p]] for p < n (edge labels into adjacency order)
 hipError_t dev_gather_i32(int64_t n, const int32_t *eid, const int32_t *el, int32_t *out, hipStream_t s);
+// Fill the samples of a hub table whose header is in place (see build_hub_table).
+hipError_t dev_hub_samples(uint32_t *d_tab, uint32_t base, uint32_t total, const void *adj_t, int key_bytes,
+                           hipStream_t s);
 // own scan and radix sort (tm_sort.hip). Scans: exclusive, in == out allowed,
 // `tmp` holds scan_tmp_elems(n) elements. Radix sort: stable, keys below
 // 2^end_bit, ping-pong between (keys, vals) and the *_alt buffers (*in_alt
@@ -318,6 +337,8 @@ struct tm_ctx {
     int last_tuned = 0;       // 1: it came from the tune table
     int64_t trace_us = 0;     // launch sampling period (0 = off)
     int root_handoff = 1;     // hand unstarted roots to waiting wavefronts once the queue is empty
+    int hub_lds = 0;          // stage the hub lists' sampled keys in LDS (TM_PARAM_HUB_LDS)
+    int step_form = tmo::kDefaultStepForm;  // matcher loop step form (TM_PARAM_STEP_FORM)
     std::vector<int64_t> trace;  // samples of the last sampled launch, kTraceCols each
     void *scratch = nullptr;     // this device's no-allocation scratch (tm_count_batch_noalloc)
 };
@@ -346,6 +367,9 @@ struct tm_graph {
     int32_t *d_el = nullptr;      // edge labels (m entries, id order), once attached
     int32_t *d_adj_el = nullptr;  // the same in adjacency order (2m entries)
     bool has_edge_labels = false;
+    uint32_t *d_hub = nullptr;    // hub-list sample table (see kHubMaxWords), or null
+    uint32_t hub_words = 0, hub_dmin = 0;
+    int32_t hub_lists = 0;
     std::vector<int64_t> h_t;     // sorted absolute times (root-range lookup)
     std::vector<int64_t> perm;    // empty when the input was sorted
     int64_t device_bytes = 0;
