@@ -375,7 +375,8 @@ def bench_serve(ctx, dg, g, args):
     time (plain), then through the continuous-batching server with Poisson
     arrivals at 0.7x the plain capacity, and once more with every query
     submitted at once (served capacity). Both forms use the table-driven
-    kernels and the same per-query work budget."""
+    kernels and the same per-query work budget; a query over it in either pass
+    is then run alone with its specialised kernel and a larger budget."""
     import numpy as np
     import torch
     from paper_2310_02800_amd import _native as N
@@ -518,6 +519,26 @@ def bench_serve(ctx, dg, g, args):
                             if rr[i][0]["count"] != rec["count"]:
                                 oracle_bad.append(i)
         assert not oracle_bad, f"served counts differ from the oracle's on queries {oracle_bad[:10]}"
+        # queries over the work budget in either pass: each alone, with its
+        # specialised kernel and a larger budget (counted; an over-budget
+        # enumeration's rows would not fit the pool)
+        over = sorted({i for i in range(n) if plain[i][0] == N.TM_E_CANCELLED} |
+                      {i for i, (r, _) in res_f.items() if r["status"] == N.TM_E_CANCELLED})
+        alone = []
+        ctx.set_param(N.TM_PARAM_TIER, 0)
+        ctx.set_param(N.TM_PARAM_WORK_BUDGET, args.serve_alone_budget)
+        for i in over:
+            q = qs[i]
+            log(f"serve: query {i} alone ({q.motif.edges}, delta {q.motif.delta})")
+            t0 = time.perf_counter()
+            try:
+                c, st = ctx.count(dg, ctx.compile(q.motif), t_lo=q.t_lo, t_hi=q.t_hi, stream=stream), N.TM_OK
+            except N.NativeError as e:
+                c, st = None, e.status
+            alone.append({"index": i, "edges": q.motif.edges, "delta": q.motif.delta, "enumerate": q.enumerate,
+                          "status": "ok" if st == N.TM_OK else "cancelled" if st == N.TM_E_CANCELLED else st,
+                          "count": c, "s": time.perf_counter() - t0})
+            log(f"serve: query {i} alone: {alone[-1]['status']} in {alone[-1]['s']:.1f} s")
         ok = [i for i in range(n_rate) if res[i][0]["status"] == N.TM_OK]
         inst = sum(res[i][0]["count"] for i in ok)
         ok_f = [i for i in range(n) if res_f[i][0]["status"] == N.TM_OK]
@@ -528,9 +549,12 @@ def bench_serve(ctx, dg, g, args):
                         "motifs with 3-6 edges and 3-5 nodes, delta log-uniform in [600, 86400], root range "
                         "1-100% of the span, 10% enumerations",
             "queries": n, "work_budget_steps": budget,
-            "cancelled": {"plain": sum(1 for p in plain if p[0] == N.TM_E_CANCELLED),
-                          "served": sum(1 for r, _ in list(res.values()) + list(res_f.values())
-                                        if r["status"] == N.TM_E_CANCELLED)},
+            "cancelled_in_stream": {"plain": sum(1 for p in plain if p[0] == N.TM_E_CANCELLED),
+                                    "served": sum(1 for r, _ in list(res.values()) + list(res_f.values())
+                                                  if r["status"] == N.TM_E_CANCELLED)},
+            "over_budget_alone": {"work_budget_steps": args.serve_alone_budget, "queries": alone},
+            # queries with no exact result at the end: over budget in the stream and alone
+            "cancelled": sum(1 for a in alone if a["status"] != "ok"),
             "over_pool": sum(1 for p in plain if p[0] == N.TM_E_CAPACITY),
             "plain": {"capacity_qps": cap_plain, "service_ms": {"p50": pct(svc, 50), "p99": pct(svc, 99)},
                       # one first-in-first-out worker at the served arrival times: the measured service
@@ -593,7 +617,10 @@ def main():
     ap.add_argument("--query-only", type=int, default=None,
                     help="time only headline query i (0..5: 3-cycle, 4-cycle, out-star at 3600 s, then at 86400 s) "
                          "as plain counts and print its JSON (for kernel traces and counters of one query)")
-    ap.add_argument("--serve-budget", type=int, default=0, help="work budget per served query (steps, 0 = none)")
+    ap.add_argument("--serve-budget", type=int, default=1 << 31,
+                    help="work budget per query in the stream (wavefront loop steps, 0 = none)")
+    ap.add_argument("--serve-alone-budget", type=int, default=1 << 35,
+                    help="work budget of an over-budget query run alone afterwards (steps, 0 = none)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=64)
     ap.add_argument("--serve-pool-gib", type=float, default=8.0)

@@ -195,7 +195,8 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
  * 1024}, each with splitting off and with splitting of windows of 32 or more;
  * at 256 roots also splitting from 2, 8 and 128; then half and twice the
  * best roots per chunk at its splitting setting; then, at the best of those,
- * TM_PARAM_LEAF_MIN in {0, 128, 2048}), checks that every trial returns the
+ * TM_PARAM_LEAF_MIN in {0, 128, 2048}; then, at the best, at most 3 and 2
+ * workgroups per CU instead of as many as fit), checks that every trial returns the
  * same counts (else TM_E_DEVICE), returns them, and keeps the fastest setting for
  * the key. Later counts, batches and enumerations with the key use it. The
  * key is the graph (node and edge counts, time span), the kernel module, and
@@ -206,8 +207,11 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *value);
  * tm_last_launch: the setting of the last count / batch / enumerate on ctx
  * (root chunk used or its upper bound, split flag, smallest split window,
  * smallest window counted in closed form, 1 if it came from the tune table);
- * each output may be NULL. tm_tune_save writes the table as text to path (host string);
- * tm_tune_load merges a saved table into ctx (TM_E_INVALID if the file
+ * each output may be NULL. tm_tune_save writes the table as text to path (host string;
+ * a "tmotif-tune 3" header, then per key: root chunk, split flag, smallest split
+ * window, closed-form threshold, workgroups per CU (0 = as many as fit), ms);
+ * tm_tune_load merges a saved table into ctx (version 2 tables, without the
+ * workgroups column, are read as 0 there; TM_E_INVALID if the file
  * cannot be read or is not a table; then nothing is merged); tm_tune_clear
  * empties it (n_removed, may be NULL, receives the number of entries). */
 tm_status tm_last_launch(tm_ctx *ctx, int64_t *root_chunk, int32_t *split, int64_t *split_min, int64_t *leaf_min,

@@ -229,9 +229,10 @@ GArgs base_args(const tm_ctx *ctx, const tm_graph *g, tm_ctx::Workspace *w, cons
     return a;
 }
 
-int grid_for(tm_ctx *ctx, const tmo::Module *mod, uint32_t lds_bytes) {
+int grid_for(tm_ctx *ctx, const tmo::Module *mod, uint32_t lds_bytes, int bpc) {
     if (ctx->grid > 0) return (int)ctx->grid;
     int per_cu = mod->max_blocks_per_cu > 0 ? mod->max_blocks_per_cu : 1;
+    if (bpc > 0) per_cu = std::min(per_cu, bpc);
     if (lds_bytes > 0) per_cu = std::max(1, std::min(per_cu, (int)(tmo::kLdsPerCu / lds_bytes)));
     return std::max(1, per_cu * std::max(ctx->num_cus, 1));
 }
@@ -272,7 +273,7 @@ tm_status sample_launch(tm_ctx *ctx, tm_ctx::Workspace *w, int64_t chunks, hipSt
 }
 
 tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int mode, GArgs *a,
-                 hipStream_t stream, bool timed) {
+                 hipStream_t stream, bool timed, int bpc) {
     hipFunction_t fn = mod->fn[mode];
     if (!fn) return fail(TM_E_DEVICE, "kernel variant missing from module");
     HIP_TRY(tmo::dev_fill_u64(w->ctl, 0, tmo::CTL_WORDS, stream), "reset counters");
@@ -323,7 +324,7 @@ tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int 
         HIP_TRY(hipEventRecord(w->tr_go, stream), "hipEventRecord");  // after the control words are reset
     }
     if (timed) HIP_TRY(hipEventRecord(w->ev0, stream), "hipEventRecord");
-    HIP_TRY(hipModuleLaunchKernel(fn, grid_for(ctx, mod, lds), 1, 1, ctx->block, 1, 1, lds, stream, params, nullptr),
+    HIP_TRY(hipModuleLaunchKernel(fn, grid_for(ctx, mod, lds, bpc), 1, 1, ctx->block, 1, 1, lds, stream, params, nullptr),
             "hipModuleLaunchKernel");
     if (timed) HIP_TRY(hipEventRecord(w->ev1, stream), "hipEventRecord");
     if (sampled) return sample_launch(ctx, w, a->total_chunks, stream);
@@ -408,7 +409,7 @@ tm_status run_single(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm
     a.rch = (int32_t)rch;
     a.nq = 1;
     const bool timed = cfg.timed;
-    tm_status s = launch(ctx, w, mod, mode, &a, stream, timed);
+    tm_status s = launch(ctx, w, mod, mode, &a, stream, timed, cfg.bpc);
     if (s != TM_OK) return s;
     if (timed) {
         HIP_TRY(hipEventSynchronize(w->ev1), "hipEventSynchronize");
@@ -486,6 +487,7 @@ bool tune_lookup(tm_ctx *ctx, const std::string &key, tmo::LaunchCfg *c) {
     c->split = it->second.split;
     c->split_min = it->second.split_min;
     c->leaf_min = it->second.leaf_min;
+    c->bpc = it->second.bpc;
     return true;
 }
 
@@ -571,6 +573,18 @@ tm_status run_tuned(tm_ctx *ctx, const std::string &key, int64_t roots, F &&once
                     if (st != TM_OK) return st;
                 }
             }
+            // stage 4: fewer workgroups per CU at the best setting (less
+            // contention for the caches and the work queues; a launch with
+            // little work to spread can run faster on fewer wavefronts)
+            if (have) {
+                const tmo::LaunchCfg base_c = best_c;
+                for (int b : {3, 2}) {
+                    tmo::LaunchCfg c = base_c;
+                    c.bpc = b;
+                    const tm_status st = trial(c);
+                    if (st != TM_OK) return st;
+                }
+            }
             if (have) {
                 std::lock_guard<std::mutex> lk(ctx->tune_mu);
                 tmo::TuneEntry e;
@@ -578,6 +592,7 @@ tm_status run_tuned(tm_ctx *ctx, const std::string &key, int64_t roots, F &&once
                 e.split = best_c.split;
                 e.split_min = best_c.split_min;
                 e.leaf_min = best_c.leaf_min;
+                e.bpc = best_c.bpc;
                 e.ms = best;
                 ctx->tune[key] = e;
             }
@@ -766,13 +781,14 @@ tm_status tm_last_launch(tm_ctx *ctx, int64_t *root_chunk, int32_t *split, int64
 
 tm_status tm_tune_save(tm_ctx *ctx, const char *path) {
     if (!ctx || !path) return fail(TM_E_INVALID, "null argument");
-    std::string text = "tmotif-tune 2\n";
+    std::string text = "tmotif-tune 3\n";
     {
         std::lock_guard<std::mutex> lk(ctx->tune_mu);
         char buf[128];
         for (const auto &kv : ctx->tune) {
-            std::snprintf(buf, sizeof(buf), " %lld %d %lld %lld %.6f\n", (long long)kv.second.rch, kv.second.split,
-                          (long long)kv.second.split_min, (long long)kv.second.leaf_min, kv.second.ms);
+            std::snprintf(buf, sizeof(buf), " %lld %d %lld %lld %d %.6f\n", (long long)kv.second.rch,
+                          kv.second.split, (long long)kv.second.split_min, (long long)kv.second.leaf_min,
+                          kv.second.bpc, kv.second.ms);
             text += kv.first + buf;
         }
     }
@@ -793,8 +809,10 @@ tm_status tm_tune_load(tm_ctx *ctx, const char *path) {
     while ((got_bytes = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got_bytes);
     std::fclose(f);
     const std::string bad = std::string("not a tune table: ") + path;
-    const std::string head = "tmotif-tune 2\n";
-    if (text.compare(0, head.size(), head) != 0) return fail(TM_E_INVALID, bad);
+    // version 2 tables have no workgroups-per-CU column (as many as fit)
+    const std::string head = "tmotif-tune 3\n", head2 = "tmotif-tune 2\n";
+    const bool v2 = text.compare(0, head2.size(), head2) == 0;
+    if (!v2 && text.compare(0, head.size(), head) != 0) return fail(TM_E_INVALID, bad);
     std::map<std::string, tmo::TuneEntry> got;
     size_t pos = head.size();
     while (pos < text.size()) {
@@ -805,18 +823,23 @@ tm_status tm_tune_load(tm_ctx *ctx, const char *path) {
         const size_t sp = line.find(' ');
         if (sp == 0 || sp == std::string::npos) return fail(TM_E_INVALID, bad);
         long long rch = 0, smin = 0, lmin = 0;
-        int split = 0;
+        int split = 0, bpc = 0;
         double ms = 0;
         char tail = 0;
-        if (std::sscanf(line.c_str() + sp, " %lld %d %lld %lld %lf %c", &rch, &split, &smin, &lmin, &ms, &tail) != 5 ||
-            rch < 1 || rch > (1 << 24) || (split != 0 && split != 1) || smin < 2 ||
-            (lmin != 0 && (lmin < 32 || lmin > (1 << 24))))
+        const int want = v2 ? 5 : 6;
+        const int got_n = v2 ? std::sscanf(line.c_str() + sp, " %lld %d %lld %lld %lf %c", &rch, &split, &smin, &lmin,
+                                           &ms, &tail)
+                             : std::sscanf(line.c_str() + sp, " %lld %d %lld %lld %d %lf %c", &rch, &split, &smin,
+                                           &lmin, &bpc, &ms, &tail);
+        if (got_n != want || rch < 1 || rch > (1 << 24) || (split != 0 && split != 1) || smin < 2 ||
+            (lmin != 0 && (lmin < 32 || lmin > (1 << 24))) || bpc < 0 || bpc > 64)
             return fail(TM_E_INVALID, bad);
         tmo::TuneEntry e;
         e.rch = rch;
         e.split = split;
         e.split_min = smin;
         e.leaf_min = lmin;
+        e.bpc = bpc;
         e.ms = ms;
         got[line.substr(0, sp)] = e;
     }
@@ -1426,7 +1449,7 @@ tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, cons
     a.out = d_out;
     a.capacity = capacity;
     const bool timed = cfg.timed;
-    st = launch(ctx, w, mod.get(), tmo::MODE_ENUM_WRITE, &a, stream, timed);
+    st = launch(ctx, w, mod.get(), tmo::MODE_ENUM_WRITE, &a, stream, timed, cfg.bpc);
     if (st != TM_OK) return st;
     HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
             "read overflow");
@@ -1507,7 +1530,7 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
             a.total_chunks = c0;
             a.rch = (int32_t)rch;
             a.nq = q;
-            tm_status st = launch(ctx, w, mod.get(), tmo::MODE_COUNT, &a, stream, c.timed);
+            tm_status st = launch(ctx, w, mod.get(), tmo::MODE_COUNT, &a, stream, c.timed, c.bpc);
             if (st != TM_OK) return st;
             if (c.timed) {
                 HIP_TRY(hipEventSynchronize(w->ev1), "hipEventSynchronize");

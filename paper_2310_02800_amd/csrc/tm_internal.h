@@ -267,6 +267,7 @@ struct LaunchCfg {
     int split = 0;          // hand pending windows of busy lanes to idle lanes / wavefronts
     int64_t split_min = 2;  // smallest pending window worth splitting
     int64_t leaf_min = 512; // smallest last-level window counted in closed form (0 = never)
+    int bpc = 0;            // workgroups per CU at most (0: as many as fit)
     bool timed = false;     // record HIP events around the launch
 };
 
@@ -276,6 +277,7 @@ struct TuneEntry {
     int split = 0;
     int64_t split_min = 2;
     int64_t leaf_min = 512;
+    int bpc = 0;
     double ms = 0.0;
 };
 

@@ -129,11 +129,20 @@ def test_tune_table_round_trip(tuned, tiny_g, tiny_og, tmp_path):
     setting = ctx.last_launch()
     path = tmp_path / "tune.txt"
     ctx.tune_save(path)
-    assert path.read_text().startswith("tmotif-tune 2\n")
+    text = path.read_text()
+    assert text.startswith("tmotif-tune 3\n")
     assert ctx.tune_clear() >= 1
     ctx.tune_load(path)
     assert ctx.count(tiny_g, mm) == want
     assert ctx.last_launch() == setting  # taken from the loaded table, no new trials
+    # a version-2 table (no workgroups-per-CU column) still loads
+    v2 = tmp_path / "tune2.txt"
+    lines = text.splitlines()
+    v2.write_text("tmotif-tune 2\n" + "".join(" ".join(l.split()[:5] + l.split()[6:]) + "\n" for l in lines[1:]))
+    assert ctx.tune_clear() >= 1
+    ctx.tune_load(v2)
+    assert ctx.count(tiny_g, mm) == want
+    assert ctx.last_launch() == setting
     bad = tmp_path / "bad.txt"
     bad.write_text("not a table\n")
     with pytest.raises(N.NativeError) as ei:
