@@ -146,6 +146,13 @@ void tm_destroy(tm_ctx *ctx);
  *                          step issues the reads of all lanes (search pivots,
  *                          candidate key and neighbour, list offsets of a level to
  *                          open) before using any, one wait per step
+ *   TM_PARAM_LINE_SAMPLES  64 (default) or more: windows over lists of at least this
+ *                          many entries first search the graph's line samples (one time
+ *                          key per 128 bytes of keys, built at load time; Sec. 5.1.1
+ *                          candidate caching), then one line of the list: a window
+ *                          opened on a long list reads about two cache lines from
+ *                          beyond the L2 instead of one per halving; 0 = off.
+ *                          Results are the same
  *   TM_PARAM_TRACE_US      0 (default) = off; 10..100000 = while each mining kernel
  *                          runs, sample its control words every this many
  *                          microseconds from a side stream (the kernel is not
@@ -167,7 +174,8 @@ enum {
     TM_PARAM_TRACE_US = 13,
     TM_PARAM_ROOT_HANDOFF = 14,
     TM_PARAM_HUB_LDS = 15,
-    TM_PARAM_STEP_FORM = 16
+    TM_PARAM_STEP_FORM = 16,
+    TM_PARAM_LINE_SAMPLES = 17
 };
 tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t value);
 

@@ -22,6 +22,7 @@ TM_PARAM_WORK_BUDGET, TM_PARAM_MIN_WAVES, TM_PARAM_LEAF_MIN, TM_PARAM_TRACE_US =
 TM_PARAM_ROOT_HANDOFF = 14
 TM_PARAM_HUB_LDS = 15
 TM_PARAM_STEP_FORM = 16
+TM_PARAM_LINE_SAMPLES = 17
 
 # Every function the header declares, for the export check.
 EXPORTED = [

@@ -47,7 +47,7 @@ struct DeviceGuard {
 void free_graph_buffers(tm_graph *g) {
     void *ptrs[] = {g->d_src, g->d_dst, g->d_tk, g->d_w, g->d_adj_t, g->d_adj_nbr, g->d_adj_eid, g->d_adj_w,
                     g->d_off_out, g->d_off_in, g->d_pos_out, g->d_pos_in, g->d_pr_nbr, g->d_pr_t, g->d_pr_pos,
-                    g->d_nlab, g->d_el, g->d_adj_el, g->d_hub};
+                    g->d_nlab, g->d_el, g->d_adj_el, g->d_hub, g->d_samp};
     for (void *p : ptrs)
         if (p) hipFree(p);
 }
@@ -221,6 +221,11 @@ GArgs base_args(const tm_ctx *ctx, const tm_graph *g, tm_ctx::Workspace *w, cons
     a.m_edges = g->m;
     a.split = c.split;
     a.leaf_min = (int32_t)c.leaf_min;
+    if (ctx->samp_min > 0 && g->d_samp) {
+        a.samp = g->d_samp;
+        a.samp_min = (uint32_t)ctx->samp_min;
+        a.samp_lg = g->samp_lg;
+    }
     if (ctx->hub_lds && g->d_hub) {
         a.hub = g->d_hub;
         a.hub_words = g->hub_words;
@@ -311,7 +316,7 @@ tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int 
         a->epoch = 0;
     }
     // the work-counter mode follows the byte model (full searches): no staging
-    if (mode == tmo::MODE_STATS) { a->hub = nullptr; a->hub_words = 0; a->hub_dmin = 0; }
+    if (mode == tmo::MODE_STATS) { a->hub = nullptr; a->hub_words = 0; a->hub_dmin = 0; a->samp_min = 0; }
     const uint32_t lds = a->hub_words * 4u;
     void *params[] = {a};
     const bool sampled = ctx->trace_us > 0 && !w->no_alloc;
@@ -731,6 +736,10 @@ tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t v) {
         if (v != 0 && v != 1) return fail(TM_E_INVALID, "step form must be 0 or 1");
         ctx->step_form = (int)v;
         return TM_OK;
+    case TM_PARAM_LINE_SAMPLES:
+        if (v != 0 && (v < 64 || v > (int64_t(1) << 30))) return fail(TM_E_INVALID, "line-sample threshold must be 0 or >= 64");
+        ctx->samp_min = v;
+        return TM_OK;
     default:
         return fail(TM_E_INVALID, "unknown parameter");
     }
@@ -754,6 +763,7 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *v) {
     case TM_PARAM_ROOT_HANDOFF: *v = ctx->root_handoff; return TM_OK;
     case TM_PARAM_HUB_LDS: *v = ctx->hub_lds; return TM_OK;
     case TM_PARAM_STEP_FORM: *v = ctx->step_form; return TM_OK;
+    case TM_PARAM_LINE_SAMPLES: *v = ctx->samp_min; return TM_OK;
     default: return fail(TM_E_INVALID, "unknown parameter");
     }
 }
@@ -1060,6 +1070,16 @@ tm_status tm_load_graph(tm_ctx *ctx, int64_t n, int64_t m, const int32_t *src, c
     if (e != hipSuccess) return cleanup(hip_fail(e, "pair list build"));
     e = build_hub_table(g, s, &acc);
     if (e != hipSuccess) return cleanup(hip_fail(e, "hub table build"));
+    // line samples: one key per 128 bytes of keys (a cache line)
+    g->samp_lg = g->key_bytes == 4 ? 5 : 4;
+    {
+        const int64_t ns = (2 * m + (int64_t(1) << g->samp_lg) - 1) >> g->samp_lg;
+        e = hipMalloc(&g->d_samp, std::max<int64_t>(ns, 1) * g->key_bytes);
+        if (e == hipSuccess) acc += std::max<int64_t>(ns, 1) * g->key_bytes;
+        if (e == hipSuccess) e = tmo::dev_line_samples(ns, g->d_adj_t, g->key_bytes, g->samp_lg, g->d_samp, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "line samples"));
+    }
     g->device_bytes = acc;
     hipStreamDestroy(s);
     *out = g;

@@ -252,13 +252,28 @@ struct GArgs {
   const u32* pr_pos;
   const int* el; const int* adj_el;
   const u32* hub; u32 hub_words; u32 hub_dmin;
+  const tkey* samp; u32 samp_min; int samp_lg;
 };
 static_assert(sizeof(QArgs) == 384, "QArgs layout");
-static_assert(sizeof(GArgs) == 272, "GArgs layout");
+static_assert(sizeof(GArgs) == 288, "GArgs layout");
 // Hub-list samples staged by the workgroup (launches with hub_words > 0):
 // [0] H, [1, 1+H) list starts (ascending), [1+H, 2+2H) sample offsets,
 // [2+2H, 2+3H) log2 strides, time keys from word 2+3H rounded up to even.
 extern __shared__ u32 lds_hub[];
+// A window over [lo, hi) of the unified adjacency: the line samples
+// (smp[j] = key at position j << lg) inside the range are searched first, which
+// leaves to the search over the list the positions between the last sample
+// <= x and the next one: one line of keys instead of one line per halving.
+__device__ __forceinline__ void line_narrow(const tkey* smp, int lg, u32 lo, u32 hi, tkey x, u32& sb, u32& sn) {
+  const u32 j0 = (lo + (1u << lg) - 1u) >> lg, j1 = (hi - 1u) >> lg;
+  if (j0 > j1) return;
+  u32 b = j0, k = j1 - j0 + 1u;
+  while (k > 0u) { const u32 h2 = k >> 1; if (smp[b + h2] <= x) { b += h2 + 1u; k -= h2 + 1u; } else { k = h2; } }
+  // b: the first sample in range with key > x (j1 + 1 if none)
+  const u32 nlo = b == j0 ? lo : ((b - 1u) << lg) + 1u;
+  const u32 nhi = b <= j1 ? (b << lg) : hi;
+  sb = nlo; sn = nhi - nlo;
+}
 // A window over the hub list that starts at adjacency position lo: locate the
 // first key > x among the list's samples in LDS and leave [sb, sb+sn) to the
 // search in HBM, one stride at most; lists not in the table are left as they are.
@@ -689,11 +704,22 @@ struct Emitter {
           << " = (tkey)(h_ < (i64)tmaxk ? h_ : (i64)tmaxk); }\n";
         o << ind << "  sb = lo_; sn = hi_ - lo_; sx = (" << tp << "); lvl = " << i << ";\n";
         o << ind << "  if (MODE == 1) { st_win++; st_probe += bitlen(sn); }\n";
-        if (G)
+        // a long window first searches the line samples inside the list
+        // (phase 5: sb, sn index the samples; cur<i> keeps the list start)
+        o << ind << "  bool ls_ = false;\n";
+        if (G) {
             o << ind << "  if (MODE != 1 && g.hub_words != 0u && gk" << i << " != 3 && sn >= g.hub_dmin) hub_narrow(lo_, sx, sb, sn);\n";
-        else if (p.kind[i] != LIST_GLOBAL)
+            o << ind << "  if (MODE != 1 && g.samp_min != 0u && gk" << i << " != 3 && sn >= g.samp_min) {\n";
+        } else if (p.kind[i] != LIST_GLOBAL) {
             o << ind << "  if (MODE != 1 && g.hub_words != 0u && sn >= g.hub_dmin) hub_narrow(lo_, sx, sb, sn);\n";
-        o << ind << "  if (sn == 0u) { cur" << i << " = sb; ph = 0; } else { ph = 1; }\n";
+            o << ind << "  if (MODE != 1 && g.samp_min != 0u && sn >= g.samp_min) {\n";
+        }
+        if (G || p.kind[i] != LIST_GLOBAL) {
+            o << ind << "    const u32 j0 = (lo_ + (1u << g.samp_lg) - 1u) >> g.samp_lg, j1 = (hi_ - 1u) >> g.samp_lg;\n";
+            o << ind << "    if (j0 <= j1) { cur" << i << " = lo_; sb = j0; sn = j1 - j0 + 1u; ls_ = true; }\n";
+            o << ind << "  }\n";
+        }
+        o << ind << "  if (ls_) ph = 5; else if (sn == 0u) { cur" << i << " = sb; ph = 0; } else { ph = 1; }\n";
         o << ind << "}\n";
     }
 
@@ -738,7 +764,10 @@ struct Emitter {
             return;
         }
         o << ind << "if (MODE == 1) { st_win++; st_probe += bitlen(sn); }\n";
-        if (hub) o << ind << "if (MODE != 1 && g.hub_words != 0u && sn >= g.hub_dmin) hub_narrow(lo_, sx, sb, sn);\n";
+        if (hub) {
+            o << ind << "if (MODE != 1 && g.hub_words != 0u && sn >= g.hub_dmin) hub_narrow(lo_, sx, sb, sn);\n";
+            o << ind << "if (MODE != 1 && g.samp_min != 0u && sn >= g.samp_min) line_narrow(g.samp, g.samp_lg, lo_, hi_, sx, sb, sn);\n";
+        }
         o << ind << "if (sn == 0u) { cur" << i << " = sb; ph = 0; } else { ph = 1; }\n";
     }
 
@@ -764,6 +793,8 @@ struct Emitter {
             o << in2 << "if (MODE == 1) { st_win++; st_probe += bitlen(sn); }\n";
             o << in2 << "if (MODE != 1 && g.hub_words != 0u && gk" << s
               << " != 3 && sn >= g.hub_dmin) hub_narrow(lo_, sx, sb, sn);\n";
+            o << in2 << "if (MODE != 1 && g.samp_min != 0u && gk" << s
+              << " != 3 && sn >= g.samp_min) line_narrow(g.samp, g.samp_lg, lo_, hi_, sx, sb, sn);\n";
             o << in2 << "if (sn == 0u) { cur" << i << " = sb; ph = 0; } else { ph = 1; }\n";
             o << ind << "}\n";
             return;
@@ -1707,23 +1738,23 @@ struct Emitter {
         if (L > 1 && F) step_fused();
         if (L > 1 && !F) {
             // ---------------- search probe
-            o << "    if (lvl > 0 && (ph == 1 || ph == 2)) {\n";
+            o << "    if (lvl > 0 && (ph == 1 || ph == 2 || ph == 5)) {\n";
             if (G) {
-                o << "      const tkey* sarr = ((gglob >> lvl) & 1u) ? g.tk : g.adj_t;\n";
+                o << "      const tkey* sarr = ph == 5 ? g.samp : ((gglob >> lvl) & 1u) ? g.tk : g.adj_t;\n";
             } else if (glob) {
                 o << "      bool gl = false;\n";
                 for (int i = 1; i < L; i++)
                     if (p.kind[i] == LIST_GLOBAL) o << "      gl = gl || lvl == " << i << ";\n";
-                o << "      const tkey* sarr = gl ? g.tk : g.adj_t;\n";
+                o << "      const tkey* sarr = ph == 5 ? g.samp : gl ? g.tk : g.adj_t;\n";
             } else {
-                o << "      const tkey* sarr = g.adj_t;\n";
+                o << "      const tkey* sarr = ph == 5 ? g.samp : g.adj_t;\n";
             }
             // ph 2: first probe at the window start (tie skip after a jump).
             // A search of 3 or more unknown entries reads three pivots at
             // once and keeps one of the four ranges between them: half as
             // many dependent steps as a binary search, the three reads in
             // flight together.
-            o << "      if (ph == 1 && sn >= 3u) {\n";
+            o << "      if (ph != 2 && sn >= 3u) {\n";
             o << "        const u32 o1 = ((sn + 1u) >> 2) - 1u, o2 = ((2u * (sn + 1u)) >> 2) - 1u, "
                  "o3 = ((3u * (sn + 1u)) >> 2) - 1u;\n";
             o << "        const tkey v1 = sarr[sb + o1], v2 = sarr[sb + o2], v3 = sarr[sb + o3];\n";
@@ -1736,7 +1767,21 @@ struct Emitter {
             o << "        const tkey v = sarr[mid];\n";
             o << "        if (v <= sx) { sb = mid + 1u; sn = sn - half - 1u; } else { sn = half; }\n";
             o << "      }\n";
-            o << "      ph = 1;\n";
+            o << "      if (ph == 2) ph = 1;\n";
+            // the samples' search ended at the first sample > sx (index sb):
+            // the list's first key > sx lies after the sample before it and
+            // at or before that one
+            o << "      if (ph == 5 && sn == 0u) {\n";
+            o << "        u32 lo_ = 0u, hi_ = 0u;\n";
+            o << "        switch (lvl) {\n";
+            for (int i = 1; i < L; i++) o << "          case " << i << ": lo_ = cur" << i << "; hi_ = end" << i << "; break;\n";
+            o << "          default: break;\n";
+            o << "        }\n";
+            o << "        const u32 j0 = (lo_ + (1u << g.samp_lg) - 1u) >> g.samp_lg, j1 = (hi_ - 1u) >> g.samp_lg;\n";
+            o << "        const u32 nlo = sb == j0 ? lo_ : ((sb - 1u) << g.samp_lg) + 1u;\n";
+            o << "        const u32 nhi = sb <= j1 ? (sb << g.samp_lg) : hi_;\n";
+            o << "        sb = nlo; sn = nhi - nlo; ph = 1;\n";
+            o << "      }\n";
             search_done();
             o << "    } else if (lvl > 0 && ph == 0) {\n";
             // ---------------- candidate scan

@@ -207,6 +207,25 @@ hipError_t dev_hub_samples(uint32_t *d_tab, uint32_t base, uint32_t total, const
     return hipGetLastError();
 }
 
+// Line samples of the unified adjacency: samp[j] = adj_t[j << lg], one time
+// key per 2^lg positions (one cache line of keys), a search index that is
+// 2^lg times smaller than the lists it covers.
+template <typename K>
+__global__ void k_line_samples(int64_t n, const K *adj_t, int lg, K *samp) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        samp[j] = adj_t[j << lg];
+}
+
+hipError_t dev_line_samples(int64_t n, const void *adj_t, int key_bytes, int lg, void *samp, hipStream_t s) {
+    clear_stale_error();
+    if (n <= 0) return hipSuccess;
+    if (key_bytes == 4)
+        k_line_samples<int32_t><<<blocks_for(n), kThreads, 0, s>>>(n, (const int32_t *)adj_t, lg, (int32_t *)samp);
+    else
+        k_line_samples<int64_t><<<blocks_for(n), kThreads, 0, s>>>(n, (const int64_t *)adj_t, lg, (int64_t *)samp);
+    return hipGetLastError();
+}
+
 // Device scratch of tm_count_batch_noalloc, for callers that cannot allocate
 // device memory: control words, per-query counts, queue heads and launch
 // arguments, and the donated-work items, in one statically sized array each

@@ -87,8 +87,11 @@ struct GArgs {
     const uint32_t *hub;      // hub-list sample table staged in LDS by every workgroup, or null
     uint32_t hub_words;       // its size in 32-bit words (0: no staging)
     uint32_t hub_dmin;        // shortest hub list: only windows over lists this long look it up
+    const void *samp;         // line samples of adj_t: samp[j] = adj_t[j << samp_lg]
+    uint32_t samp_min;        // windows over at least this many entries search the samples first (0: never)
+    int32_t samp_lg;
 };
-static_assert(sizeof(GArgs) == 272, "GArgs layout");
+static_assert(sizeof(GArgs) == 288, "GArgs layout");
 
 // Hub-list staging (LDS): the longest adjacency lists each get up to
 // kHubSamplesPerList time keys sampled at a power-of-two stride (at least 32,
@@ -240,6 +243,8 @@ std::atomic<uint32_t> *scratch_epoch(int device);
 std::mutex *scratch_mutex(int device);
 // out[p] = el[eid[p]] for p < n (edge labels into adjacency order)
 hipError_t dev_gather_i32(int64_t n, const int32_t *eid, const int32_t *el, int32_t *out, hipStream_t s);
+// samp[j] = adj_t[j << lg] for j < n (line samples of the unified adjacency).
+hipError_t dev_line_samples(int64_t n, const void *adj_t, int key_bytes, int lg, void *samp, hipStream_t s);
 // Fill the samples of a hub table whose header is in place (see build_hub_table).
 hipError_t dev_hub_samples(uint32_t *d_tab, uint32_t base, uint32_t total, const void *adj_t, int key_bytes,
                            hipStream_t s);
@@ -340,6 +345,7 @@ struct tm_ctx {
     int64_t trace_us = 0;     // launch sampling period (0 = off)
     int root_handoff = 1;     // hand unstarted roots to waiting wavefronts once the queue is empty
     int hub_lds = 0;          // stage the hub lists' sampled keys in LDS (TM_PARAM_HUB_LDS)
+    int64_t samp_min = 64;    // windows this long search the line samples first (TM_PARAM_LINE_SAMPLES, 0 = off)
     int step_form = tmo::kDefaultStepForm;  // matcher loop step form (TM_PARAM_STEP_FORM)
     std::vector<int64_t> trace;  // samples of the last sampled launch, kTraceCols each
     void *scratch = nullptr;     // this device's no-allocation scratch (tm_count_batch_noalloc)
@@ -370,6 +376,8 @@ struct tm_graph {
     int32_t *d_adj_el = nullptr;  // the same in adjacency order (2m entries)
     bool has_edge_labels = false;
     uint32_t *d_hub = nullptr;    // hub-list sample table (see kHubMaxWords), or null
+    void *d_samp = nullptr;       // line samples of d_adj_t (one key per 128 bytes of keys)
+    int samp_lg = 5;              // log2 of the sample stride
     uint32_t hub_words = 0, hub_dmin = 0;
     int32_t hub_lists = 0;
     std::vector<int64_t> h_t;     // sorted absolute times (root-range lookup)
