@@ -685,7 +685,9 @@ def main():
         mot = motifs[args.query_only]
         h = ctx.compile(mot)
         c = ctx.count(dg, h, stream=stream)  # compiles, tunes (autotuning on) and loads
-        st = ctx.work_stats(dg, h, stream=stream, leaf=True)
+        s0 = ctx.last_launch_full()
+        with fixed_setting(ctx, s0[0], s0[1], s0[3], s0[4]):  # closed-form counters at the launch's threshold
+            st = ctx.work_stats(dg, h, stream=stream, leaf=True)
         tb = dg.info()["key_bytes"]
         ms, wall = time_launches(ctx, lambda: ctx.count(dg, h, stream=stream), args.steps, args.warmup, 1)
         setting = ctx.last_launch_full()
@@ -709,8 +711,22 @@ def main():
     batch_setting = ctx.last_launch_full()
     log(f"compiled: single {compile_single_s:.2f} s, batch {compile_batch_s:.2f} s")
 
-    # work counters (untimed) for the byte model
-    stats = [ctx.work_stats(dg, h, stream=stream, leaf=True) for h in handles]
+    # work counters (untimed) for the byte models; the closed-form counters
+    # at the closed-form threshold of the launch they describe (the batch's,
+    # and each query's own tuned one for the per-query figures)
+    with fixed_setting(ctx, batch_setting[0], batch_setting[1], batch_setting[3], batch_setting[4]):
+        stats = [ctx.work_stats(dg, h, stream=stream, leaf=True) for h in handles]
+    q_setting = []
+    for h in handles:
+        ctx.count(dg, h, stream=stream)  # tunes, or loads the shipped setting
+        q_setting.append(ctx.last_launch_full())
+    q_stats = []
+    for h, qs_, st_ in zip(handles, q_setting, stats):
+        if qs_[4] == batch_setting[4]:
+            q_stats.append(st_)
+        else:
+            with fixed_setting(ctx, qs_[0], qs_[1], qs_[3], qs_[4]):
+                q_stats.append(ctx.work_stats(dg, h, stream=stream, leaf=True))
     counts = [s["matches"] for s in stats]
     assert counts == counts_b, (counts, counts_b)
     total_instances = sum(counts)
@@ -811,10 +827,12 @@ def main():
     roof_closed = roofline_entry(kname, CLOSED_MODEL, bytes_per_launch, avg_launch_ms, traffic_for(batch_setting))
     q_ms = [statistics.mean(kms_plain[i::len(handles)]) for i in range(len(handles))]
     per_query = []
-    for i, (m, s_, c) in enumerate(zip(motifs, stats, counts)):
+    for i, (m, s_, c) in enumerate(zip(motifs, q_stats, counts)):
         mb, ab = method_bytes(s_, m.l, tb=tb), algorithmic_bytes(s_, m.l, tb=tb)
         per_query.append({"edges": m.edges, "delta": m.delta, "count": c,
                           "kernel_ms": q_ms[i], "algorithmic_bytes": ab,
+                          "launch": {"root_chunk": q_setting[i][0], "split": q_setting[i][1],
+                                     "split_min": q_setting[i][3], "leaf_min": q_setting[i][4]},
                           "frac_closed_form_model": ab / (q_ms[i] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "kernel_ms_closed_form_off": open_q[i], "method_bytes": mb,
                           "frac_method_model": mb / (open_q[i] * 1e-3) / 1e9 / HBM_PEAK_GBS})
