@@ -47,7 +47,7 @@ struct DeviceGuard {
 void free_graph_buffers(tm_graph *g) {
     void *ptrs[] = {g->d_src, g->d_dst, g->d_tk, g->d_w, g->d_adj_t, g->d_adj_nbr, g->d_adj_eid, g->d_adj_w,
                     g->d_off_out, g->d_off_in, g->d_pos_out, g->d_pos_in, g->d_pr_nbr, g->d_pr_t, g->d_pr_pos,
-                    g->d_nlab, g->d_el, g->d_adj_el, g->d_hub, g->d_samp};
+                    g->d_nlab, g->d_el, g->d_adj_el, g->d_hub, g->d_samp, g->d_pr_samp};
     for (void *p : ptrs)
         if (p) hipFree(p);
 }
@@ -225,6 +225,7 @@ GArgs base_args(const tm_ctx *ctx, const tm_graph *g, tm_ctx::Workspace *w, cons
         a.samp = g->d_samp;
         a.samp_min = (uint32_t)ctx->samp_min;
         a.samp_lg = g->samp_lg;
+        a.pr_samp = g->d_pr_samp;
     }
     if (ctx->hub_lds && g->d_hub) {
         a.hub = g->d_hub;
@@ -316,7 +317,7 @@ tm_status launch(tm_ctx *ctx, tm_ctx::Workspace *w, const tmo::Module *mod, int 
         a->epoch = 0;
     }
     // the work-counter mode follows the byte model (full searches): no staging
-    if (mode == tmo::MODE_STATS) { a->hub = nullptr; a->hub_words = 0; a->hub_dmin = 0; a->samp_min = 0; }
+    if (mode == tmo::MODE_STATS) { a->hub = nullptr; a->hub_words = 0; a->hub_dmin = 0; a->samp_min = 0; a->pr_samp = nullptr; }
     const uint32_t lds = a->hub_words * 4u;
     void *params[] = {a};
     const bool sampled = ctx->trace_us > 0 && !w->no_alloc;
@@ -1077,6 +1078,10 @@ tm_status tm_load_graph(tm_ctx *ctx, int64_t n, int64_t m, const int32_t *src, c
         e = hipMalloc(&g->d_samp, std::max<int64_t>(ns, 1) * g->key_bytes);
         if (e == hipSuccess) acc += std::max<int64_t>(ns, 1) * g->key_bytes;
         if (e == hipSuccess) e = tmo::dev_line_samples(ns, g->d_adj_t, g->key_bytes, g->samp_lg, g->d_samp, s);
+        // and every 32nd neighbour id of the pair-sorted lists (int32: one per line)
+        const int64_t np = (2 * m + 31) >> 5;
+        if (e == hipSuccess) e = dmalloc(&g->d_pr_samp, np, &acc);
+        if (e == hipSuccess) e = tmo::dev_line_samples(np, g->d_pr_nbr, 4, 5, g->d_pr_samp, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return cleanup(hip_fail(e, "line samples"));
     }

@@ -253,9 +253,10 @@ struct GArgs {
   const int* el; const int* adj_el;
   const u32* hub; u32 hub_words; u32 hub_dmin;
   const tkey* samp; u32 samp_min; int samp_lg;
+  const int* pr_samp;
 };
 static_assert(sizeof(QArgs) == 384, "QArgs layout");
-static_assert(sizeof(GArgs) == 288, "GArgs layout");
+static_assert(sizeof(GArgs) == 296, "GArgs layout");
 // Hub-list samples staged by the workgroup (launches with hub_words > 0):
 // [0] H, [1, 1+H) list starts (ascending), [1+H, 2+2H) sample offsets,
 // [2+2H, 2+3H) log2 strides, time keys from word 2+3H rounded up to even.
@@ -360,8 +361,16 @@ __device__ __forceinline__ u32 win_len(const tkey* at, u32 c, u32 e, tkey t, u32
   return lo - c;
 }
 // In one node's list [lo, hi) sorted by (neighbour, time): the first entry
-// with neighbour >= x.
-__device__ __forceinline__ u32 nbr_lb(const int* pn, u32 lo, u32 hi, int x, u32& pr) {
+// with neighbour >= x. With ps (every 32nd neighbour id of the lists), a list
+// of 64+ entries is first narrowed to the line after the last sample < x.
+__device__ __forceinline__ u32 nbr_lb(const int* pn, const int* ps, u32 lo, u32 hi, int x, u32& pr) {
+  if (ps && hi - lo >= 64u) {
+    const u32 j0 = (lo + 31u) >> 5, j1 = (hi - 1u) >> 5;
+    u32 b = j0, k = j1 - j0 + 1u;
+    while (k > 0u) { const u32 h = k >> 1; if (ps[b + h] < x) { b += h + 1u; k -= h + 1u; } else k = h; }
+    const u32 nlo = b == j0 ? lo : ((b - 1u) << 5) + 1u, nhi = b <= j1 ? (b << 5) : hi;
+    lo = nlo; hi = nhi;
+  }
   u32 n = hi - lo;
   while (n > 0u) { const u32 h = n >> 1, m = lo + h; ++pr; if (pn[m] < x) { lo = m + 1u; n -= h + 1u; } else n = h; }
   return lo;
@@ -385,9 +394,9 @@ __device__ __forceinline__ u32 run_ub(const int* pn, const tkey* pt, u32 s, u32 
   return lo;
 }
 // Entries of [lo, hi) with neighbour x and time in (t0, t1], t0 < t1.
-__device__ __forceinline__ u32 pair_cnt(const int* pn, const tkey* pt, u32 lo, u32 hi, int x, tkey t0, tkey t1,
-                                        u32& pr) {
-  const u32 s = nbr_lb(pn, lo, hi, x, pr);
+__device__ __forceinline__ u32 pair_cnt(const int* pn, const int* ps, const tkey* pt, u32 lo, u32 hi, int x, tkey t0,
+                                        tkey t1, u32& pr) {
+  const u32 s = nbr_lb(pn, ps, lo, hi, x, pr);
   ++pr;
   if (s >= hi || pn[s] != x) return 0u;
   return run_ub(pn, pt, s, hi, x, t1, pr) - run_ub(pn, pt, s, hi, x, t0, pr);
@@ -1319,7 +1328,7 @@ struct Emitter {
         if (G) {
             o << in << "if (gk" << s << " == 2) {\n";
             o << in << "  const int u_ = mget(ga" << s << ");\n";
-            o << in << "  lc_ = pair_cnt(g.pr_nbr, g.pr_t, g.off_out[u_], g.off_out[u_ + 1], mget(gb" << s
+            o << in << "  lc_ = pair_cnt(g.pr_nbr, prs, g.pr_t, g.off_out[u_], g.off_out[u_ + 1], mget(gb" << s
               << "), sx, hi" << s << ", pr_);\n";
             if (need_w)
                 o << in << "  w_ = win_len(g.adj_t, cur" << s << ", end" << s << ", hi" << s << ", pr_);\n";
@@ -1330,11 +1339,11 @@ struct Emitter {
               << "g.off_in[u_ + 1];\n";
             o << in << "  w_ = win_len(g.adj_t, cur" << s << ", end" << s << ", hi" << s << ", pr_); lc_ = w_;\n";
             o << in << "  for (int v_ = 0; v_ < 8; ++v_)\n";
-            o << in << "    if ((gm" << s << " >> v_) & 1u) lc_ -= pair_cnt(g.pr_nbr, g.pr_t, plo, phi, mget(v_), sx, hi"
+            o << in << "    if ((gm" << s << " >> v_) & 1u) lc_ -= pair_cnt(g.pr_nbr, prs, g.pr_t, plo, phi, mget(v_), sx, hi"
               << s << ", pr_);\n";
             o << in << "}\n";
         } else if (p.kind[i] == LIST_BOTH) {
-            o << in << "lc_ = pair_cnt(g.pr_nbr, g.pr_t, g.off_out[m" << p.a[i] << "], g.off_out[m" << p.a[i]
+            o << in << "lc_ = pair_cnt(g.pr_nbr, prs, g.pr_t, g.off_out[m" << p.a[i] << "], g.off_out[m" << p.a[i]
               << " + 1], m" << p.b[i] << ", sx, hi" << s << ", pr_);\n";
             if (need_w) o << in << "w_ = win_len(g.adj_t, cur" << s << ", end" << s << ", hi" << s << ", pr_);\n";
         } else if (leaf_cache()) {
@@ -1349,7 +1358,7 @@ struct Emitter {
             for (int v : p.mapped[i]) {
                 if (!fixed_at_leaf(v)) continue;
                 const std::string V = I(v);
-                o << in << "  ls" << V << " = nbr_lb(g.pr_nbr, plo, phi, m" << V << ", pr_); ++pr_;\n";
+                o << in << "  ls" << V << " = nbr_lb(g.pr_nbr, prs, plo, phi, m" << V << ", pr_); ++pr_;\n";
                 o << in << "  if (ls" << V << " >= phi || g.pr_nbr[ls" << V << "] != m" << V << ") ls" << V << " = ~0u;\n";
                 o << in << "  else if (q_gf) le" << V << " = run_ub(g.pr_nbr, g.pr_t, ls" << V << ", phi, m" << V << ", "
                   << h << ", pr_);\n";
@@ -1373,10 +1382,10 @@ struct Emitter {
                     o << in << "  lc_ -= (u64)(run_ub(g.pr_nbr, g.pr_t, s_, phi, m" << V << ", " << h
                       << ", pr_) - run_ub(g.pr_nbr, g.pr_t, s_, phi, m" << V << ", sx, pr_));\n";
                     o << in << "} else {\n";
-                    o << in << "  lc_ -= pair_cnt(g.pr_nbr, g.pr_t, plo, phi, m" << V << ", sx, " << h << ", pr_);\n";
+                    o << in << "  lc_ -= pair_cnt(g.pr_nbr, prs, g.pr_t, plo, phi, m" << V << ", sx, " << h << ", pr_);\n";
                     o << in << "}\n";
                 } else
-                    o << in << "lc_ -= pair_cnt(g.pr_nbr, g.pr_t, plo, phi, m" << V << ", sx, " << h << ", pr_);\n";
+                    o << in << "lc_ -= pair_cnt(g.pr_nbr, prs, g.pr_t, plo, phi, m" << V << ", sx, " << h << ", pr_);\n";
             }
         } else {
             const bool out = p.kind[i] == LIST_OUT;
@@ -1385,7 +1394,7 @@ struct Emitter {
             o << in << "const u32 plo = " << off << "[m" << u << "], phi = " << off << "[m" << u << " + 1];\n";
             o << in << "w_ = win_len(g.adj_t, cur" << s << ", end" << s << ", hi" << s << ", pr_); lc_ = w_;\n";
             for (int v : p.mapped[i])
-                o << in << "lc_ -= pair_cnt(g.pr_nbr, g.pr_t, plo, phi, m" << v << ", sx, hi" << s << ", pr_);\n";
+                o << in << "lc_ -= pair_cnt(g.pr_nbr, prs, g.pr_t, plo, phi, m" << v << ", sx, hi" << s << ", pr_);\n";
         }
     }
 
@@ -1537,7 +1546,7 @@ struct Emitter {
             o << "__device__ __forceinline__ bool anti_free(const GArgs& g, int u, int v, tkey t0, i64 d) {\n";
             o << "  const u32 lo = g.off_out[u], hi = g.off_out[u + 1];\n";
             o << "  u32 pr = 0u;\n";
-            o << "  const u32 s = nbr_lb(g.pr_nbr, lo, hi, v, pr);\n";
+            o << "  const u32 s = nbr_lb(g.pr_nbr, g.samp_min != 0u ? g.pr_samp : nullptr, lo, hi, v, pr);\n";
             o << "  if (s >= hi || g.pr_nbr[s] != v) return true;\n";
             o << "  const u32 f = run_ub(g.pr_nbr, g.pr_t, s, hi, v, (tkey)(t0 - 1), pr);\n";
             o << "  if (f >= hi || g.pr_nbr[f] != v) return true;\n";
@@ -1559,6 +1568,7 @@ struct Emitter {
         }
         o << "  const int lane = lane_id();\n";
         o << "  const qptr q = (qptr)(g.qa + qi);  // uniform: scalar loads\n";
+        o << "  const int* const prs = MODE != 1 ? g.pr_samp : nullptr;  // pair-list line samples (not in the byte model's mode)\n";
         o << "  const i64 q_r0 = q->r0, q_delta = q->delta, q_c0 = q->c0, q_c1 = q->c0 + q->nchunks;\n";
         o << "  // chunk j of a query holds its roots j, j + nchunks, j + 2 nchunks, ...: a burst of\n";
         o << "  // consecutive heavy roots spreads over many wavefronts\n";

@@ -90,8 +90,9 @@ struct GArgs {
     const void *samp;         // line samples of adj_t: samp[j] = adj_t[j << samp_lg]
     uint32_t samp_min;        // windows over at least this many entries search the samples first (0: never)
     int32_t samp_lg;
+    const int32_t *pr_samp;   // line samples of pr_nbr: pr_samp[j] = pr_nbr[32 j], or null
 };
-static_assert(sizeof(GArgs) == 288, "GArgs layout");
+static_assert(sizeof(GArgs) == 296, "GArgs layout");
 
 // Hub-list staging (LDS): the longest adjacency lists each get up to
 // kHubSamplesPerList time keys sampled at a power-of-two stride (at least 32,
@@ -377,6 +378,7 @@ struct tm_graph {
     bool has_edge_labels = false;
     uint32_t *d_hub = nullptr;    // hub-list sample table (see kHubMaxWords), or null
     void *d_samp = nullptr;       // line samples of d_adj_t (one key per 128 bytes of keys)
+    int32_t *d_pr_samp = nullptr; // line samples of d_pr_nbr (every 32nd neighbour id)
     int samp_lg = 5;              // log2 of the sample stride
     uint32_t hub_words = 0, hub_dmin = 0;
     int32_t hub_lists = 0;
