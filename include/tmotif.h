@@ -153,6 +153,14 @@ void tm_destroy(tm_ctx *ctx);
  *                          opened on a long list reads about two cache lines from
  *                          beyond the L2 instead of one per halving; 0 = off.
  *                          Results are the same
+ *   TM_PARAM_XCD_ORDER     0 (default) = chunk j of a query holds its roots j, j + C,
+ *                          j + 2C, ... (C chunks: a burst of heavy roots spreads over
+ *                          many wavefronts); 1 = chunks are contiguous root ranges in
+ *                          time order, cut into 8 slices, and workgroup b takes
+ *                          chunks from slice b mod 8 (its XCD under round-robin
+ *                          dispatch; a slice that runs dry hands over to the next),
+ *                          so one XCD's L2 serves the adjacency of a narrow time
+ *                          range. Results are the same
  *   TM_PARAM_TRACE_US      0 (default) = off; 10..100000 = while each mining kernel
  *                          runs, sample its control words every this many
  *                          microseconds from a side stream (the kernel is not
@@ -175,7 +183,8 @@ enum {
     TM_PARAM_ROOT_HANDOFF = 14,
     TM_PARAM_HUB_LDS = 15,
     TM_PARAM_STEP_FORM = 16,
-    TM_PARAM_LINE_SAMPLES = 17
+    TM_PARAM_LINE_SAMPLES = 17,
+    TM_PARAM_XCD_ORDER = 18
 };
 tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t value);
 

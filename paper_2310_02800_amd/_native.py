@@ -23,6 +23,7 @@ TM_PARAM_ROOT_HANDOFF = 14
 TM_PARAM_HUB_LDS = 15
 TM_PARAM_STEP_FORM = 16
 TM_PARAM_LINE_SAMPLES = 17
+TM_PARAM_XCD_ORDER = 18
 
 # Every function the header declares, for the export check.
 EXPORTED = [

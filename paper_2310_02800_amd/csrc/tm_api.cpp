@@ -167,6 +167,7 @@ void fill_qargs(const tm_graph *g, const tm_motif *m, int64_t r0, int64_t r1, in
     for (int j = 0; j < m->plan.n_anti; j++) q->gap[tmo::anti_slot(j)] = std::min<int64_t>(m->plan.anti_delta[j], span);
     q->c0 = c0;
     q->nchunks = (r1 - r0 + rch - 1) / rch;
+    q->xns = (q->nchunks + 7) / 8;
     q->fn = fn;
     q->budget = budget;
     q->split = split;
@@ -190,6 +191,17 @@ void fill_qargs(const tm_graph *g, const tm_motif *m, int64_t r0, int64_t r1, in
         q->plev[j] = (uint8_t)p.pred_lvl[j];
     }
     tmo::fill_plan_tables(p, q);
+}
+
+// XCD order: each query's slices start where the previous query's end in
+// every XCD's chunk sequence; returns that sequence's length.
+int64_t xcd_prefix(QArgs *q, int nq) {
+    int64_t s = 0;
+    for (int i = 0; i < nq; i++) {
+        q[i].xs0 = s;
+        s += q[i].xns;
+    }
+    return s;
 }
 
 GArgs base_args(const tm_ctx *ctx, const tm_graph *g, tm_ctx::Workspace *w, const tmo::LaunchCfg &c) {
@@ -221,6 +233,7 @@ GArgs base_args(const tm_ctx *ctx, const tm_graph *g, tm_ctx::Workspace *w, cons
     a.m_edges = g->m;
     a.split = c.split;
     a.leaf_min = (int32_t)c.leaf_min;
+    a.xcd = ctx->xcd_order;
     if (ctx->samp_min > 0 && g->d_samp) {
         a.samp = g->d_samp;
         a.samp_min = (uint32_t)ctx->samp_min;
@@ -389,7 +402,7 @@ tm_status get_module(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, int tier
     std::string err;
     const tmo::Plan gp = tmo::generic_plan(m->plan.l);
     auto mod = ctx->compiler.get(use_generic(tier, m) ? gp : m->plan, g->key_bytes, ctx->block, &err,
-                                 ctx->min_waves, tmo::mode_group(mode), ctx->step_form);
+                                 ctx->min_waves, tmo::mode_group(mode), ctx->step_form | (ctx->xcd_order << 1));
     if (!mod) return fail(TM_E_COMPILE, err);
     *out = mod;
     return TM_OK;
@@ -405,12 +418,14 @@ tm_status run_single(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm
     const int64_t chunks = (r1 - r0 + rch - 1) / rch;
     HIP_TRY(ws_prepare(w, chunks, 1), "workspace");
     fill_qargs(g, m, r0, r1, 0, rch, 0, budget, cfg.split, cfg.split_min, (QArgs *)w->h_qa);
+    const int64_t xlen = xcd_prefix((QArgs *)w->h_qa, 1);
     HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload query");
     HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 2, stream), "reset count and step tally");
     *chunks_out = chunks;
     *r0_out = r0;
     if (chunks == 0) return TM_OK;
     GArgs a = base_args(ctx, g, w, cfg);
+    a.xlen = xlen;
     a.total_chunks = chunks;
     a.rch = (int32_t)rch;
     a.nq = 1;
@@ -444,7 +459,8 @@ int bitlen64(int64_t x) { return x > 0 ? 64 - __builtin_clzll((unsigned long lon
 
 std::string module_key(const tm_ctx *ctx, const tm_graph *g, const tmo::Plan &p) {
     return "S" + std::to_string(g->key_bytes) + "b" + std::to_string(ctx->block) +
-           (ctx->min_waves ? "w" + std::to_string(ctx->min_waves) : std::string()) + ":" + p.key();
+           (ctx->min_waves ? "w" + std::to_string(ctx->min_waves) : std::string()) +
+           (ctx->xcd_order ? "x" : "") + ":" + p.key();
 }
 
 std::string tune_key(const tm_graph *g, const std::string &mod, int64_t delta, int64_t roots, int q) {
@@ -737,6 +753,10 @@ tm_status tm_set_param(tm_ctx *ctx, int32_t param, int64_t v) {
         if (v != 0 && v != 1) return fail(TM_E_INVALID, "step form must be 0 or 1");
         ctx->step_form = (int)v;
         return TM_OK;
+    case TM_PARAM_XCD_ORDER:
+        if (v != 0 && v != 1) return fail(TM_E_INVALID, "XCD order must be 0 or 1");
+        ctx->xcd_order = (int)v;
+        return TM_OK;
     case TM_PARAM_LINE_SAMPLES:
         if (v != 0 && (v < 64 || v > (int64_t(1) << 30))) return fail(TM_E_INVALID, "line-sample threshold must be 0 or >= 64");
         ctx->samp_min = v;
@@ -765,6 +785,7 @@ tm_status tm_get_param(tm_ctx *ctx, int32_t param, int64_t *v) {
     case TM_PARAM_HUB_LDS: *v = ctx->hub_lds; return TM_OK;
     case TM_PARAM_STEP_FORM: *v = ctx->step_form; return TM_OK;
     case TM_PARAM_LINE_SAMPLES: *v = ctx->samp_min; return TM_OK;
+    case TM_PARAM_XCD_ORDER: *v = ctx->xcd_order; return TM_OK;
     default: return fail(TM_E_INVALID, "unknown parameter");
     }
 }
@@ -1226,7 +1247,7 @@ tm_status tm_compile_motif(tm_ctx *ctx, const tm_motif_desc *desc, tm_motif **ou
     // here; with the generic tier this is the shared module of the motif length
     const tmo::Plan gp = tmo::generic_plan(m->plan.l);
     if (!ctx->compiler.get(use_generic(ctx->tier, m) ? gp : m->plan, 4, ctx->block, &err, ctx->min_waves,
-                           tmo::mode_group(tmo::MODE_COUNT), ctx->step_form)) {
+                           tmo::mode_group(tmo::MODE_COUNT), ctx->step_form | (ctx->xcd_order << 1))) {
         delete m;
         return fail(TM_E_COMPILE, err);
     }
@@ -1468,6 +1489,7 @@ tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, cons
     HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload query");
     HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 2, stream), "reset count");
     GArgs a = base_args(ctx, g, w, cfg);
+    a.xlen = ((QArgs *)w->h_qa)->xns;
     a.total_chunks = chunks;
     a.rch = (int32_t)rch;
     a.nq = 1;
@@ -1503,12 +1525,12 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
     std::string err;
     std::shared_ptr<tmo::Module> mod;
     if (no_alloc) {
-        mod = ctx->compiler.find_batch(plans, g->key_bytes, ctx->block, ctx->min_waves, ctx->step_form);
+        mod = ctx->compiler.find_batch(plans, g->key_bytes, ctx->block, ctx->min_waves, ctx->step_form | (ctx->xcd_order << 1));
         if (!mod)
             return fail(TM_E_INVALID, "the batched kernel of these motifs is not loaded: run tm_count_batch with "
                                       "them once first");
     } else {
-        mod = ctx->compiler.get_batch(plans, g->key_bytes, ctx->block, &err, ctx->min_waves, ctx->step_form);
+        mod = ctx->compiler.get_batch(plans, g->key_bytes, ctx->block, &err, ctx->min_waves, ctx->step_form | (ctx->xcd_order << 1));
         if (!mod) return fail(TM_E_COMPILE, err);
         HIP_TRY(ws_prepare(w, 0, q), "workspace");
     }
@@ -1547,10 +1569,12 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
             any_split |= c.split;
             c0 += h[j].nchunks;
         }
+        const int64_t xlen = xcd_prefix(h, q);
         HIP_TRY(hipMemcpyAsync(w->qa, w->h_qa, q * sizeof(QArgs), hipMemcpyHostToDevice, stream), "upload queries");
         HIP_TRY(tmo::dev_fill_u64(w->counts, 0, 2 * (int64_t)q, stream), "reset counts and step tallies");
         if (c0 > 0) {
             GArgs a = base_args(ctx, g, w, c);
+            a.xlen = xlen;
             a.split = any_split;
             a.total_chunks = c0;
             a.rch = (int32_t)rch;
@@ -1580,7 +1604,8 @@ tm_status count_batch_impl(tm_ctx *ctx, const tm_graph *g, int32_t q, const tm_m
     std::string mkey;
     if (ctx->autotune) {
         mkey = "B" + std::to_string(g->key_bytes) + "b" + std::to_string(ctx->block) +
-               (ctx->min_waves ? "w" + std::to_string(ctx->min_waves) : std::string()) + ":";
+               (ctx->min_waves ? "w" + std::to_string(ctx->min_waves) : std::string()) +
+               (ctx->xcd_order ? "x" : "") + ":";
         for (auto *p : plans) mkey += p->key() + "|";
     }
     const std::string key = ctx->autotune ? tune_key(g, mkey, dmax, roots, q) : std::string();

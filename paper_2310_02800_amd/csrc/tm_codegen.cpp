@@ -229,6 +229,7 @@ struct QArgs {
   int elo[8], ehi[8];
   float pth[12];
   unsigned char pop[12], plev[12];
+  i64 xns, xs0;
 };
 
 // Query arguments are read-only during a launch and uniform per wavefront; in the
@@ -254,13 +255,35 @@ struct GArgs {
   const u32* hub; u32 hub_words; u32 hub_dmin;
   const tkey* samp; u32 samp_min; int samp_lg;
   const int* pr_samp;
+  int xcd; int pad_; i64 xlen;
 };
-static_assert(sizeof(QArgs) == 384, "QArgs layout");
-static_assert(sizeof(GArgs) == 296, "GArgs layout");
+static_assert(sizeof(QArgs) == 400, "QArgs layout");
+static_assert(sizeof(GArgs) == 312, "GArgs layout");
 // Hub-list samples staged by the workgroup (launches with hub_words > 0):
 // [0] H, [1, 1+H) list starts (ascending), [1+H, 2+2H) sample offsets,
 // [2+2H, 2+3H) log2 strides, time keys from word 2+3H rounded up to even.
 extern __shared__ u32 lds_hub[];
+// The next root chunk for this wavefront (lane 0 calls it), or total_chunks
+// when none is left; ctl[0] counts the chunks taken. In XCD order each
+// query's chunks are contiguous root ranges in time order, cut into 8 slices;
+// workgroup b takes from slice b mod 8 first (its XCD under round-robin
+// dispatch, so that XCD's L2 serves a narrow time range of the adjacency) and
+// moves to the next slice when its own runs dry.
+__device__ __forceinline__ i64 next_chunk_x(const GArgs& g) {
+  const int x = (int)(blockIdx.x & 7u);
+  for (int k = 0; k < 8; ++k) {
+    const int y = (x + k) & 7;
+    for (;;) {
+      const u64 pos = atomicAdd(&g.ctl[16 + y], 1ull);
+      if (pos >= (u64)g.xlen) break;
+      int lo = 0, hi = g.nq - 1;
+      while (lo < hi) { const int md = (lo + hi + 1) >> 1; if ((u64)g.qa[md].xs0 <= pos) lo = md; else hi = md - 1; }
+      const i64 loc = (i64)y * g.qa[lo].xns + ((i64)pos - g.qa[lo].xs0);
+      if (loc < g.qa[lo].nchunks) { atomicAdd(&g.ctl[0], 1ull); return g.qa[lo].c0 + loc; }
+    }
+  }
+  return g.total_chunks;
+}
 // A window over [lo, hi) of the unified adjacency: the line samples
 // (smp[j] = key at position j << lg) inside the range are searched first, which
 // leaves to the search over the list the positions between the last sample
@@ -345,6 +368,11 @@ __device__ __forceinline__ bool preds_at(qptr q, int lv, float w) {
 // a label in the inclusive range [lo, hi]
 __device__ __forceinline__ bool in_range(int x, int lo, int hi) { return x >= lo && x <= hi; }
 __device__ __forceinline__ u32 bitlen(u32 x) { return x ? 32u - (u32)__builtin_clz(x) : 0u; }
+// Roots in chunk L of a query of n roots cut into contiguous runs of rch.
+__device__ __forceinline__ i64 ch_roots_x(i64 L, i64 n, i64 rch) {
+  const i64 left = n - L * rch;
+  return left < rch ? left : rch;
+}
 // Counting a last-level window without scanning it. `pr` counts the reads.
 // Entries of [c, e) (sorted by time) with time <= t, galloping from c.
 __device__ __forceinline__ u32 win_len(const tkey* at, u32 c, u32 e, tkey t, u32& pr) {
@@ -508,7 +536,12 @@ struct Emitter {
     // then consumes them, so that a wavefront waits once per step; a binding
     // candidate leaves the next level's open to the following step (phase 4).
     bool F = false;
-    explicit Emitter(const Plan &pl, bool generic = false, bool fused = false) : p(pl), G(generic), F(fused) {}
+    // Root order: false, chunk L of a query holds roots L, L + C, L + 2C, ...;
+    // true (XCD order), chunks are contiguous root ranges taken per XCD from
+    // 8 time slices (next_chunk).
+    bool X = false;
+    explicit Emitter(const Plan &pl, bool generic = false, int form = 0)
+        : p(pl), G(generic), F((form & 1) != 0), X((form & 2) != 0) {}
 
     std::string I(int i) const { return std::to_string(i); }
 
@@ -1106,7 +1139,7 @@ struct Emitter {
         o << "        for (i64 t = lane; t < fit; t += 64) {\n";
         o << "          const i64 k = pend - fit + t;\n";
         o << "          u32* it = item_at(g, qi, (u64)(s0 + t));\n";
-        o << "          st_ag(it + 1, 0u); st_ag(it + 7, (u32)(q_r0 + (pchunk - q_c0) + k * q_nch)); st_ag64(it + 8, pchunk);\n";
+        o << "          st_ag(it + 1, 0u); st_ag(it + 7, (u32)(" << (X ? "q_r0 + (pchunk - q_c0) * q_rch + k" : "q_r0 + (pchunk - q_c0) + k * q_nch") << ")); st_ag64(it + 8, pchunk);\n";
         o << "          mem_order();\n";
         o << "          st_ag(it, g.epoch);\n";
         o << "        }\n";
@@ -1573,6 +1606,9 @@ struct Emitter {
         o << "  // chunk j of a query holds its roots j, j + nchunks, j + 2 nchunks, ...: a burst of\n";
         o << "  // consecutive heavy roots spreads over many wavefronts\n";
         o << "  const i64 q_nch = q->nchunks, q_n = q->r1 - q->r0, q_budget = q->budget;\n";
+        // root i of the query's chunk L: interleaved, q_r0 + L + i * nchunks; in
+        // XCD order, contiguous: q_r0 + L * q_rch + i
+        if (X) o << "  const i64 q_rch = q_nch > 0 ? (q_n + q_nch - 1) / q_nch : 0;\n";
         o << "  const bool q_split = g.split && q->split; const u32 q_smin = (u32)q->split_min;\n";
         for (int i = 0; i + 1 < L; i++) o << "  const i64 gap" << i << " = q->gap[" << i << "];\n";
         for (int j = 0; j < p.n_anti; j++) o << "  const i64 adl" << j << " = q->gap[" << anti_slot(j) << "];\n";
@@ -1632,7 +1668,8 @@ struct Emitter {
         o << "  i64 pnext = 0, pend = 0, pchunk = chunk, pending = -1;\n";
         o << "  bool drained = chunk < 0;\n";
         o << "  if (chunk >= 0) {\n";
-        o << "    pnext = 0; pend = (q_n - (chunk - q_c0) + q_nch - 1) / q_nch;\n";
+        if (X) o << "    pnext = 0; pend = ch_roots_x(chunk - q_c0, q_n, q_rch);\n";
+        else o << "    pnext = 0; pend = (q_n - (chunk - q_c0) + q_nch - 1) / q_nch;\n";
         o << "  } else {\n";
         o << "    // start from donated work items [ih, ih + in) of this query\n";
         o << "    lvl = -1;\n";
@@ -1652,20 +1689,23 @@ struct Emitter {
         o << "      const i64 rk = (i64)rank_in(need);\n";
         o << "      const i64 avail = pend - pnext;\n";
         o << "      i64 myr = -1, myc = pchunk;\n";
-        o << "      if (wantp && rk < avail) myr = q_r0 + (pchunk - q_c0) + (pnext + rk) * q_nch;\n";
+        if (X) o << "      if (wantp && rk < avail) myr = q_r0 + (pchunk - q_c0) * q_rch + pnext + rk;\n";
+        else o << "      if (wantp && rk < avail) myr = q_r0 + (pchunk - q_c0) + (pnext + rk) * q_nch;\n";
         o << "      if (avail >= nneed) { pnext += nneed; }\n";
         o << "      else {\n";
         o << "        pnext = pend;\n";
         o << "        if (!drained) {\n";
         o << "          i64 c = 0;\n";
-        o << "          if (lane == 0) c = (i64)atomicAdd(&g.ctl[0], 1ull);\n";
+        o << "          if (lane == 0) c = " << (X ? "next_chunk_x(g)" : "(i64)atomicAdd(&g.ctl[0], 1ull)") << ";\n";
         o << "          c = bcast64(c);\n";
-        o << "          if (c >= q_c1) { drained = true; pending = c < g.total_chunks ? c : -1; }\n";
+        o << "          if (" << (X ? "c < q_c0 || " : "") << "c >= q_c1) { drained = true; pending = c < g.total_chunks ? c : -1; }\n";
         o << "          else {\n";
         o << "            pchunk = c;\n";
-        o << "            pnext = 0; pend = (q_n - (c - q_c0) + q_nch - 1) / q_nch;\n";
+        if (X) o << "            pnext = 0; pend = ch_roots_x(c - q_c0, q_n, q_rch);\n";
+        else o << "            pnext = 0; pend = (q_n - (c - q_c0) + q_nch - 1) / q_nch;\n";
         o << "            const i64 k2 = rk - avail;\n";
-        o << "            if (wantp && myr < 0 && k2 < pend) { myr = q_r0 + (c - q_c0) + k2 * q_nch; myc = c; }\n";
+        if (X) o << "            if (wantp && myr < 0 && k2 < pend) { myr = q_r0 + (c - q_c0) * q_rch + k2; myc = c; }\n";
+        else o << "            if (wantp && myr < 0 && k2 < pend) { myr = q_r0 + (c - q_c0) + k2 * q_nch; myc = c; }\n";
         o << "            const i64 take = nneed - avail < pend - pnext ? nneed - avail : pend - pnext;\n";
         o << "            pnext += take;\n";
         o << "          }\n";
@@ -1723,7 +1763,8 @@ struct Emitter {
         o << "      if (used > q_budget) {\n";
         o << "        if (!drained) {\n";
         o << "          i64 c = 0;\n";
-        o << "          do { if (lane == 0) c = (i64)atomicAdd(&g.ctl[0], 1ull); c = bcast64(c); } while (c < q_c1);\n";
+        if (X) o << "          do { if (lane == 0) c = next_chunk_x(g); c = bcast64(c); } while (c >= q_c0 && c < q_c1);\n";
+        else o << "          do { if (lane == 0) c = (i64)atomicAdd(&g.ctl[0], 1ull); c = bcast64(c); } while (c < q_c1);\n";
         o << "          drained = true; pending = c < g.total_chunks ? c : -1;\n";
         o << "        }\n";
         o << "        break;\n";
@@ -1870,7 +1911,7 @@ const char *const kBatchName = "tm_count_batch";
 
 // `modes`: bit set of the single-query kernels to emit (bit i = mode i), or
 // 0 for the batched module's one counting kernel.
-void emit_kernels(std::ostringstream &o, int nfn, int block, unsigned modes, int min_waves, bool outlined) {
+void emit_kernels(std::ostringstream &o, int nfn, int block, unsigned modes, int min_waves, bool outlined, int form) {
     const bool batch = modes == 0;
     const char *const *names = batch ? &kBatchName : kSingleNames;
     const int nmodes = batch ? 1 : 4;
@@ -1896,7 +1937,7 @@ void emit_kernels(std::ostringstream &o, int nfn, int block, unsigned modes, int
         o << "  }\n";
         if (outlined) o << "  const u64 ga = (u64)__builtin_amdgcn_kernarg_segment_ptr();\n";
         o << "  i64 c = 0;\n";
-        o << "  if (lane == 0) { atomicAdd(&g.ctl[8], 1ull); c = (i64)atomicAdd(&g.ctl[0], 1ull); }\n";
+        o << "  if (lane == 0) { atomicAdd(&g.ctl[8], 1ull); c = " << ((form & 2) ? "next_chunk_x(g)" : "(i64)atomicAdd(&g.ctl[0], 1ull)") << "; }\n";
         o << "  c = bcast64(c);\n";
         o << "  bool busy = true, hung = false;\n";
         o << "  u32 polls = 0u, nap = 1u;\n";
@@ -1975,10 +2016,10 @@ static std::string header(int key_bytes) {
 }
 
 std::string generate_source(const Plan &p, int key_bytes, int block, int min_waves, unsigned modes, int form) {
-    Emitter e(p, p.generic, form != 0);
+    Emitter e(p, p.generic, form);
     e.o << header(key_bytes);
     e.matcher(0);
-    emit_kernels(e.o, 1, block, modes & kAllModes, min_waves, false);
+    emit_kernels(e.o, 1, block, modes & kAllModes, min_waves, false, form);
     return e.o.str();
 }
 
@@ -1990,11 +2031,11 @@ std::string generate_batch_source(const std::vector<const Plan *> &plans, int ke
     for (auto *pl : plans) n_generic += pl->generic ? 1 : 0;
     const bool outlined = (int)plans.size() > kMaxInlinedMatchers || n_generic > 1;
     for (size_t f = 0; f < plans.size(); f++) {
-        Emitter e(*plans[f], plans[f]->generic, form != 0);
+        Emitter e(*plans[f], plans[f]->generic, form);
         e.matcher((int)f, outlined);
         all << e.o.str();
     }
-    emit_kernels(all, (int)plans.size(), block, 0u, min_waves, outlined);
+    emit_kernels(all, (int)plans.size(), block, 0u, min_waves, outlined, form);
     return all.str();
 }
 

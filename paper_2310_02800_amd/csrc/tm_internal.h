@@ -45,8 +45,11 @@ struct QArgs {
     int32_t elo[8], ehi[8];
     float pth[12];
     uint8_t pop[12], plev[12];
+    // XCD order (GArgs.xcd): this query's chunks cut into 8 slices of xns
+    // chunks; xs0 = the slices' start in every XCD's chunk sequence
+    int64_t xns, xs0;
 };
-static_assert(sizeof(QArgs) == 384, "QArgs layout");
+static_assert(sizeof(QArgs) == 400, "QArgs layout");
 
 struct GArgs {
     const int32_t *src;
@@ -91,8 +94,11 @@ struct GArgs {
     uint32_t samp_min;        // windows over at least this many entries search the samples first (0: never)
     int32_t samp_lg;
     const int32_t *pr_samp;   // line samples of pr_nbr: pr_samp[j] = pr_nbr[32 j], or null
+    int32_t xcd;              // 1: chunks are contiguous root ranges, taken per XCD from 8 time slices
+    int32_t pad_;
+    int64_t xlen;             // chunks in one XCD's sequence (sum of the queries' xns)
 };
-static_assert(sizeof(GArgs) == 296, "GArgs layout");
+static_assert(sizeof(GArgs) == 312, "GArgs layout");
 
 // Hub-list staging (LDS): the longest adjacency lists each get up to
 // kHubSamplesPerList time keys sampled at a power-of-two stride (at least 32,
@@ -105,7 +111,7 @@ constexpr uint32_t kLdsPerCu = 160u * 1024u;  // gfx950
 // ctl words: [10..12] work counters of the windows counted without a scan,
 // [13] donated items waiting in all queues
 enum { CTL_CURSOR = 0, CTL_OVERFLOW = 1, CTL_STATS = 2, CTL_ERROR = 7, CTL_BUSY = 8, CTL_HUNGRY = 9,
-       CTL_LEAF = 10, CTL_AVAIL = 13, CTL_HANDED = 14, CTL_WORDS = 16 };
+       CTL_LEAF = 10, CTL_AVAIL = 13, CTL_HANDED = 14, CTL_XCD = 16, CTL_WORDS = 24 };
 constexpr uint32_t kItemWords = 32;
 constexpr uint64_t kItemsTotal = uint64_t(1) << 20;  // donated work items per launch (128 MiB)
 constexpr int kTraceCols = 8;            // t_ns, cursor, chunks, busy, waiting, items, done, handed
@@ -348,6 +354,7 @@ struct tm_ctx {
     int hub_lds = 0;          // stage the hub lists' sampled keys in LDS (TM_PARAM_HUB_LDS)
     int64_t samp_min = 64;    // windows this long search the line samples first (TM_PARAM_LINE_SAMPLES, 0 = off)
     int step_form = tmo::kDefaultStepForm;  // matcher loop step form (TM_PARAM_STEP_FORM)
+    int xcd_order = 0;        // root chunks in XCD time slices (TM_PARAM_XCD_ORDER)
     std::vector<int64_t> trace;  // samples of the last sampled launch, kTraceCols each
     void *scratch = nullptr;     // this device's no-allocation scratch (tm_count_batch_noalloc)
 };
