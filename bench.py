@@ -374,9 +374,12 @@ def bench_serve(ctx, dg, g, args):
     range covering 1-100% of the span, 10% enumerations), first one query at a
     time (plain), then through the continuous-batching server with Poisson
     arrivals at 0.7x the plain capacity, and once more with every query
-    submitted at once (served capacity). Both forms use the table-driven
-    kernels and the same per-query work budget; a query over it in either pass
-    is then run alone with its specialised kernel and a larger budget."""
+    submitted at once (served capacity). The plain form uses the table-driven
+    kernels; the server (tier 2 by default) runs count queries table-driven in
+    batches up to a probe budget and moves those over it to their specialised
+    kernels, compiled on its compile thread while it serves. Both use the same
+    per-query work budget; a query over it in either pass is then run alone
+    with its specialised kernel and a larger budget."""
     import numpy as np
     import torch
     from paper_2310_02800_amd import _native as N
@@ -439,7 +442,8 @@ def bench_serve(ctx, dg, g, args):
 
         def serve(arr_s, nq):
             srv = api.Server(ctx, dg, stream_slots=args.serve_slots, max_batch=args.serve_batch,
-                             enum_pool_bytes=pool_bytes, tier=1, work_budget=budget)
+                             enum_pool_bytes=pool_bytes, tier=args.serve_tier, work_budget=budget,
+                             probe_budget=args.serve_probe_budget if args.serve_tier == 2 else 0)
             res = {}
             sched = {}
             try:
@@ -539,6 +543,10 @@ def bench_serve(ctx, dg, g, args):
                           "status": "ok" if st == N.TM_OK else "cancelled" if st == N.TM_E_CANCELLED else st,
                           "count": c, "s": time.perf_counter() - t0})
             log(f"serve: query {i} alone: {alone[-1]['status']} in {alone[-1]['s']:.1f} s")
+        def moved(rr):  # tier 2: queries over the probe budget, and those of them run specialised
+            return {"probed": sum(1 for r, _ in rr.values() if r["probed"]),
+                    "specialised": sum(1 for r, _ in rr.values() if r["probed"] and r["kernel_tier"] == 0)}
+
         ok = [i for i in range(n_rate) if res[i][0]["status"] == N.TM_OK]
         inst = sum(res[i][0]["count"] for i in ok)
         ok_f = [i for i in range(n) if res_f[i][0]["status"] == N.TM_OK]
@@ -566,7 +574,9 @@ def bench_serve(ctx, dg, g, args):
                        "instances_per_s_at_rate": inst / span_s,
                        "latency_ms": {"p50": pct(lat_served, 50), "p99": pct(lat_served, 99)},
                        "capacity_qps": n / span_f, "instances_per_s_at_capacity": inst_f / span_f,
-                       "slots": args.serve_slots, "max_batch": args.serve_batch},
+                       "slots": args.serve_slots, "max_batch": args.serve_batch, "tier": args.serve_tier,
+                       "probe_budget_steps": args.serve_probe_budget if args.serve_tier == 2 else None,
+                       "moved_at_rate": moved(res), "moved_at_capacity": moved(res_f)},
             "capacity_vs_plain": (n / span_f) / cap_plain,
             "results_compared": both, "agree": agree, "oracle_checked": oracle_checked,
         }
@@ -619,6 +629,11 @@ def main():
                          "as plain counts and print its JSON (for kernel traces and counters of one query)")
     ap.add_argument("--serve-budget", type=int, default=1 << 31,
                     help="work budget per query in the stream (wavefront loop steps, 0 = none)")
+    ap.add_argument("--serve-tier", type=int, default=2, choices=(0, 1, 2),
+                    help="server kernel tier (2: table-driven batches, specialised kernels for queries over the "
+                         "probe budget)")
+    ap.add_argument("--serve-probe-budget", type=int, default=1 << 24,
+                    help="tier 2: steps a count query may take in a table-driven batch")
     ap.add_argument("--serve-alone-budget", type=int, default=1 << 35,
                     help="work budget of an over-budget query run alone afterwards (steps, 0 = none)")
     ap.add_argument("--serve-slots", type=int, default=4)

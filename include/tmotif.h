@@ -528,6 +528,17 @@ tm_status tm_count_batch_noalloc(tm_ctx *ctx, const tm_graph *g, int32_t q, cons
  * compilation when tier = 1 (see TM_PARAM_TIER), except once per structure of
  * a motif with anti-edges: under tier 1 such a count query is launched on its
  * own, with its specialised matcher.
+ * tier = 2 (specialise heavy queries; the paper compiles a kernel per query,
+ * Sec. 4.2, which a stream of thousands of structures cannot wait for): count
+ * queries run first in table-driven batches, each capped at probe_budget
+ * steps. A query that exceeds the cap leaves its batch (the partial work is
+ * dropped) and its structure's specialised counting kernel is compiled on the
+ * server's compile thread while the slots go on serving; the query then runs
+ * on its own with that kernel and its full budget. A slot that would be idle
+ * takes a query still waiting for a compile that has not started and runs it
+ * with the table-driven kernel instead. Compiled kernels stay loaded, so a
+ * later heavy query of the same structure starts at once. Enumerations run
+ * table-driven, as under tier 1.
  * Timestamps are host monotonic-clock nanoseconds (CLOCK_MONOTONIC). */
 typedef struct tm_server tm_server;
 
@@ -536,11 +547,13 @@ typedef struct {
     int32_t max_batch;        /* count queries per batched launch (1..4096) */
     int64_t enum_pool_bytes;  /* device memory for enumeration rows (>= 0) */
     int32_t queue_capacity;   /* pending queries before TM_E_BUSY (>= 1) */
-    int32_t tier;             /* kernel tier, as TM_PARAM_TIER */
+    int32_t tier;             /* kernel tier, as TM_PARAM_TIER, or 2 (see above) */
     int64_t work_budget;      /* default work budget of a query, as TM_PARAM_WORK_BUDGET (0 = none) */
     const char *tune_path;    /* NULL, or a tune table (tm_tune_save) merged at start if the
                                  file exists and written back at stop; launches are tuned
                                  when the context has TM_PARAM_AUTOTUNE = 1 */
+    int64_t probe_budget;     /* tier 2: steps a count query may take in a table-driven
+                                 batch (>= 1); ignored by tiers 0 and 1 */
 } tm_server_cfg;
 
 typedef struct {
@@ -562,6 +575,9 @@ typedef struct {
     uint64_t n_rows;
     int64_t t_arrival_ns, t_admit_ns, t_launch_ns, t_done_ns;
     char error[128];          /* for a status other than TM_OK: what failed (NUL-terminated) */
+    int32_t kernel_tier;      /* the kernels of the final run: 0 specialised, 1 table-driven */
+    int32_t probed;           /* tier 2: 1 if the query exceeded probe_budget in a batch and was
+                                 run again on its own (t_launch_ns is that run's) */
 } tm_result;
 
 /* Start serving graph g of ctx. The graph and the context must outlive the

@@ -59,7 +59,7 @@ class RootRange(ctypes.Structure):
 class ServerCfg(ctypes.Structure):
     _fields_ = [("stream_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("enum_pool_bytes", ctypes.c_int64),
                 ("queue_capacity", ctypes.c_int32), ("tier", ctypes.c_int32), ("work_budget", ctypes.c_int64),
-                ("tune_path", ctypes.c_char_p)]
+                ("tune_path", ctypes.c_char_p), ("probe_budget", ctypes.c_int64)]
 
 
 class Query(ctypes.Structure):
@@ -71,7 +71,8 @@ class Result(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
                 ("n_edges", ctypes.c_int32), ("count", ctypes.c_uint64), ("rows", ctypes.c_void_p),
                 ("n_rows", ctypes.c_uint64), ("t_arrival_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
-                ("t_launch_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64), ("error", ctypes.c_char * 128)]
+                ("t_launch_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64), ("error", ctypes.c_char * 128),
+                ("kernel_tier", ctypes.c_int32), ("probed", ctypes.c_int32)]
 
 
 class GraphInfo(ctypes.Structure):

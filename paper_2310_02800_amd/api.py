@@ -414,10 +414,10 @@ class Server:
     """Continuous-batching query server over one resident graph (tm_server_*)."""
 
     def __init__(self, ctx: Context, g: Graph, stream_slots=2, max_batch=64, enum_pool_bytes=1 << 30,
-                 queue_capacity=1 << 16, tier=1, tune_path=None, work_budget=0):
+                 queue_capacity=1 << 16, tier=1, tune_path=None, work_budget=0, probe_budget=0):
         self._tune_path = None if tune_path is None else os.fsencode(tune_path)  # kept alive for the call
         cfg = N.ServerCfg(int(stream_slots), int(max_batch), int(enum_pool_bytes), int(queue_capacity), int(tier),
-                          int(work_budget), self._tune_path)
+                          int(work_budget), self._tune_path, int(probe_budget))
         h = ctypes.c_void_p()
         N.check(N.lib().tm_server_start(ctx._h, g.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -449,7 +449,8 @@ class Server:
                         "rows": r.rows, "n_rows": r.n_rows, "n_edges": r.n_edges,
                         "t_arrival_ns": r.t_arrival_ns, "t_admit_ns": r.t_admit_ns,
                         "t_launch_ns": r.t_launch_ns, "t_done_ns": r.t_done_ns,
-                        "error": r.error.decode(errors="replace")})
+                        "error": r.error.decode(errors="replace"), "kernel_tier": r.kernel_tier,
+                        "probed": bool(r.probed)})
         return out
 
     def rows(self, result):

@@ -1351,43 +1351,8 @@ tm_status tm_count(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_r
     tm_status st = check_pair(ctx, g, m);
     if (st != TM_OK) return st;
     if (!count_out) return fail(TM_E_INVALID, "count_out is null");
-    DeviceGuard dg(ctx->device);
-    std::shared_ptr<tmo::Module> mod;
-    if ((st = get_module(ctx, g, m, ctx->tier, tmo::MODE_COUNT, &mod)) != TM_OK) return st;
     WsLease lease(ctx);
-    tm_ctx::Workspace *w = lease.w;
-    int64_t r0, r1, chunks = 0;
-    root_ids(g, range, &r0, &r1);
-    const int64_t budget = ctx->work_budget;
-    auto once = [&](const tmo::LaunchCfg &c, double *ms, std::vector<uint64_t> *res) -> tm_status {
-        int64_t rr0 = 0;
-        tm_status s =
-            run_single(ctx, g, m, range, stream, tmo::MODE_COUNT, w, mod.get(), c, budget, &chunks, &rr0, ms);
-        if (s != TM_OK) return s;
-        HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
-                "read count");
-        HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
-                "read control words");
-        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
-        if (chunks && w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
-        res->assign(1, budget > 0 && (int64_t)w->h_counts[1] > budget ? kCancelled : w->h_counts[0]);
-        return TM_OK;
-    };
-    const tmo::Plan gp = tmo::generic_plan(m->plan.l);
-    const std::string key = ctx->autotune ? tune_key(g, module_key(ctx, g, use_generic(ctx->tier, m) ? gp : m->plan),
-                                                     m->delta,
-                                                     r1 - r0, 1)
-                                          : std::string();
-    std::vector<uint64_t> res;
-    tmo::LaunchCfg used;
-    bool tuned = false;
-    double ms = 0;
-    st = run_tuned(ctx, key, r1 - r0, once, &res, &used, &tuned, &ms);
-    if (st != TM_OK) return st;
-    note_launch(ctx, used, tuned, ms, chunks ? 1 : 0);
-    if (res[0] == kCancelled) return fail(TM_E_CANCELLED, "work budget exceeded");
-    *count_out = res[0];
-    return TM_OK;
+    return tmo::count_impl(ctx, g, m, range, ctx->tier, ctx->work_budget, stream, lease.w, count_out);
 }
 
 tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range,
@@ -1420,6 +1385,52 @@ tm_status tm_work_stats(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const
 }  // extern "C"
 
 namespace tmo {
+
+tm_status count_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range, int tier,
+                     int64_t budget, hipStream_t stream, tm_ctx::Workspace *w, uint64_t *count_out) {
+    DeviceGuard dg(ctx->device);
+    std::shared_ptr<tmo::Module> mod;
+    tm_status st;
+    if ((st = get_module(ctx, g, m, tier, tmo::MODE_COUNT, &mod)) != TM_OK) return st;
+    int64_t r0, r1, chunks = 0;
+    root_ids(g, range, &r0, &r1);
+    auto once = [&](const tmo::LaunchCfg &c, double *ms, std::vector<uint64_t> *res) -> tm_status {
+        int64_t rr0 = 0;
+        tm_status s =
+            run_single(ctx, g, m, range, stream, tmo::MODE_COUNT, w, mod.get(), c, budget, &chunks, &rr0, ms);
+        if (s != TM_OK) return s;
+        HIP_TRY(hipMemcpyAsync(w->h_counts, w->counts, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+                "read count");
+        HIP_TRY(hipMemcpyAsync(w->h_ctl, w->ctl, tmo::CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+                "read control words");
+        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        if (chunks && w->h_ctl[tmo::CTL_ERROR]) return fail(TM_E_DEVICE, "work item handoff timed out");
+        res->assign(1, budget > 0 && (int64_t)w->h_counts[1] > budget ? kCancelled : w->h_counts[0]);
+        return TM_OK;
+    };
+    const tmo::Plan gp = tmo::generic_plan(m->plan.l);
+    const std::string key = ctx->autotune ? tune_key(g, module_key(ctx, g, use_generic(tier, m) ? gp : m->plan),
+                                                     m->delta,
+                                                     r1 - r0, 1)
+                                          : std::string();
+    std::vector<uint64_t> res;
+    tmo::LaunchCfg used;
+    bool tuned = false;
+    double ms = 0;
+    st = run_tuned(ctx, key, r1 - r0, once, &res, &used, &tuned, &ms);
+    if (st != TM_OK) return st;
+    note_launch(ctx, used, tuned, ms, chunks ? 1 : 0);
+    if (res[0] == kCancelled) return fail(TM_E_CANCELLED, "work budget exceeded");
+    *count_out = res[0];
+    return TM_OK;
+}
+
+
+tm_status load_count_module(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, int tier) {
+    DeviceGuard dg(ctx->device);
+    std::shared_ptr<tmo::Module> mod;
+    return get_module(ctx, g, m, tier, tmo::MODE_COUNT, &mod);
+}
 
 tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range, int tier,
                          int64_t budget, hipStream_t stream, tm_ctx::Workspace *w, const RowAlloc &alloc,

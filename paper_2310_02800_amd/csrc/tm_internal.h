@@ -416,6 +416,13 @@ using RowAlloc = std::function<int64_t *(uint64_t rows, uint64_t *capacity, tm_s
 tm_status enumerate_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range, int tier,
                          int64_t budget, hipStream_t stream, tm_ctx::Workspace *w, const RowAlloc &alloc,
                          uint64_t *n_out, int64_t **rows_out);
+// One query counted on its own (its module compiled first if not loaded),
+// with the context's launch settings or its tuned ones.
+tm_status count_impl(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, const tm_root_range *range, int tier,
+                     int64_t budget, hipStream_t stream, tm_ctx::Workspace *w, uint64_t *count_out);
+// The single-query counting module of this motif under `tier`, compiled if it
+// is not loaded (TM_E_COMPILE on failure).
+tm_status load_count_module(tm_ctx *ctx, const tm_graph *g, const tm_motif *m, int tier);
 // no_alloc: the workspace is a view of the device scratch; the batched module
 // must already be loaded (TM_E_INVALID otherwise) and the launch uses the
 // key's tuned setting or the defaults, untimed, with no tuning trials.

@@ -16,6 +16,12 @@
 // * Results (count, rows, status, and arrival / admit / launch / done
 //   timestamps on the host's monotonic clock) are collected by tm_poll;
 //   enumeration rows stay in the pool until tm_release.
+// * Tier 2: count queries run table-driven in batches under a probe budget; a
+//   query over it is moved to a per-structure wait list, one compile thread
+//   builds that structure's specialised counting kernel, and the query then
+//   runs on its own with it (the ready list, which slots serve first). A slot
+//   with nothing else to do runs a waiting query whose compile has not
+//   started with the table-driven kernel instead.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -44,6 +50,10 @@ struct Pending {
     bool enumerate = false;
     int64_t budget = 0;  // wavefront loop steps (0 = no limit)
     int64_t t_arrival = 0, t_admit = 0;
+    int kernel_tier = 1;
+    bool capped = false;   // its batch ran it under the probe budget
+    bool probed = false;   // it exceeded the probe budget and runs again alone
+    bool spec_ok = false;  // its specialised kernel is loaded
 };
 
 }  // namespace
@@ -66,6 +76,15 @@ struct tm_server {
     std::map<uint64_t, uint64_t> free_ranges;               // offset -> size
     std::map<uint64_t, std::pair<uint64_t, uint64_t>> held;  // ticket -> (offset, size)
     uint64_t served = 0, batches = 0;
+    // tier 2 (all under mu)
+    std::deque<Pending *> ready;                            // heavy queries ready to run alone
+    std::map<std::string, std::vector<Pending *>> waiting;  // heavy queries by structure, awaiting its compile
+    std::deque<std::pair<std::string, tm_motif>> compile_q; // structures to compile, oldest first
+    std::map<std::string, bool> compiled;                   // structure -> its compile succeeded
+    std::string compiling;                                  // the structure being compiled, if any
+    std::thread compiler;
+    bool compile_stop = false;
+    std::condition_variable cv_compile;
 };
 
 namespace {
@@ -135,6 +154,8 @@ void publish(tm_server *s, const Pending &p, tm_status st, uint64_t count, int64
     r.t_admit_ns = p.t_admit;
     r.t_launch_ns = t_launch;
     r.t_done_ns = now_ns();
+    r.kernel_tier = p.kernel_tier;
+    r.probed = p.probed ? 1 : 0;
     if (st != TM_OK) std::snprintf(r.error, sizeof(r.error), "%s", why ? why : tm_last_error());
     std::lock_guard<std::mutex> lk(s->mu);
     s->results.push_back(r);
@@ -148,6 +169,72 @@ void publish(tm_server *s, const Pending &p, tm_status st, uint64_t count, int64
 // every batch it joins a module of its own).
 bool alone(const tm_server *s, const Pending *p) { return p->enumerate || (s->cfg.tier && p->motif.plan.n_anti > 0); }
 
+// Tier 2, under mu: a waiting query whose structure is not being compiled
+// (taken out of the wait list when `take`).
+Pending *stealable(tm_server *s, bool take) {
+    for (auto it = s->waiting.begin(); it != s->waiting.end(); ++it) {
+        if (it->first == s->compiling || it->second.empty()) continue;
+        Pending *p = it->second.front();
+        if (take) {
+            it->second.erase(it->second.begin());
+            if (it->second.empty()) s->waiting.erase(it);
+        }
+        return p;
+    }
+    return nullptr;
+}
+
+// Tier 2: a query that exceeded the probe budget waits for its structure's
+// specialised kernel (queued for compilation once), or is ready at once when
+// that compile already ran.
+void to_heavy(tm_server *s, Pending *p) {
+    p->probed = true;
+    const std::string key = p->motif.plan.key();
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto c = s->compiled.find(key);
+    if (c != s->compiled.end()) {
+        p->spec_ok = c->second;
+        s->ready.push_back(p);
+    } else {
+        auto &v = s->waiting[key];
+        bool queued = key == s->compiling;
+        for (auto &q : s->compile_q) queued = queued || q.first == key;
+        if (!queued) {
+            s->compile_q.emplace_back(key, p->motif);
+            s->cv_compile.notify_one();
+        }
+        v.push_back(p);
+    }
+    s->cv_pending.notify_all();
+}
+
+void compile_main(tm_server *s) {
+    for (;;) {
+        std::pair<std::string, tm_motif> job;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_compile.wait(lk, [&] { return s->compile_stop || !s->compile_q.empty(); });
+            if (s->compile_stop) break;
+            job = s->compile_q.front();
+            s->compile_q.pop_front();
+            s->compiling = job.first;
+        }
+        const bool ok = tmo::load_count_module(s->ctx, s->g, &job.second, 0) == TM_OK;
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->compiling.clear();
+        s->compiled[job.first] = ok;
+        auto it = s->waiting.find(job.first);
+        if (it != s->waiting.end()) {
+            for (Pending *p : it->second) {
+                p->spec_ok = ok;
+                s->ready.push_back(p);
+            }
+            s->waiting.erase(it);
+        }
+        s->cv_pending.notify_all();
+    }
+}
+
 void slot_main(tm_server *s) {
     tm_ctx *ctx = s->ctx;
     hipSetDevice(ctx->device);
@@ -160,13 +247,26 @@ void slot_main(tm_server *s) {
     std::vector<uint64_t> counts;
     std::vector<int64_t> budgets;
     std::vector<uint8_t> cancelled;
+    const int base_tier = s->cfg.tier == 2 ? 1 : s->cfg.tier;
     for (;;) {
         batch.clear();
+        bool heavy = false;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_pending.wait(lk, [&] { return s->stopping || !s->pending.empty(); });
-            if (s->pending.empty()) break;  // stopping and drained
-            if (alone(s, s->pending.front())) {
+            s->cv_pending.wait(lk, [&] {
+                return !s->pending.empty() || !s->ready.empty() || stealable(s, false) ||
+                       (s->stopping && s->waiting.empty());
+            });
+            if (!s->ready.empty()) {
+                batch.push_back(s->ready.front());
+                s->ready.pop_front();
+                heavy = true;
+            } else if (s->pending.empty()) {
+                Pending *p = stealable(s, true);
+                if (!p) break;  // stopping and drained
+                batch.push_back(p);
+                heavy = true;
+            } else if (alone(s, s->pending.front())) {
                 batch.push_back(s->pending.front());
                 s->pending.pop_front();
             } else {
@@ -177,6 +277,18 @@ void slot_main(tm_server *s) {
                 }
             }
             s->batches++;
+        }
+        if (heavy) {
+            // alone, with the specialised kernel when it compiled, else table-driven
+            Pending *p = batch[0];
+            p->kernel_tier = p->spec_ok ? 0 : 1;
+            uint64_t c = 0;
+            const int64_t t_launch = now_ns();
+            const tm_status st = tmo::count_impl(ctx, s->g, &p->motif, p->has_range ? &p->range : nullptr,
+                                                 p->kernel_tier, p->budget, stream, w, &c);
+            publish(s, *p, st, st == TM_OK ? c : 0, nullptr, 0, t_launch);
+            delete p;
+            continue;
         }
         const int64_t t_admit = now_ns();
         for (Pending *p : batch) p->t_admit = t_admit;
@@ -191,8 +303,9 @@ void slot_main(tm_server *s) {
             uint64_t n = 0;
             int64_t *rows = nullptr;
             const int64_t t_launch = now_ns();
+            p->kernel_tier = base_tier;
             tm_status st = tmo::enumerate_impl(ctx, s->g, &p->motif, p->has_range ? &p->range : nullptr,
-                                               s->cfg.tier, p->budget, stream, w, alloc, &n, &rows);
+                                               base_tier, p->budget, stream, w, alloc, &n, &rows);
             if (st == TM_OK && n > 0 && !rows) st = TM_E_CAPACITY;
             if (st != TM_OK) {
                 std::lock_guard<std::mutex> lk(s->mu);
@@ -206,20 +319,28 @@ void slot_main(tm_server *s) {
             motifs.clear();
             ranges.clear();
             budgets.clear();
+            const int tier = batch[0]->motif.plan.n_anti > 0 ? 0 : base_tier;
+            // tier 2: a table-driven batch caps each query at the probe budget
+            const bool probe = s->cfg.tier == 2 && tier == 1;
             for (Pending *p : batch) {
                 motifs.push_back(&p->motif);
                 tm_root_range r = p->range;
                 if (!p->has_range) r = {INT64_MIN, INT64_MAX};
                 ranges.push_back(r);
-                budgets.push_back(p->budget);
+                p->capped = probe && (p->budget == 0 || p->budget > s->cfg.probe_budget);
+                p->kernel_tier = tier;
+                budgets.push_back(p->capped ? s->cfg.probe_budget : p->budget);
             }
             counts.assign(batch.size(), 0);
             cancelled.assign(batch.size(), 0);
             const int64_t t_launch = now_ns();
-            const int tier = batch[0]->motif.plan.n_anti > 0 ? 0 : s->cfg.tier;
             tm_status st = tmo::count_batch_impl(ctx, s->g, (int)batch.size(), motifs.data(), ranges.data(),
                                                  budgets.data(), tier, stream, w, counts.data(), cancelled.data());
             for (size_t i = 0; i < batch.size(); i++) {
+                if (st == TM_OK && cancelled[i] && batch[i]->capped) {
+                    to_heavy(s, batch[i]);
+                    continue;
+                }
                 const tm_status qs = st != TM_OK ? st : cancelled[i] ? TM_E_CANCELLED : TM_OK;
                 publish(s, *batch[i], qs, qs == TM_OK ? counts[i] : 0, nullptr, 0, t_launch,
                         st == TM_OK && cancelled[i] ? "work budget exceeded" : nullptr);
@@ -240,8 +361,8 @@ tm_status tm_server_start(tm_ctx *ctx, const tm_graph *g, const tm_server_cfg *c
     *out = nullptr;
     if (g->ctx != ctx) return tmo::set_error(TM_E_INVALID, "graph belongs to another context");
     if (cfg->stream_slots < 1 || cfg->stream_slots > 64 || cfg->max_batch < 1 || cfg->max_batch > 4096 ||
-        cfg->queue_capacity < 1 || cfg->enum_pool_bytes < 0 || (cfg->tier != 0 && cfg->tier != 1) ||
-        cfg->work_budget < 0)
+        cfg->queue_capacity < 1 || cfg->enum_pool_bytes < 0 || cfg->tier < 0 || cfg->tier > 2 ||
+        cfg->work_budget < 0 || (cfg->tier == 2 && cfg->probe_budget < 1))
         return tmo::set_error(TM_E_INVALID, "server configuration out of range");
     tm_server *s = new (std::nothrow) tm_server();
     if (!s) return tmo::set_error(TM_E_OOM, "host allocation");
@@ -269,6 +390,7 @@ tm_status tm_server_start(tm_ctx *ctx, const tm_graph *g, const tm_server_cfg *c
         }
         s->free_ranges[0] = s->pool_bytes;
     }
+    if (cfg->tier == 2) s->compiler = std::thread(compile_main, s);
     for (int i = 0; i < cfg->stream_slots; i++) s->slots.emplace_back(slot_main, s);
     *out = s;
     return TM_OK;
@@ -359,6 +481,14 @@ tm_status tm_server_stop(tm_server *s) {
         s->cv_pool.notify_all();
     }
     for (auto &t : s->slots) t.join();
+    if (s->compiler.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->compile_stop = true;
+            s->cv_compile.notify_all();
+        }
+        s->compiler.join();
+    }
     hipSetDevice(s->ctx->device);
     if (s->pool) hipFree(s->pool);
     const tm_status st = s->tune_path.empty() ? TM_OK : tm_tune_save(s->ctx, s->tune_path.c_str());

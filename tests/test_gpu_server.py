@@ -163,3 +163,59 @@ def test_submit_rejects_bad_queries(ctx, tiny_g):
         assert ei.value.status == N.TM_E_INVALID
     finally:
         srv.stop()
+
+
+def test_tier2_specialises_heavy_queries(ctx):
+    """Tier 2 with a probe budget of one step: count queries that do any real
+    work leave their table-driven batch and run again on their own, with
+    their structure's specialised kernel once it compiled (or table-driven,
+    taken by an idle slot first). Every result equals the oracle's; the
+    enumerations and the anti-edge query are served as under tier 1."""
+    g = synth.random_graph(np.random.Generator(np.random.PCG64(77)), 3000, 400_000, 2_000_000)
+    dg = ctx.load_synth(g)
+    og = oracle.OracleGraph.from_graph(g)
+    rng = np.random.Generator(np.random.PCG64(9))
+    base = [([(0, 1), (1, 2), (2, 0)], 60_000, None), (synth.FOUR_CYCLE, 120_000, None),
+            (synth.OUT_STAR3, 60_000, None), ([(0, 1), (1, 2), (2, 3)], 90_000, [30_000, 30_000])]
+    qs = []
+    for i in range(24):
+        e, d, gap = base[i % 4]
+        m = synth.Motif(list(e), int(d * rng.uniform(0.3, 1.0)), gap=gap)
+        w = int(rng.uniform(0.02, 1.0) * 2_000_000)
+        lo = int(rng.integers(0, 2_000_000 - w + 1))
+        qs.append(synth.Query(motif=m, t_lo=lo, t_hi=lo + w, enumerate=False, arrival=0.0))
+    qs.append(synth.Query(motif=synth.Motif(list(synth.FOUR_CYCLE), 60_000, anti=[(2, 0, 1, 20_000)]),
+                          t_lo=0, t_hi=2_000_000, enumerate=False, arrival=0.0))
+    for d in (20_000, 40_000):
+        qs.append(synth.Query(motif=synth.Motif([(0, 1), (1, 2), (2, 0)], d), t_lo=500_000, t_hi=560_000,
+                              enumerate=True, arrival=0.0))
+    with pytest.raises(N.NativeError) as ei:
+        api.Server(ctx, dg, stream_slots=1, tier=2, probe_budget=0)
+    assert ei.value.status == N.TM_E_INVALID
+    srv = api.Server(ctx, dg, stream_slots=3, max_batch=8, enum_pool_bytes=256 << 20, tier=2, probe_budget=1)
+    try:
+        got = _serve(srv, qs, None, limit_s=240)
+    finally:
+        srv.stop()
+    assert len(got) == len(qs)
+    probed = 0
+    for i, q in enumerate(qs):
+        r, rows = got[i]
+        say("query", i, q.motif.edges, q.motif.delta, "probed", r["probed"], "tier", r["kernel_tier"])
+        assert r["status"] == N.TM_OK, (i, r)
+        want = oracle.count(og, q.motif, t_lo=q.t_lo, t_hi=q.t_hi, nthreads=8)
+        assert r["count"] == want, (i, q.motif)
+        assert r["t_arrival_ns"] <= r["t_admit_ns"] <= r["t_launch_ns"] <= r["t_done_ns"]
+        if q.enumerate:
+            assert not r["probed"] and r["kernel_tier"] == 1
+            assert np.array_equal(sorted_rows(rows),
+                                  sorted_rows(oracle.enumerate(og, q.motif, t_lo=q.t_lo, t_hi=q.t_hi)))
+        elif q.motif.anti:
+            assert not r["probed"] and r["kernel_tier"] == 0
+        elif r["probed"]:
+            probed += 1
+        else:
+            assert r["kernel_tier"] == 1
+    say("probed", probed, "specialised", sum(1 for r, _ in got.values() if r["probed"] and r["kernel_tier"] == 0))
+    assert probed > 0
+    assert any(r["probed"] and r["kernel_tier"] == 0 for r, _ in got.values())
