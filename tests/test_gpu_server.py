@@ -219,3 +219,17 @@ def test_tier2_specialises_heavy_queries(ctx):
     say("probed", probed, "specialised", sum(1 for r, _ in got.values() if r["probed"] and r["kernel_tier"] == 0))
     assert probed > 0
     assert any(r["probed"] and r["kernel_tier"] == 0 for r, _ in got.values())
+
+
+def test_tier2_stop_drains_waiting_queries(ctx, tiny_g):
+    """Stopping a tier-2 server right after submission returns once every
+    query has run, including those moved over the probe budget that wait for
+    a compile (on the tiny graph, one structure not compiled before)."""
+    srv = api.Server(ctx, tiny_g, stream_slots=2, max_batch=4, enum_pool_bytes=0, tier=2, probe_budget=1)
+    mots = [synth.Motif([(0, 1), (1, 2), (2, 3), (3, 1)], d) for d in (30_000, 50_000, 70_000, 86_400)]
+    mots += [synth.Motif(synth.OUT_STAR3, d) for d in (40_000, 86_400)]
+    t0 = time.time()
+    for i, m in enumerate(mots):
+        srv.submit(m, tag=i)
+    srv.stop()
+    say("stopped after", time.time() - t0, "s")
