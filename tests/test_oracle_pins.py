@@ -316,3 +316,44 @@ def test_stats_counters_are_consistent(tiny_og):
     assert st["roots"] == 20_000
     c1, st1 = oracle.count(tiny_og, Motif(TRI, 10_000), list_rule=1, nthreads=3, with_stats=True)
     assert st1 == st
+
+
+# Four edges, counted by hand: e0 0->1 @1, e1 1->2 @2, e2 1->3 @3, e3 2->0 @4.
+# out(0) = [e0], out(1) = [e1, e2], out(2) = [e3], out(3) = []; in(0) = [e3].
+# A window over a list of L entries costs ceil(log2(L + 1)) probes (1, 2, 2
+# for L = 1, 2, 3; none for an empty list); every candidate read counts as a
+# visit, including the one whose time ends the window.
+HAND = dict(n=4, src=[0, 1, 1, 2], dst=[1, 2, 3, 0], t=[1, 2, 3, 4], w=[1.0, 3.0, 0.5, 2.0])
+HAND_CASES = [
+    # 2-path, delta 10: roots e0 (out(1): L 2, visits e1 e2, both match), e1
+    # (out(2): L 1, visits e3, match), e2 (out(3): empty), e3 (out(0): L 1,
+    # window after t = 4 is empty)
+    (Motif([(0, 1), (1, 2)], 10), dict(roots=4, windows=4, probes=4, visits=3, pred_visits=0, matches=3)),
+    # delta 1: root e0 reads e1 (match) then e2 (t 3 > 2 ends the window);
+    # root e1 reads e3 (t 4 > 3 ends it); the rest as above
+    (Motif([(0, 1), (1, 2)], 1), dict(roots=4, windows=4, probes=4, visits=3, pred_visits=0, matches=1)),
+    # a predicate on edge 1 (w < 2.5): every level-1 visit is a predicate
+    # visit; e1 (w 3.0) fails it, e2 (0.5) and e3 (2.0) pass
+    (Motif([(0, 1), (1, 2)], 10, pred_edge=1, pred_op=synth.PRED_LT, pred_theta=2.5),
+     dict(roots=4, windows=4, probes=4, visits=3, pred_visits=3, matches=2)),
+    # the same predicate on the root edge: one predicate visit per root; e0
+    # (w 1.0), e2 (0.5) and e3 (2.0) pass, e1 (3.0) fails before its window
+    # opens; e2's window over out(3) is empty
+    (Motif([(0, 1), (1, 2)], 10, pred_edge=0, pred_op=synth.PRED_LT, pred_theta=2.5),
+     dict(roots=4, windows=3, probes=3, visits=2, pred_visits=4, matches=2)),
+    # triangle, delta 10, shorter list at the closing level (ties: out-list):
+    # root e0: out(1) L 2 (2 probes), e1 -> closing level over out(2) (L 1,
+    # 1 probe, visits e3, match), e2 -> out(3) empty (outdeg 0 < indeg(0) 1);
+    # root e1: out(2) L 1, e3 binds node 0 -> closing level over out(0) (L 1,
+    # 1 probe, nothing after t = 4); root e2: out(3) empty; root e3: out(0)
+    # L 1, nothing after t = 4
+    (Motif(TRI, 10), dict(roots=4, windows=7, probes=6, visits=4, pred_visits=0, matches=1)),
+]
+
+
+@pytest.mark.parametrize("mot,want", HAND_CASES)
+def test_work_counters_by_hand(mot, want):
+    og = oracle.OracleGraph(HAND["n"], HAND["src"], HAND["dst"], HAND["t"], HAND["w"])
+    c, st = oracle.count(og, mot, list_rule=1, with_stats=True)
+    assert c == want["matches"]
+    assert st == want
