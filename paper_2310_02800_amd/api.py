@@ -411,7 +411,12 @@ class _DeviceRows:
 
 
 class Server:
-    """Continuous-batching query server over one resident graph (tm_server_*)."""
+    """Continuous-batching query server over one resident graph (tm_server_*).
+
+    tier: 0 specialised kernels, 1 table-driven, 2 table-driven batches with
+    the count queries over ``probe_budget`` steps run again on specialised
+    kernels compiled in the background (results then carry ``kernel_tier``
+    and ``probed``)."""
 
     def __init__(self, ctx: Context, g: Graph, stream_slots=2, max_batch=64, enum_pool_bytes=1 << 30,
                  queue_capacity=1 << 16, tier=1, tune_path=None, work_budget=0, probe_budget=0):
