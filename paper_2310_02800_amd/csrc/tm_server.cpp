@@ -208,6 +208,9 @@ void to_heavy(tm_server *s, Pending *p) {
     s->cv_pending.notify_all();
 }
 
+// Tier 2: the compile thread. Builds one structure's specialised counting
+// kernel at a time, oldest request first, and moves the queries waiting for
+// it to the ready list (table-driven there if the compile failed).
 void compile_main(tm_server *s) {
     for (;;) {
         std::pair<std::string, tm_motif> job;
